@@ -1,0 +1,230 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test fixes the oracle to something the paper or mathematics determines:
+hand-derived values (tests/golden), closed forms of special inputs, theorems
+(Parseval, shift, convolution/adjointness), brute force on tiny grids, and
+an independent library FFT (numpy.fft).  A dropped term, a wrong sign, a
+swapped axis or a missing scale in the oracle fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SHAPES = [(1, 1, 1), (2, 3, 4), (5, 6, 4), (7, 3, 5), (4, 4, 4), (3, 8, 12), (9, 10, 6), (8, 16, 11)]
+
+
+def _rand(shape, seed):
+    return synth.complex_normal(shape, seed)
+
+
+def test_golden_hand_derived():
+    with open(os.path.join(HERE, "golden", "dft_small.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        shape = tuple(case["shape"])
+        a = (np.array(case["input_re"]) + 1j * np.array(case["input_im"])).reshape(shape)
+        want = (np.array(case["output_re"]) + 1j * np.array(case["output_im"])).reshape(shape)
+        np.testing.assert_allclose(oracle.fftn(a), want, rtol=0, atol=1e-13, err_msg=case["note"])
+        np.testing.assert_allclose(oracle.brute3d(a), want, rtol=0, atol=1e-13, err_msg=case["note"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 11, 12, 13, 16, 30, 48, 97, 100, 120, 128, 160, 512])
+def test_dft1d_vs_numpy(n):
+    x = _rand((n,), n)
+    got = oracle.dft1d(x)
+    want = np.fft.fft(x)
+    assert oracle.rel_l2(got, want) < 1e-14
+    # sign +1 is the conjugate-exponent sum: n * ifft
+    assert oracle.rel_l2(oracle.dft1d(x, +1), n * np.fft.ifft(x)) < 1e-14
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fftn_vs_brute_force(shape):
+    a = _rand(shape, 11)
+    fast = oracle.fftn(a)
+    slow = oracle.brute3d(a)
+    assert oracle.rel_l2(fast, slow) < 1e-13
+    assert oracle.rel_l2(oracle.bfftn(a), oracle.brute3d(a, +1)) < 1e-13
+
+
+def test_fftn_vs_brute_force_32cubed():
+    """The 32^3 complex128 workload on its seeded input: recursive FFT vs the literal sum."""
+    a = synth.complex_normal(synth.CFG1["shape"], synth.CFG1["seed"])
+    assert oracle.rel_l2(oracle.fftn(a), oracle.brute3d(a)) < 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(32, 24, 20), (17, 19, 23)])
+def test_against_numpy_fft(shape):
+    a = _rand(shape, 3)
+    assert oracle.rel_l2(oracle.fftn(a), np.fft.fftn(a)) < 1e-14
+    assert oracle.rel_l2(oracle.ifftn(a), np.fft.ifftn(a)) < 1e-14
+    r = a.real.copy()
+    assert oracle.rel_l2(oracle.rfftn(r), np.fft.rfftn(r)) < 1e-14
+    h = np.fft.rfftn(r)
+    nx = shape[2]
+    assert oracle.rel_l2(oracle.irfftn(h, nx), np.fft.irfftn(h, s=shape, axes=(0, 1, 2))) < 1e-14
+
+
+def test_irfftn_ignores_imag_of_dc_and_nyquist_like_numpy():
+    """Non-Hermitian half spectra: both drop Im of the kx = 0 and kx = nx/2 bins after z, y."""
+    shape = (6, 5, 8)
+    h = synth.complex_normal((6, 5, 5), 9)
+    want = np.fft.irfftn(h, s=shape, axes=(0, 1, 2))
+    assert oracle.rel_l2(oracle.irfftn(h, 8), want) < 1e-14
+    shape = (4, 3, 7)  # odd nx: only the kx = 0 bin is special
+    h = synth.complex_normal((4, 3, 4), 10)
+    assert oracle.rel_l2(oracle.irfftn(h, 7), np.fft.irfftn(h, s=shape, axes=(0, 1, 2))) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 10), (8, 8, 8)])
+def test_delta_closed_forms(shape):
+    nz, ny, nx = shape
+    a = np.zeros(shape, complex)
+    a[0, 0, 0] = 1
+    np.testing.assert_allclose(oracle.fftn(a), np.ones(shape), atol=1e-15)
+    # impulse at (x0, y0, z0) -> phase ramp exp(-2 pi i (kx x0/nx + ky y0/ny + kz z0/nz))
+    x0, y0, z0 = nx - 1, 1 % ny, nz // 2
+    a = np.zeros(shape, complex)
+    a[z0, y0, x0] = 1
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ramp = np.exp(-2j * np.pi * (kx * x0 / nx + ky * y0 / ny + kz * z0 / nz))
+    np.testing.assert_allclose(oracle.fftn(a), ramp, atol=1e-14)
+    np.testing.assert_allclose(oracle.brute3d(a), ramp, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 7)])
+def test_constant_and_cosine_closed_forms(shape):
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    c = 0.75 - 0.5j
+    want = np.zeros(shape, complex)
+    want[0, 0, 0] = n * c
+    np.testing.assert_allclose(oracle.fftn(np.full(shape, c)), want, atol=1e-12)
+    # cos(2 pi p x / nx) -> n/2 at kx = p and kx = nx - p, zero elsewhere
+    p = 2
+    x = np.arange(nx)
+    a = np.broadcast_to(np.cos(2 * np.pi * p * x / nx), shape).astype(complex)
+    want = np.zeros(shape, complex)
+    want[0, 0, p] = n / 2
+    want[0, 0, nx - p] += n / 2
+    np.testing.assert_allclose(oracle.fftn(a), want, atol=1e-12)
+    # a sine along z -> -i n/2 at kz = 1 and +i n/2 at kz = nz - 1
+    z = np.arange(nz)
+    a = np.broadcast_to(np.sin(2 * np.pi * z / nz)[:, None, None], shape).astype(complex)
+    want = np.zeros(shape, complex)
+    want[1, 0, 0] = -0.5j * n
+    want[nz - 1, 0, 0] = 0.5j * n
+    np.testing.assert_allclose(oracle.fftn(a), want, atol=1e-12)
+
+
+def test_parseval_linearity_roundtrip():
+    shape = (12, 10, 9)
+    a, b = _rand(shape, 1), _rand(shape, 2)
+    n = a.size
+    A, B = oracle.fftn(a), oracle.fftn(b)
+    assert abs(np.vdot(A, A).real - n * np.vdot(a, a).real) < 1e-12 * n * np.vdot(a, a).real
+    alpha, beta = 0.3 - 1.2j, -2.0 + 0.1j
+    assert oracle.rel_l2(oracle.fftn(alpha * a + beta * b), alpha * A + beta * B) < 1e-14
+    assert oracle.rel_l2(oracle.ifftn(A), a) < 1e-14
+    assert oracle.rel_l2(oracle.bfftn(A), n * a) < 1e-14
+    r = a.real.copy()
+    assert oracle.rel_l2(oracle.irfftn(oracle.rfftn(r), 9), r) < 1e-14
+
+
+def test_shift_theorem():
+    shape = (6, 10, 8)
+    nz, ny, nx = shape
+    a = _rand(shape, 4)
+    sz, sy, sx = 2, 3, 5
+    shifted = np.roll(a, (sz, sy, sx), axis=(0, 1, 2))
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ramp = np.exp(-2j * np.pi * (kx * sx / nx + ky * sy / ny + kz * sz / nz))
+    assert oracle.rel_l2(oracle.fftn(shifted), ramp * oracle.fftn(a)) < 1e-14
+
+
+def test_adjoint_and_hermitian_symmetry():
+    shape = (5, 6, 8)
+    a, b = _rand(shape, 5), _rand(shape, 6)
+    # <F a, b> = <a, F^H b> with F^H = bfftn
+    lhs = np.vdot(b, oracle.fftn(a))
+    rhs = np.vdot(oracle.bfftn(b), a)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    r = a.real.copy()
+    X = oracle.fftn(r.astype(complex))
+    flip = np.roll(X[::-1, ::-1, ::-1], 1, axis=(0, 1, 2))  # X[-k]
+    assert oracle.rel_l2(flip, np.conj(X)) < 1e-14
+    assert oracle.rel_l2(oracle.rfftn(r), X[:, :, : shape[2] // 2 + 1]) < 1e-15
+
+
+def test_axis_order_invariance():
+    """Separability (Sec. III-A): 1D DFTs along z, then x, then y give the same 3D result."""
+    shape = (6, 5, 8)
+    a = _rand(shape, 7)
+    b = a.copy()
+    for axis in (0, 2, 1):
+        b = np.apply_along_axis(oracle.dft1d, axis, b)
+    assert oracle.rel_l2(b, oracle.fftn(a)) < 1e-14
+
+
+@pytest.mark.parametrize("real", [False, True])
+def test_dft3d_points_vs_fftn(real):
+    shape = (10, 12, 16)
+    a = _rand(shape, 8)
+    if real:
+        a = a.real.copy()
+    X = oracle.fftn(a.astype(complex))
+    rng = np.random.default_rng(0)
+    pts = np.stack([rng.integers(0, s, 40) for s in shape], axis=1)
+    got = oracle.dft3d_points(a, pts)
+    want = X[pts[:, 0], pts[:, 1], pts[:, 2]]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11)
+
+
+def _wavenumbers(n):
+    k = np.arange(n)
+    return np.where(2 * k <= n, k, k - n)
+
+
+def test_poisson_closed_form():
+    """f = cos(k0 . x) on a 2 pi box solves to phi = -cos(k0 . x)/|k0|^2 exactly."""
+    shape = (16, 12, 10)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(*(2 * np.pi * np.arange(n) / n for n in shape), indexing="ij")
+    for k0 in [(1, 2, 3), (0, 0, 1), (8, 6, 5), (3, 0, 5)]:  # (kz, ky, kx); includes Nyquist modes
+        kz, ky, kx = k0
+        f = np.cos(kx * x + ky * y + kz * z)
+        phi = oracle.poisson(f)
+        np.testing.assert_allclose(phi, -f / (kx * kx + ky * ky + kz * kz), atol=1e-13)
+    # a constant has no zero-mean part: the k = 0 mode is dropped
+    np.testing.assert_allclose(oracle.poisson(np.full(shape, 3.0)), 0, atol=1e-14)
+
+
+def test_poisson_laplacian_and_mean():
+    """The spectral Laplacian of phi gives back f minus its mean."""
+    shape = (8, 10, 12)
+    f = synth.real_normal(shape, 3)
+    phi = oracle.poisson(f)
+    assert abs(phi.mean()) < 1e-14
+    # spectral Laplacian with numpy (independent library FFT)
+    kz, ky, kx = np.meshgrid(*(_wavenumbers(n) for n in shape), indexing="ij")
+    lap = np.fft.ifftn(-(kx ** 2 + ky ** 2 + kz ** 2) * np.fft.fftn(phi)).real
+    np.testing.assert_allclose(lap, f - f.mean(), atol=1e-12)
+
+
+def test_poisson_self_adjoint_and_gradient():
+    """<P f, w> = <f, P w>, and L(f) = sum(P(f) w) has gradient P(w) (checked by differences)."""
+    shape = (8, 6, 10)
+    f, w, d = (synth.real_normal(shape, s) for s in (1, 2, 3))
+    lhs = np.sum(oracle.poisson(f) * w)
+    rhs = np.sum(f * oracle.poisson(w))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    g = oracle.poisson_grad(w)
+    eps = 1e-3
+    fd = (np.sum(oracle.poisson(f + eps * d) * w) - np.sum(oracle.poisson(f - eps * d) * w)) / (2 * eps)
+    assert abs(fd - np.sum(g * d)) < 1e-10 * abs(fd)
