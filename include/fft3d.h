@@ -1,0 +1,183 @@
+/*
+ * fft3d -- pencil-decomposed 3D FFT for one AMD Instinct MI355X (gfx950).
+ *
+ * The transform is the 3D DFT of the paper's Sec. III-A,
+ *   X[kx,ky,kz] = sum_{x,y,z} A[x,y,z] exp(-2 pi i (kx x/Nx + ky y/Ny + kz z/Nz)),
+ * evaluated as three stages of batched 1D FFTs (x, then y, then z; the inverse
+ * mirrors the order, Sec. IV-A), each stage cut into P1 x P2 pencil tiles that
+ * are issued as tasks on HIP streams with per-tile dependencies (Alg. 1 and
+ * the data-dependency scheduler of Sec. IV-D; placement as in Alg. 3).
+ *
+ * Layout of every array: element (x, y, z) at index x + Nx*(y + Ny*z), x
+ * fastest (a C array of shape [Nz][Ny][Nx]).  Complex values are interleaved
+ * (re, im) pairs of float (FFT3D_C64) or double (FFT3D_C128).  A real-to-
+ * complex plan maps a real Nx x Ny x Nz array to the half spectrum of
+ * (Nx/2 + 1) x Ny x Nz complex values (x halved, Sec. V-B's Hermitian
+ * symmetry), and back.
+ *
+ * Pointers named in/out/f/phi are DEVICE pointers owned by the caller.  The
+ * `stream` argument is a hipStream_t (NULL: the default stream); all work is
+ * enqueued after the work already on that stream and completes before work
+ * enqueued on it later.  No call blocks the host on the GPU except
+ * fft3d_plan and fft3d_destroy.  A plan may be used from one host thread at a
+ * time and by one stream at a time (its workspace and events are shared).
+ *
+ * Errors: every call returns an fft3d_status.  Argument errors are detected
+ * before any work is enqueued.  An asynchronous GPU fault surfaces as
+ * FFT3D_ERR_HIP from a later call.  fft3d_last_error() gives a text detail for
+ * the calling thread's most recent failure.
+ */
+#ifndef FFT3D_H
+#define FFT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft3d_plan_s* fft3d_plan_t;
+
+typedef enum {
+    FFT3D_C64 = 0,  /* complex64 (real side: float32) */
+    FFT3D_C128 = 1  /* complex128 (real side: float64) */
+} fft3d_dtype;
+
+typedef enum {
+    FFT3D_OK = 0,
+    FFT3D_ERR_INVALID_ARG = -1,      /* null pointer, bad dtype, grid, stream count */
+    FFT3D_ERR_UNSUPPORTED_SIZE = -2, /* a length without a compiled kernel */
+    FFT3D_ERR_ALLOC = -3,            /* device allocation failed */
+    FFT3D_ERR_HIP = -4,              /* HIP runtime error (incl. asynchronous faults) */
+    FFT3D_ERR_ALIAS = -5,            /* in and out overlap in a way the operation forbids */
+    FFT3D_ERR_WORKSPACE = -6,        /* caller workspace too small */
+    FFT3D_ERR_WRONG_PLAN = -7        /* operation needs the other plan kind (C2C vs R2C) */
+} fft3d_status;
+
+/*
+ * Create a plan for an Nx x Ny x Nz transform.
+ *   dtype  FFT3D_C64 or FFT3D_C128.
+ *   p1,p2  pencil grid: x-pencils are split P1 ways along y and P2 ways along
+ *          z, y-pencils P1 along x and P2 along z, z-pencils P1 along x and P2
+ *          along y (balanced blocks).  1 <= p1 <= min(Ny, Nxc), 1 <= p2 <=
+ *          min(Nz, Ny), Nxc = Nx (C2C) or Nx/2+1 (R2C).
+ *   r2c    0: complex-to-complex plan; 1: real-to-complex plan (Nx even).
+ * Each of Nx, Ny, Nz must be a supported length (fft3d_length_supported).
+ * Allocates the plan's twiddle tables, its streams and events, and for R2C
+ * plans a half-spectrum workspace (replaceable by fft3d_set_workspace).
+ */
+fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                        int p1, int p2, int r2c);
+
+/* Release everything the plan allocated (not caller buffers).  Synchronises
+ * the plan's streams first.  NULL is accepted. */
+fft3d_status fft3d_destroy(fft3d_plan_t plan);
+
+/*
+ * Forward transform (Sec. III-A definition: exponent sign -1, unscaled).
+ * C2C plan: in, out = Nx*Ny*Nz complex; in == out (in place) is allowed,
+ *           partial overlap is FFT3D_ERR_ALIAS.
+ * R2C plan: in = Nx*Ny*Nz reals, out = (Nx/2+1)*Ny*Nz complex; no overlap.
+ * `in` is never written (except in place).
+ */
+fft3d_status fft3d_forward(fft3d_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * Inverse transform: exponent sign +1, scaled by 1/(Nx*Ny*Nz), stages z, y, x
+ * (Sec. IV-A).  C2C: same buffer rules as forward.  R2C plan: in = half
+ * spectrum (left intact; the imaginary parts of its kx = 0 and kx = Nx/2 bins
+ * are ignored), out = real array, no overlap; uses the plan workspace.
+ */
+fft3d_status fft3d_inverse(fft3d_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * Adjoint of fft3d_forward (the vector-Jacobian product of the forward map).
+ * C2C: the unscaled sign +1 transform F^H.  R2C: the adjoint of the real-to-
+ * complex map, i.e. the unscaled complex-to-real transform of the half
+ * spectrum with its interior bins (0 < kx < Nx/2) halved.  Buffer rules as
+ * fft3d_inverse.
+ */
+fft3d_status fft3d_backward(fft3d_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * Spectral Poisson solve on a periodic box of side 2 pi (R2C plans only):
+ *   phi = irfftn( M .* rfftn(f) ),  M(k) = -1/|k|^2,  M(0) = 0,
+ * with integer wavenumbers k_j = j for j <= n/2 and j - n otherwise.  The
+ * z stage runs forward FFT, multiplier and inverse FFT in one kernel.  f and
+ * phi are real Nx*Ny*Nz arrays; f == phi is allowed, partial overlap is not.
+ * Uses the plan workspace.
+ */
+fft3d_status fft3d_poisson(fft3d_plan_t plan, const void* f, void* phi, void* stream);
+
+/*
+ * Adjoint of fft3d_poisson (gradient of sum(phi * g) with respect to f, given
+ * g = gphi): the adjoint of every stage of the solve, applied in reverse
+ * order.  Same buffer rules as fft3d_poisson.
+ */
+fft3d_status fft3d_poisson_adjoint(fft3d_plan_t plan, const void* gphi, void* gf, void* stream);
+
+/* Bytes of the plan's workspace (0 for C2C plans). */
+size_t fft3d_workspace_bytes(fft3d_plan_t plan);
+
+/*
+ * Replace the plan-owned workspace by a caller buffer of at least
+ * fft3d_workspace_bytes(plan) bytes (device memory, 256-byte aligned), which
+ * the caller keeps alive while the plan uses it.  NULL restores a plan-owned
+ * workspace.  Too small -> FFT3D_ERR_WORKSPACE.
+ */
+fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
+
+/*
+ * Number of internal HIP streams the tiles are placed on (1..16; default 4).
+ * With 1, every tile is enqueued directly on the caller's stream.
+ */
+fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
+
+/*
+ * Override the lines-per-workgroup choice for one stage kernel of this plan
+ * (axis 0..2; lw a power of two, 0 restores the default).  Used by the
+ * autotuner; results do not depend on it.
+ */
+fft3d_status fft3d_set_lines_per_block(fft3d_plan_t plan, int axis, int lw);
+
+/* Text for a status code; and the calling thread's last failure detail. */
+const char* fft3d_status_string(int status);
+const char* fft3d_last_error(void);
+
+/* ----------------------------------------------------- host-side queries
+ * These run on the host only and need no GPU; tests use them to check the
+ * planner. */
+
+/* 1 if n has a compiled kernel, else 0. */
+int fft3d_length_supported(int64_t n);
+
+/* Radix plan of length n: out[0] = number of passes np, out[1..np] the
+ * radices, out[np+1] threads per line.  Returns the count written, or -1 for
+ * an unsupported length or cap too small. */
+int fft3d_query_radix_plan(int64_t n, int* out, int cap);
+
+/* Forward twiddle table W_n^m = exp(-2 pi i m/n), m < n, interleaved (re, im)
+ * in the plan precision (float for FFT3D_C64, double for FFT3D_C128).
+ * out holds 2n values of that type. */
+fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out);
+
+/*
+ * Task graph of an operation (0 forward, 1 inverse, 2 backward, 3 Poisson,
+ * 4 Poisson adjoint) for the given plan parameters and stream count, written
+ * as int64 records:
+ *   header: [ntasks, nstages]
+ *   per stage: [kind, axis, n, conj, weight, src, dst]
+ *   per task:  [stage, x0, x1, y0, y1, z0, z1, stream, ndeps, deps..., nwaits, waits...]
+ * Boxes are half-open ranges over the complex array.  Returns the number of
+ * int64 values needed; writes them only if cap is large enough.  Negative on
+ * invalid arguments.
+ */
+int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int op,
+                             int nstreams, int64_t* out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT3D_H */

@@ -1,0 +1,267 @@
+// Device-side building blocks: complex arithmetic, radix-2/3/4/5/8/16
+// butterflies and the Stockham pass driver used by every stage kernel.
+//
+// A length-N line is transformed by the passes of radix_plan(N).  Pass p
+// (radix R, sub-transform length Ns before it) treats butterfly j < N/R:
+//   inputs   a[r] = data[j + r*N/R],               r < R
+//   twiddle  a[r] *= W_N^(r * (j mod Ns) * N/(Ns*R))
+//   DFT_R    on a
+//   outputs  data'[(j / Ns)*Ns*R + (j mod Ns) + r*Ns] = a[r]
+// (the self-sorting Stockham formulation: natural order in and out, no bit
+// reversal).  Pass 0 reads through a caller-supplied loader (global memory),
+// the last pass writes through a caller-supplied storer, and the passes in
+// between exchange through LDS.  The butterflies are written for the forward
+// sign (exponent -1); the conjugate-sign transform is taken as conj(F(conj x)),
+// which the kernels apply at load and store time.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "fft_lengths.hpp"
+
+#define FD __device__ __forceinline__
+
+namespace fft3d {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T> FD cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> FD cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> FD cpx<T> operator*(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T> FD cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> FD cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+template <typename T> FD cpx<T> mul_i(cpx<T> a) { return {-a.im, a.re}; }     // i * a
+template <typename T> FD cpx<T> mul_negi(cpx<T> a) { return {a.im, -a.re}; }  // -i * a
+
+// cos/sin constants of the small DFTs, in long double so each precision gets
+// its correctly rounded value.
+#define K_SQRT1_2 0.707106781186547524400844362104849039L
+#define K_SIN_PI_3 0.866025403784438646763723170752936183L
+#define K_COS_2PI_5 0.309016994374947424102293417182819059L
+#define K_COS_4PI_5 (-0.809016994374947424102293417182819059L)
+#define K_SIN_2PI_5 0.951056516295153572116439333379382143L
+#define K_SIN_4PI_5 0.587785252292473129168705954639072769L
+#define K_COS_PI_8 0.923879532511286756128183189396788933L
+#define K_SIN_PI_8 0.382683432365089771728459984030398866L
+
+// ---------------------------------------------------------------- DFT_R
+// Forward sign: X[k] = sum_j x[j] exp(-2 pi i j k / R), in place, natural order.
+
+template <typename T> FD void dft2(cpx<T>* v)
+{
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <typename T> FD void dft3(cpx<T>* v)
+{
+    const T h = (T)K_SIN_PI_3;
+    cpx<T> s = v[1] + v[2];
+    cpx<T> m = v[0] - s * (T)0.5;
+    cpx<T> d = (v[1] - v[2]) * h;
+    v[0] = v[0] + s;
+    v[1] = m + mul_negi(d);
+    v[2] = m + mul_i(d);
+}
+
+template <typename T> FD void dft4v(cpx<T>& x0, cpx<T>& x1, cpx<T>& x2, cpx<T>& x3)
+{
+    cpx<T> s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
+    x0 = s02 + s13;
+    x2 = s02 - s13;
+    x1 = d02 + mul_negi(d13);
+    x3 = d02 + mul_i(d13);
+}
+
+template <typename T> FD void dft4(cpx<T>* v) { dft4v(v[0], v[1], v[2], v[3]); }
+
+template <typename T> FD void dft5(cpx<T>* v)
+{
+    const T c1 = (T)K_COS_2PI_5, c2 = (T)K_COS_4PI_5, s1 = (T)K_SIN_2PI_5, s2 = (T)K_SIN_4PI_5;
+    cpx<T> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+    cpx<T> x0 = v[0];
+    cpx<T> a1 = x0 + t1 * c1 + t2 * c2;
+    cpx<T> a2 = x0 + t1 * c2 + t2 * c1;
+    cpx<T> b1 = t3 * s1 + t4 * s2;
+    cpx<T> b2 = t3 * s2 - t4 * s1;
+    v[0] = x0 + t1 + t2;
+    v[1] = a1 + mul_negi(b1);
+    v[4] = a1 + mul_i(b1);
+    v[2] = a2 + mul_negi(b2);
+    v[3] = a2 + mul_i(b2);
+}
+
+// radix 8 as 2 x 4: u_j = x_j + x_{j+4}, v_j = (x_j - x_{j+4}) W8^j, then DFT4
+// of u gives the even outputs and DFT4 of v the odd ones.
+template <typename T> FD void dft8(cpx<T>* x)
+{
+    const T r = (T)K_SQRT1_2;
+    cpx<T> u0 = x[0] + x[4], u1 = x[1] + x[5], u2 = x[2] + x[6], u3 = x[3] + x[7];
+    cpx<T> v0 = x[0] - x[4], v1 = x[1] - x[5], v2 = x[2] - x[6], v3 = x[3] - x[7];
+    v1 = cpx<T>{(v1.re + v1.im) * r, (v1.im - v1.re) * r};   // * (1 - i)/sqrt2
+    v2 = mul_negi(v2);                                        // * -i
+    v3 = cpx<T>{(v3.im - v3.re) * r, -(v3.re + v3.im) * r};  // * (-1 - i)/sqrt2
+    dft4v(u0, u1, u2, u3);
+    dft4v(v0, v1, v2, v3);
+    x[0] = u0; x[2] = u1; x[4] = u2; x[6] = u3;
+    x[1] = v0; x[3] = v1; x[5] = v2; x[7] = v3;
+}
+
+// radix 16 as 4 x 4: DFT4 over m of x_{j+4m}, twiddle W16^(j q), DFT4 over j.
+template <typename T> FD void dft16(cpx<T>* x)
+{
+    const T c = (T)K_COS_PI_8, s = (T)K_SIN_PI_8, r = (T)K_SQRT1_2;
+    cpx<T> y[16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cpx<T> a = x[j], b = x[j + 4], cc = x[j + 8], d = x[j + 12];
+        dft4v(a, b, cc, d);
+        y[4 * j + 0] = a; y[4 * j + 1] = b; y[4 * j + 2] = cc; y[4 * j + 3] = d;
+    }
+    // twiddles W16^(j q) for j, q in 1..3 (exponents 1, 2, 3, 2, 4, 6, 3, 6, 9)
+    y[5] = cmul(y[5], cpx<T>{c, -s});    // e = 1
+    y[6] = cpx<T>{(y[6].re + y[6].im) * r, (y[6].im - y[6].re) * r};  // e = 2
+    y[7] = cmul(y[7], cpx<T>{s, -c});    // e = 3
+    y[9] = cpx<T>{(y[9].re + y[9].im) * r, (y[9].im - y[9].re) * r};  // e = 2
+    y[10] = mul_negi(y[10]);             // e = 4
+    y[11] = cpx<T>{(y[11].im - y[11].re) * r, -(y[11].re + y[11].im) * r};  // e = 6
+    y[13] = cmul(y[13], cpx<T>{s, -c});  // e = 3
+    y[14] = cpx<T>{(y[14].im - y[14].re) * r, -(y[14].re + y[14].im) * r};  // e = 6
+    y[15] = cmul(y[15], cpx<T>{-c, s});  // e = 9
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cpx<T> a = y[q], b = y[4 + q], cc = y[8 + q], d = y[12 + q];
+        dft4v(a, b, cc, d);
+        x[q] = a; x[q + 4] = b; x[q + 8] = cc; x[q + 12] = d;
+    }
+}
+
+template <int R, typename T> FD void dft_radix(cpx<T>* v)
+{
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 3) dft3(v);
+    else if constexpr (R == 4) dft4(v);
+    else if constexpr (R == 5) dft5(v);
+    else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 16) dft16(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ------------------------------------------------------------ pass driver
+
+template <int N, int P>
+struct PassInfo {
+    static constexpr RadixPlan PL = radix_plan(N);
+    static constexpr int R = PL.r[P];
+    static constexpr int BF = N / R;          // butterflies in this pass
+    static constexpr int NS = radix_ns(PL, P);  // sub-transform length before it
+    static constexpr int TPL = PL.tpl;
+    static constexpr int NB = (BF + TPL - 1) / TPL;  // butterflies per thread
+    static constexpr bool FULL = (BF % TPL) == 0;
+    static constexpr int TWSTEP = N / (NS * R);
+    static constexpr bool LAST = (P + 1 == PL.np);
+};
+
+// LDS view of the lines of a workgroup: element e of this thread's line sits
+// at base + e * es.
+template <typename T>
+struct LdsLine {
+    cpx<T>* base;
+    int es;
+    FD cpx<T>& operator[](int e) const { return base[e * es]; }
+};
+
+// One Stockham pass.  `Load(e)` supplies pass-0 inputs, `Store(e, v)` takes
+// final outputs; other passes use the LDS line.  tw is the forward root table
+// W_N^m = exp(-2 pi i m / N) read at index m * TWM.
+// SRC_LDS: the loader reads this workgroup's LDS, so pass 0 must not write
+// LDS before every thread has loaded.  DST_LDS: the storer writes LDS, so the
+// last pass must not store before every thread has read its inputs.
+template <typename T, int N, int P, int TWM, bool SRC_LDS, bool DST_LDS, class Load, class Store>
+FD void stockham_pass(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw,
+                      Load& load, Store& store)
+{
+    using PI = PassInfo<N, P>;
+    constexpr int R = PI::R, BF = PI::BF, NS = PI::NS, TPL = PI::TPL, NB = PI::NB;
+    cpx<T> v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = tj + i * TPL;
+        if (PI::FULL || j < BF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (P == 0) v[i][r] = load(j + r * BF);
+                else v[i][r] = L[j + r * BF];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int j = tj + i * TPL;
+        if (PI::FULL || j < BF) {
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(r * k * PI::TWSTEP) * TWM]);
+            }
+            dft_radix<R>(v[i]);
+        }
+    }
+    if constexpr (PI::LAST) {
+        if constexpr (DST_LDS && (P > 0 || SRC_LDS)) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = tj + i * TPL;  // last pass: j < NS, output j + r*NS
+            if (PI::FULL || j < BF) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) store(j + r * NS, v[i][r]);
+            }
+        }
+    } else {
+        if constexpr (P > 0 || SRC_LDS) __syncthreads();  // every read of this pass is done
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = tj + i * TPL;
+            if (PI::FULL || j < BF) {
+                const int k = j % NS;
+                const int o = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) L[o + r * NS] = v[i][r];
+            }
+        }
+        __syncthreads();  // the next pass reads what this one wrote
+    }
+}
+
+template <typename T, int N, int P, int TWM, bool SRC_LDS, bool DST_LDS, class Load, class Store>
+FD void stockham_from(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw, Load& load,
+                      Store& store)
+{
+    stockham_pass<T, N, P, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
+    if constexpr (P + 1 < radix_plan(N).np)
+        stockham_from<T, N, P + 1, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
+}
+
+// Full length-N forward FFT of one line.  For N == 1 it is a copy.  When the
+// kernel loops over several line batches it must __syncthreads() between
+// batches (pass 0 writes LDS without a leading barrier).
+template <typename T, int N, int TWM = 1, bool SRC_LDS = false, bool DST_LDS = false, class Load,
+          class Store>
+FD void fft_line(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw, Load& load, Store& store)
+{
+    if constexpr (N == 1) {
+        if (tj == 0) store(0, load(0));  // one slot per line, touched by one thread
+    } else {
+        stockham_from<T, N, 0, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
+    }
+}
+
+}  // namespace fft3d

@@ -1,0 +1,107 @@
+// Supported 1D lengths and their compile-time radix plans.
+//
+// Every axis of a 3D transform is a batch of 1D DFTs (paper Sec. III-A: the 3D
+// FFT is the tensor product of 1D FFTs along x, y and z).  The GPU kernels are
+// specialised per length: the radix sequence of the Stockham passes, the
+// number of threads that cooperate on one line and the per-thread register
+// footprint are constants, so every butterfly is fully unrolled.
+//
+// This header is plain C++ (no HIP) so the host-side plan can use it too.
+#pragma once
+
+// Lengths with a compiled kernel: products 2^a 3^b 5^c up to 4096 that cover
+// every workload shape plus a spread of common sizes.
+#define FFT3D_FOR_EACH_LENGTH(X)                                                      \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(25)      \
+    X(30) X(32) X(40) X(48) X(50) X(60) X(64) X(75) X(80) X(96) X(100) X(120)         \
+    X(125) X(128) X(150) X(160) X(192) X(200) X(240) X(250) X(256) X(300) X(320)      \
+    X(384) X(400) X(480) X(500) X(512) X(600) X(640) X(750) X(768) X(800) X(960)      \
+    X(1000) X(1024) X(2048) X(4096)
+
+namespace fft3d {
+
+// Radix sequence of a length-n Stockham FFT.  np passes with radices r[0..np);
+// tpl threads cooperate on one line; pass p has n / r[p] butterflies, split
+// round-robin over the tpl threads (a thread may have one masked butterfly).
+struct RadixPlan {
+    int n;
+    int np;
+    int r[12];
+    int tpl;
+};
+
+constexpr RadixPlan radix_plan(int n)
+{
+    RadixPlan p{n, 0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, 1};
+    if (n < 1) {
+        p.np = -1;
+        return p;
+    }
+    int m = n, a = 0, b = 0, c = 0;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    while (m % 5 == 0) { m /= 5; ++c; }
+    if (m != 1) {
+        p.np = -1;
+        return p;
+    }
+    // power-of-two part: as few passes as possible, radices no larger than 16,
+    // the larger radices first
+    while (a > 12) { p.r[p.np++] = 16; a -= 4; }
+    switch (a) {
+    case 1: p.r[p.np++] = 2; break;
+    case 2: p.r[p.np++] = 4; break;
+    case 3: p.r[p.np++] = 8; break;
+    case 4: p.r[p.np++] = 16; break;
+    case 5: p.r[p.np++] = 8; p.r[p.np++] = 4; break;
+    case 6: p.r[p.np++] = 8; p.r[p.np++] = 8; break;
+    case 7: p.r[p.np++] = 16; p.r[p.np++] = 8; break;
+    case 8: p.r[p.np++] = 16; p.r[p.np++] = 16; break;
+    case 9: p.r[p.np++] = 8; p.r[p.np++] = 8; p.r[p.np++] = 8; break;
+    case 10: p.r[p.np++] = 16; p.r[p.np++] = 8; p.r[p.np++] = 8; break;
+    case 11: p.r[p.np++] = 16; p.r[p.np++] = 16; p.r[p.np++] = 8; break;
+    case 12: p.r[p.np++] = 16; p.r[p.np++] = 16; p.r[p.np++] = 16; break;
+    default: break;
+    }
+    for (int i = 0; i < b; ++i) p.r[p.np++] = 3;
+    for (int i = 0; i < c; ++i) p.r[p.np++] = 5;
+    int rmax = 1;
+    for (int i = 0; i < p.np; ++i) rmax = p.r[i] > rmax ? p.r[i] : rmax;
+    p.tpl = n / rmax;
+    return p;
+}
+
+// Product of the radices of passes [0, pass): the sub-transform length that
+// pass `pass` starts from.
+constexpr int radix_ns(const RadixPlan& p, int pass)
+{
+    int ns = 1;
+    for (int i = 0; i < pass; ++i) ns *= p.r[i];
+    return ns;
+}
+
+// Complex values one thread holds during its widest pass.
+constexpr int radix_ept(const RadixPlan& p)
+{
+    int e = 1;
+    for (int i = 0; i < p.np; ++i) {
+        int bf = p.n / p.r[i];
+        int nb = (bf + p.tpl - 1) / p.tpl;
+        e = nb * p.r[i] > e ? nb * p.r[i] : e;
+    }
+    return e;
+}
+
+inline bool length_supported(long long n)
+{
+#define FFT3D_LEN_CASE(L) case L:
+    switch (n) {
+        FFT3D_FOR_EACH_LENGTH(FFT3D_LEN_CASE)
+        return true;
+    default:
+        return false;
+    }
+#undef FFT3D_LEN_CASE
+}
+
+}  // namespace fft3d

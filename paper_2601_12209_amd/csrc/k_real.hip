@@ -1,0 +1,150 @@
+// Real-to-complex and complex-to-real x-stage kernels.
+//
+// R2C exploits Hermitian symmetry (paper Sec. V-B): a real line x of even
+// length n is read as the complex line z[m] = x[2m] + i x[2m+1] of length
+// h = n/2, transformed with the length-h kernel, and split in LDS:
+//   E[k] = (Z[k] + conj Z[h-k]) / 2        (DFT of the even samples)
+//   O[k] = (Z[k] - conj Z[h-k]) / (2i)     (DFT of the odd samples)
+//   X[k] = E[k] + W_n^k O[k],  k = 0..h    (indices of Z taken mod h)
+// C2R runs the same algebra backwards: from the half spectrum X[0..h],
+//   Z'[k] = (X[k] + conj X[h-k]) + i W_n^-k (X[k] - conj X[h-k]),  k < h,
+// whose length-h conjugate-sign DFT is the unscaled real line, interleaved
+// (even samples in the real parts, odd in the imaginary parts).  The
+// imaginary parts of X[0] and X[h] are dropped first, which is what a real
+// result requires of a consistent half spectrum.
+#include "device_fft.hpp"
+#include "kernels.hpp"
+#include "stage_args.hpp"
+
+namespace fft3d {
+
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
+{
+    constexpr int H = N / 2;
+    constexpr int TPL = radix_plan(H).tpl;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int t = threadIdx.x;
+    const int tj = t % TPL, lw = t / TPL;
+    const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
+    const bool ok = l < a.A * a.B;
+    const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
+    const cpx<T>* __restrict__ in =
+        reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table
+    LdsLine<T> L{lds + lw * H, 1};
+    auto load = [&](int e) -> cpx<T> { return ok ? in[e] : cpx<T>{(T)0, (T)0}; };
+    auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
+    // W_H^m = W_N^(2m): the half-length passes read the length-N table at stride 2
+    fft_line<T, H, 2, false, true>(L, tj, tw, load, store_lds);
+    __syncthreads();
+    const T half = (T)0.5;
+    const T wgt = a.weight ? (T)2 : (T)1;
+    const T scale = (T)a.scale;
+    for (int k = tj; k <= H; k += TPL) {
+        const cpx<T> zk = L[k == H ? 0 : k];
+        const cpx<T> zr = conj(L[k == 0 ? 0 : H - k]);
+        const cpx<T> e = (zk + zr) * half;
+        const cpx<T> o = mul_negi(zk - zr) * half;
+        cpx<T> x = e + cmul(tw[k], o);
+        if (k > 0 && k < H) x = x * wgt;
+        if (ok) out[k] = x * scale;
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
+{
+    constexpr int H = N / 2;
+    constexpr int TPL = radix_plan(H).tpl;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int t = threadIdx.x;
+    const int tj = t % TPL, lw = t / TPL;
+    const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
+    const bool ok = l < a.A * a.B;
+    const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
+    const cpx<T>* __restrict__ in =
+        reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table
+    LdsLine<T> L{lds + lw * (H + 1), 1};
+    const T wgt = a.weight ? (T)0.5 : (T)1;
+    for (int k = tj; k <= H; k += TPL) {
+        cpx<T> v = ok ? in[k] : cpx<T>{(T)0, (T)0};
+        if (k == 0 || k == H) v.im = (T)0;
+        else v = v * wgt;
+        L[k] = v;
+    }
+    __syncthreads();
+    // conjugate-sign DFT as conj(F(conj Z'))
+    auto load = [&](int e) -> cpx<T> {
+        const cpx<T> xe = L[e], xr = conj(L[H - e]);
+        const cpx<T> s = xe + xr, d = xe - xr;
+        const cpx<T> z = s + mul_i(cmul(conj(tw[e]), d));
+        return conj(z);
+    };
+    const T scale = (T)a.scale;
+    auto store = [&](int e, cpx<T> v) {
+        if (ok) out[e] = conj(v) * scale;
+    };
+    fft_line<T, H, 2, true, false>(L, tj, tw, load, store);
+}
+
+template <typename T, int N>
+static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
+{
+    if constexpr (N % 2 != 0) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int H = N / 2;
+        constexpr int TPL = radix_plan(H).tpl;
+        const int threads = a.lw * TPL;
+        const size_t lds = (size_t)a.lw * (H + 1) * sizeof(cpx<T>);
+        const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
+        if (grid.x == 0) return hipSuccess;
+        if (r2c) {
+            static const hipError_t attr = hipFuncSetAttribute(
+                reinterpret_cast<const void*>(&k_r2c_x<T, N>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+            (void)attr;
+            hipLaunchKernelGGL((k_r2c_x<T, N>), grid, dim3(threads), lds, s, a);
+        } else {
+            static const hipError_t attr = hipFuncSetAttribute(
+                reinterpret_cast<const void*>(&k_c2r_x<T, N>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+            (void)attr;
+            hipLaunchKernelGGL((k_c2r_x<T, N>), grid, dim3(threads), lds, s, a);
+        }
+        return hipGetLastError();
+    }
+}
+
+static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    // the half length must have a kernel of its own
+#define FFT3D_REAL_CASE(L)                                                                \
+    case 2 * L:                                                                           \
+        return dtype == DT_F64 ? launch_real_n<double, 2 * L>(r2c, a, s)                  \
+                               : launch_real_n<float, 2 * L>(r2c, a, s);
+    switch (n) {
+        FFT3D_FOR_EACH_LENGTH(FFT3D_REAL_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef FFT3D_REAL_CASE
+}
+
+hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    return launch_real(true, n, dtype, a, s);
+}
+
+hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    return launch_real(false, n, dtype, a, s);
+}
+
+}  // namespace fft3d

@@ -1,0 +1,22 @@
+// Stage-kernel launchers (one per kernel kind).  Each dispatches on the line
+// length to the kernel specialised for it and returns hipErrorInvalidValue for
+// a length without a kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+
+#include "stage_args.hpp"
+
+namespace fft3d {
+
+// LDS one workgroup may allocate on gfx950 (160 KiB per compute unit).
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s);
+// n is the real line length (even); the complex kernel runs at n/2.
+hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s);
+hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s);
+hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s);
+
+}  // namespace fft3d

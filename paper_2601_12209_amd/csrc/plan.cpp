@@ -1,0 +1,218 @@
+// Host-side planning (no HIP): pencil tiles, tile DAG, stream placement,
+// twiddle tables.
+#include "plan.hpp"
+
+#include <math.h>
+
+#include <algorithm>
+
+#include "stage_args.hpp"
+
+namespace fft3d {
+
+bool boxes_overlap(const Box& a, const Box& b)
+{
+    for (int d = 0; d < 3; ++d)
+        if (a.hi[d] <= b.lo[d] || b.hi[d] <= a.lo[d]) return false;
+    return true;
+}
+
+void split_range(int64_t n, int p, int i, int64_t* lo, int64_t* hi)
+{
+    const int64_t q = n / p, r = n % p;
+    *lo = i * q + std::min<int64_t>(i, r);
+    *hi = *lo + q + (i < r ? 1 : 0);
+}
+
+std::vector<Box> stage_boxes(const PlanDesc& d, int axis)
+{
+    const int64_t ext[3] = {d.nxc(), d.ny, d.nz};
+    // the two axes a pencil of this orientation is split along, over p1 x p2
+    int s1, s2;
+    if (axis == 0) { s1 = 1; s2 = 2; }
+    else if (axis == 1) { s1 = 0; s2 = 2; }
+    else { s1 = 0; s2 = 1; }
+    std::vector<Box> out;
+    for (int j2 = 0; j2 < d.p2; ++j2) {
+        for (int j1 = 0; j1 < d.p1; ++j1) {
+            Box b;
+            b.lo[axis] = 0;
+            b.hi[axis] = ext[axis];
+            split_range(ext[s1], d.p1, j1, &b.lo[s1], &b.hi[s1]);
+            split_range(ext[s2], d.p2, j2, &b.lo[s2], &b.hi[s2]);
+            out.push_back(b);
+        }
+    }
+    return out;
+}
+
+static Stage mk(int kind, int axis, int n, int conj, int weight, double scale, int src, int dst)
+{
+    Stage s;
+    s.kind = kind; s.axis = axis; s.n = n; s.conj = conj; s.weight = weight;
+    s.scale = scale; s.src = src; s.dst = dst;
+    return s;
+}
+
+std::vector<Stage> op_stages(const PlanDesc& d, int op)
+{
+    const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
+    const double inv_n = 1.0 / ((double)d.nx * (double)d.ny * (double)d.nz);
+    std::vector<Stage> s;
+    if (!d.r2c) {
+        switch (op) {
+        case OP_FORWARD:  // x, y, z (Alg. 1)
+            s.push_back(mk(K_C2C, 0, nx, 0, 0, 1.0, BUF_IN, BUF_OUT));
+            s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+            s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+            break;
+        case OP_INVERSE:   // mirrored: z, y, x
+        case OP_BACKWARD:
+            s.push_back(mk(K_C2C, 2, nz, 1, 0, 1.0, BUF_IN, BUF_OUT));
+            s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_OUT, BUF_OUT));
+            s.push_back(mk(K_C2C, 0, nx, 1, 0, op == OP_INVERSE ? inv_n : 1.0, BUF_OUT, BUF_OUT));
+            break;
+        default:
+            break;
+        }
+        return s;
+    }
+    switch (op) {
+    case OP_FORWARD:
+        s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_OUT));
+        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+        s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+        break;
+    case OP_INVERSE:
+    case OP_BACKWARD:
+        // the input half spectrum is left intact: z reads it into the workspace
+        s.push_back(mk(K_C2C, 2, nz, 1, 0, 1.0, BUF_IN, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+        if (op == OP_INVERSE) s.push_back(mk(K_C2R_X, 0, nx, 0, 0, inv_n, BUF_WS, BUF_OUT));
+        else s.push_back(mk(K_C2R_X, 0, nx, 0, 1, 1.0, BUF_WS, BUF_OUT));  // adjoint of r2c
+        break;
+    case OP_POISSON:
+        s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+        s.push_back(mk(K_POISSON_Z, 2, nz, 0, 0, inv_n, BUF_WS, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+        s.push_back(mk(K_C2R_X, 0, nx, 0, 0, 1.0, BUF_WS, BUF_OUT));
+        break;
+    case OP_POISSON_ADJ:
+        // adjoint of each forward step, in reverse order:
+        //   c2r^T = (x2 interior bins) r2c, (y inverse)^T = y forward,
+        //   z stage (real multiplier) is self-adjoint, (y forward)^T = y inverse,
+        //   r2c^T = c2r of (interior bins x1/2)
+        s.push_back(mk(K_R2C_X, 0, nx, 0, 1, 1.0, BUF_IN, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+        s.push_back(mk(K_POISSON_Z, 2, nz, 0, 0, inv_n, BUF_WS, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+        s.push_back(mk(K_C2R_X, 0, nx, 0, 1, 1.0, BUF_WS, BUF_OUT));
+        break;
+    default:
+        break;
+    }
+    return s;
+}
+
+void place_tasks(Pipeline& p, int nstreams)
+{
+    if (nstreams < 1) nstreams = 1;
+    p.nstreams = nstreams;
+    std::vector<double> load(nstreams, 0.0);
+    for (auto& t : p.tasks) {
+        std::vector<int> aff(nstreams, 0);
+        for (int d : t.deps) aff[p.tasks[d].stream]++;
+        int best = 0;
+        for (int s = 1; s < nstreams; ++s) {
+            if (load[s] < load[best] || (load[s] == load[best] && aff[s] > aff[best])) best = s;
+        }
+        t.stream = best;
+        load[best] += t.cost;
+    }
+    // Event waits: a task waits, per other stream, on the last of its producers
+    // there, unless an earlier task of its own stream already waited on that
+    // producer or a later task of that stream.
+    std::vector<std::vector<int>> seen(nstreams, std::vector<int>(nstreams, -1));
+    for (size_t i = 0; i < p.tasks.size(); ++i) {
+        Task& t = p.tasks[i];
+        t.waits.clear();
+        std::vector<int> last(nstreams, -1);
+        for (int d : t.deps) {
+            const int s = p.tasks[d].stream;
+            if (s != t.stream) last[s] = std::max(last[s], d);
+        }
+        for (int s = 0; s < nstreams; ++s) {
+            if (last[s] > seen[t.stream][s]) {
+                t.waits.push_back(last[s]);
+                seen[t.stream][s] = last[s];
+            }
+        }
+    }
+}
+
+Pipeline build_pipeline(const PlanDesc& d, int op, int nstreams)
+{
+    Pipeline p;
+    p.stages = op_stages(d, op);
+    int prev_begin = -1, prev_end = -1;
+    for (int si = 0; si < (int)p.stages.size(); ++si) {
+        const int begin = (int)p.tasks.size();
+        for (const Box& b : stage_boxes(d, p.stages[si].axis)) {
+            Task t;
+            t.stage = si;
+            t.box = b;
+            t.cost = (double)b.count();
+            for (int q = prev_begin; q >= 0 && q < prev_end; ++q)
+                if (boxes_overlap(p.tasks[q].box, b)) t.deps.push_back(q);
+            p.tasks.push_back(t);
+        }
+        prev_begin = begin;
+        prev_end = (int)p.tasks.size();
+    }
+    place_tasks(p, nstreams);
+    return p;
+}
+
+// cos and sin of (pi/2) * num / n for 0 <= num <= n, evaluated on an angle
+// of at most pi/4 so the small-angle end keeps full relative accuracy.
+static void quarter_turn(int64_t num, int64_t n, long double* c, long double* s)
+{
+    const long double half_pi = 1.57079632679489661923132169163975144L;
+    if (2 * num <= n) {
+        const long double a = half_pi * (long double)num / (long double)n;
+        *c = cosl(a);
+        *s = sinl(a);
+    } else {
+        const long double a = half_pi * (long double)(n - num) / (long double)n;
+        *c = sinl(a);
+        *s = cosl(a);
+    }
+}
+
+void twiddles_f64(int64_t n, double* out)
+{
+    for (int64_t m = 0; m < n; ++m) {
+        // angle 2 pi m / n = (pi/2) * 4m / n; fold into [0, pi/2] by symmetry
+        int64_t k = 4 * m;           // in units of (pi/2)/n, within [0, 4n)
+        const bool lower = k > 2 * n;  // angle in (pi, 2 pi): sin negative
+        if (lower) k = 4 * n - k;
+        const bool second = k > n;  // angle in (pi/2, pi]: cos negative
+        if (second) k = 2 * n - k;
+        long double c, s;
+        quarter_turn(k, n, &c, &s);
+        if (second) c = -c;
+        if (lower) s = -s;
+        out[2 * m] = (double)c;
+        out[2 * m + 1] = (double)(-s);  // forward root: exp(-i angle)
+    }
+}
+
+void twiddles_f32(int64_t n, float* out)
+{
+    std::vector<double> d((size_t)(2 * n));
+    twiddles_f64(n, d.data());
+    for (int64_t i = 0; i < 2 * n; ++i) out[i] = (float)d[(size_t)i];
+}
+
+}  // namespace fft3d

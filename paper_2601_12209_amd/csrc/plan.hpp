@@ -1,0 +1,86 @@
+// Host-side planning: pencil tiles per stage, the tile dependency graph, the
+// placement of tiles on streams, and the twiddle tables.  Plain C++ with no
+// HIP dependency, so all of it runs (and is tested) without a GPU.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace fft3d {
+
+enum Op : int {
+    OP_FORWARD = 0,       // C2C: forward; R2C plan: real -> half spectrum
+    OP_INVERSE = 1,       // sign +1, scaled 1/N (R2C plan: half spectrum -> real)
+    OP_BACKWARD = 2,      // adjoint of OP_FORWARD (unscaled)
+    OP_POISSON = 3,       // R2C plan only: phi = irfftn(M .* rfftn(f))
+    OP_POISSON_ADJ = 4,   // R2C plan only: adjoint of OP_POISSON
+    OP_COUNT = 5,
+};
+
+enum Buf : int { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
+
+struct PlanDesc {
+    int64_t nx, ny, nz;
+    int dtype;  // DT_F32 / DT_F64
+    int p1, p2;
+    int r2c;
+    int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent
+};
+
+// Half-open index box over the complex array (x, y, z).
+struct Box {
+    int64_t lo[3], hi[3];
+    int64_t count() const { return (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+};
+
+bool boxes_overlap(const Box& a, const Box& b);
+
+struct Stage {
+    int kind;      // KernelKind
+    int axis;      // 0 = x, 1 = y, 2 = z
+    int n;         // kernel length (real length for R2C/C2R)
+    int conj;      // conjugate-sign transform
+    int weight;    // adjoint weighting of interior half-spectrum bins
+    double scale;  // output scale
+    int src, dst;  // Buf ids
+};
+
+struct Task {
+    int stage;
+    Box box;
+    std::vector<int> deps;   // producer tasks (previous stage, overlapping boxes)
+    int stream = 0;          // placement
+    double cost = 0;         // estimated cost (elements moved)
+    std::vector<int> waits;  // producer tasks whose events this task's stream must wait on
+};
+
+struct Pipeline {
+    std::vector<Stage> stages;
+    std::vector<Task> tasks;  // stage by stage: a topological order
+    int nstreams = 1;
+};
+
+// Balanced split of [0, n) into p blocks: block i gets n/p elements plus one
+// more while i < n % p.
+void split_range(int64_t n, int p, int i, int64_t* lo, int64_t* hi);
+
+// Pencil boxes of one stage, in tile order.  x-pencils split (y, z) over
+// p1 x p2, y-pencils split (x, z), z-pencils split (x, y).
+std::vector<Box> stage_boxes(const PlanDesc& d, int axis);
+
+// Stages of an operation (empty if the op does not apply to the plan kind).
+std::vector<Stage> op_stages(const PlanDesc& d, int op);
+
+// Full task graph of an operation placed on nstreams streams.
+Pipeline build_pipeline(const PlanDesc& d, int op, int nstreams);
+
+// Locality-aware placement (paper Alg. 3 on one device): each tile goes to
+// the least-loaded stream, ties broken by the number of its producers already
+// on that stream; then the cross-stream event waits each tile needs.
+void place_tasks(Pipeline& p, int nstreams);
+
+// Forward roots W_n^m = exp(-2 pi i m / n), m < n, as interleaved doubles.
+void twiddles_f64(int64_t n, double* out);
+void twiddles_f32(int64_t n, float* out);  // round-to-nearest-even of the f64 table
+
+}  // namespace fft3d

@@ -1,0 +1,547 @@
+// C ABI of the library: plan objects, argument checks, and the issue of
+// pencil-tile tasks onto HIP streams (paper Alg. 1 stages, Sec. IV-D per-tile
+// dependencies, Alg. 3 placement; see plan.cpp for the graph itself).
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/fft3d.h"
+#include "fft_lengths.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "stage_args.hpp"
+
+using namespace fft3d;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fft3d_status fail(fft3d_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+fft3d_status hip_fail(hipError_t e, const char* what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_last_error = buf;
+    return e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? FFT3D_ERR_ALLOC
+                                                                     : FFT3D_ERR_HIP;
+}
+
+constexpr int kMaxStreams = 16;
+constexpr int kDefaultStreams = 4;
+
+}  // namespace
+
+struct fft3d_plan_s {
+    PlanDesc d{};
+    int device = 0;
+    int nstreams = kDefaultStreams;
+    std::vector<hipStream_t> streams;  // kMaxStreams, created up front
+    std::vector<hipEvent_t> events;    // one per task of the largest pipeline
+    hipEvent_t fork = nullptr;
+    void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis forward root tables
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    Pipeline pipes[OP_COUNT];
+    bool pipe_ok[OP_COUNT] = {};
+    std::vector<char> needs_event[OP_COUNT];
+    int lw_override[3] = {0, 0, 0};
+};
+
+namespace {
+
+size_t elem_bytes(int dtype) { return dtype == DT_F64 ? 16 : 8; }
+
+int64_t next_pow2(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Lines per workgroup.  Strided stages (y, z): enough neighbouring lines that
+// one row segment is >= 128 bytes and a workgroup holds >= 256 threads, within
+// 1024 threads and 64 KiB of LDS.  Contiguous stages (x): ~256 threads.
+int default_lw(const PlanDesc& d, const Stage& st, const Box& b)
+{
+    const bool real = st.kind == K_R2C_X || st.kind == K_C2R_X;
+    const int nk = real ? st.n / 2 : st.n;
+    const int tpl = radix_plan(nk).tpl;
+    const size_t s = elem_bytes(d.dtype);
+    const size_t lds_cap = 64 * 1024;
+    if (st.axis != 0) {
+        int lw = d.dtype == DT_F64 ? 8 : 16;
+        while (lw * tpl < 256 && lw < 64) lw *= 2;
+        const int64_t a = b.hi[0] - b.lo[0];
+        lw = (int)std::min<int64_t>(lw, next_pow2(a));
+        while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * nk * s > lds_cap)) lw /= 2;
+        return lw;
+    }
+    int lw = std::max(1, 256 / tpl);
+    while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * (nk + 1) * s > lds_cap)) lw /= 2;
+    return lw;
+}
+
+StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* const bufs[3])
+{
+    const PlanDesc& d = p->d;
+    const int64_t nxc = d.nxc(), ny = d.ny;
+    const int64_t dx = b.hi[0] - b.lo[0], dy = b.hi[1] - b.lo[1], dz = b.hi[2] - b.lo[2];
+    StageArgs a;
+    memset(&a, 0, sizeof a);
+    a.in = bufs[st.src];
+    a.out = bufs[st.dst];
+    a.tw = p->tw[st.axis];
+    a.conj = st.conj;
+    a.weight = st.weight;
+    a.scale = st.scale;
+    a.se = 1;
+    if (st.axis == 0) {
+        a.A = dy;
+        a.B = dz;
+        const int64_t row = b.lo[1] + ny * b.lo[2];
+        if (st.kind == K_R2C_X) {
+            const int64_t h = d.nx / 2;  // complex pairs per real row
+            a.off = row * h; a.sa = h; a.sb = h * ny;
+            a.off_o = row * nxc; a.sa_o = nxc; a.sb_o = nxc * ny;
+        } else if (st.kind == K_C2R_X) {
+            const int64_t h = d.nx / 2;
+            a.off = row * nxc; a.sa = nxc; a.sb = nxc * ny;
+            a.off_o = row * h; a.sa_o = h; a.sb_o = h * ny;
+        } else {
+            a.off = row * nxc; a.sa = nxc; a.sb = nxc * ny;
+        }
+        a.strided = 0;
+    } else if (st.axis == 1) {
+        a.A = dx;
+        a.B = dz;
+        a.off = b.lo[0] + b.lo[2] * nxc * ny;
+        a.sa = 1;
+        a.sb = nxc * ny;
+        a.se = nxc;
+        a.strided = 1;
+    } else {
+        a.A = dx;
+        a.B = dy;
+        a.off = b.lo[0] + b.lo[1] * nxc;
+        a.sa = 1;
+        a.sb = nxc;
+        a.se = nxc * ny;
+        a.strided = 1;
+        a.pnx = d.nx; a.pny = d.ny; a.pnz = d.nz;
+        a.kx0 = b.lo[0];
+        a.ky0 = b.lo[1];
+    }
+    const int ov = p->lw_override[st.axis];
+    a.lw = ov > 0 ? ov : default_lw(d, st, b);
+    return a;
+}
+
+hipError_t launch_task(const fft3d_plan_s* p, const Stage& st, const StageArgs& a, hipStream_t s)
+{
+    switch (st.kind) {
+    case K_C2C: return launch_c2c(st.n, p->d.dtype, a, s);
+    case K_R2C_X: return launch_r2c_x(st.n, p->d.dtype, a, s);
+    case K_C2R_X: return launch_c2r_x(st.n, p->d.dtype, a, s);
+    case K_POISSON_Z: return launch_poisson_z(st.n, p->d.dtype, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+fft3d_status validate_desc(const PlanDesc& d)
+{
+    if (d.dtype != DT_F32 && d.dtype != DT_F64) return fail(FFT3D_ERR_INVALID_ARG, "dtype must be 0 (c64) or 1 (c128)");
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(FFT3D_ERR_INVALID_ARG, "dimensions must be >= 1");
+    if (d.r2c != 0 && d.r2c != 1) return fail(FFT3D_ERR_INVALID_ARG, "r2c must be 0 or 1");
+    if (!length_supported(d.ny) || !length_supported(d.nz))
+        return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "ny or nz has no compiled kernel");
+    if (d.r2c) {
+        if (d.nx % 2 != 0 || !length_supported(d.nx / 2) || !length_supported(d.nx))
+            return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "r2c needs an even nx with nx and nx/2 supported");
+    } else if (!length_supported(d.nx)) {
+        return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "nx has no compiled kernel");
+    }
+    if (d.p1 < 1 || d.p2 < 1 || d.p1 > std::min(d.ny, d.nxc()) || d.p2 > std::min(d.nz, d.ny))
+        return fail(FFT3D_ERR_INVALID_ARG, "pencil grid must satisfy 1<=p1<=min(ny,nxc), 1<=p2<=min(nz,ny)");
+    return FFT3D_OK;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+const Pipeline& get_pipeline(fft3d_plan_s* p, int op)
+{
+    if (!p->pipe_ok[op] || p->pipes[op].nstreams != p->nstreams) {
+        p->pipes[op] = build_pipeline(p->d, op, p->nstreams);
+        const Pipeline& pl = p->pipes[op];
+        std::vector<char> need(pl.tasks.size(), 0);
+        std::vector<int> last(p->nstreams, -1);
+        for (size_t i = 0; i < pl.tasks.size(); ++i) {
+            for (int w : pl.tasks[i].waits) need[w] = 1;
+            last[pl.tasks[i].stream] = (int)i;
+        }
+        for (int s = 0; s < p->nstreams; ++s)
+            if (last[s] >= 0) need[last[s]] = 1;
+        p->needs_event[op] = need;
+        p->pipe_ok[op] = true;
+    }
+    return p->pipes[op];
+}
+
+fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* stream)
+{
+    const Pipeline& pl = get_pipeline(p, op);
+    if (pl.stages.empty()) return fail(FFT3D_ERR_WRONG_PLAN, "operation not available for this plan kind");
+    hipStream_t user = (hipStream_t)stream;
+    void* bufs[3] = {const_cast<void*>(in), out, p->ws};
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (p->nstreams == 1) {
+        for (const Task& t : pl.tasks) {
+            const Stage& st = pl.stages[t.stage];
+            e = launch_task(p, st, make_args(p, st, t.box, bufs), user);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+        return FFT3D_OK;
+    }
+    const std::vector<char>& need = p->needs_event[op];
+    e = hipEventRecord(p->fork, user);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
+    std::vector<char> started(p->nstreams, 0);
+    std::vector<int> last(p->nstreams, -1);
+    for (size_t i = 0; i < pl.tasks.size(); ++i) {
+        const Task& t = pl.tasks[i];
+        hipStream_t s = p->streams[t.stream];
+        if (!started[t.stream]) {
+            e = hipStreamWaitEvent(s, p->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
+            started[t.stream] = 1;
+        }
+        for (int w : t.waits) {
+            e = hipStreamWaitEvent(s, p->events[w], 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        }
+        const Stage& st = pl.stages[t.stage];
+        e = launch_task(p, st, make_args(p, st, t.box, bufs), s);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (need[i]) {
+            e = hipEventRecord(p->events[i], s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        last[t.stream] = (int)i;
+    }
+    for (int s = 0; s < p->nstreams; ++s) {
+        if (last[s] < 0) continue;
+        e = hipStreamWaitEvent(user, p->events[last[s]], 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(join)");
+    }
+    return FFT3D_OK;
+}
+
+void release(fft3d_plan_s* p)
+{
+    for (hipStream_t s : p->streams)
+        if (s) {
+            hipStreamSynchronize(s);
+            hipStreamDestroy(s);
+        }
+    for (hipEvent_t ev : p->events)
+        if (ev) hipEventDestroy(ev);
+    if (p->fork) hipEventDestroy(p->fork);
+    for (void* t : p->tw)
+        if (t) hipFree(t);
+    if (p->ws && p->ws_owned) hipFree(p->ws);
+    delete p;
+}
+
+fft3d_status check_plan_and_ptrs(fft3d_plan_t p, const void* in, const void* out)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (!in || !out) return fail(FFT3D_ERR_INVALID_ARG, "null buffer");
+    return FFT3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype, int p1,
+                        int p2, int r2c)
+{
+    if (!plan) return fail(FFT3D_ERR_INVALID_ARG, "null plan pointer");
+    *plan = nullptr;
+    PlanDesc d;
+    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = dtype; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
+    fft3d_status st = validate_desc(d);
+    if (st != FFT3D_OK) return st;
+
+    fft3d_plan_s* p = new fft3d_plan_s();
+    p->d = d;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    // twiddle tables in the plan precision (FP64-generated, rounded for c64)
+    const int64_t lens[3] = {nx, ny, nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        const int64_t n = lens[ax];
+        const size_t bytes = (size_t)n * elem_bytes(dtype);
+        std::vector<char> host(bytes);
+        if (dtype == DT_F64) twiddles_f64(n, (double*)host.data());
+        else twiddles_f32(n, (float*)host.data());
+        e = hipMalloc(&p->tw[ax], bytes);
+        if (e == hipSuccess) e = hipMemcpy(p->tw[ax], host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            release(p);
+            return hip_fail(e, "twiddle upload");
+        }
+    }
+    if (r2c) {
+        p->ws_bytes = (size_t)d.nxc() * ny * nz * elem_bytes(dtype);
+        e = hipMalloc(&p->ws, p->ws_bytes);
+        if (e != hipSuccess) {
+            p->ws = nullptr;
+            release(p);
+            return hip_fail(e, "workspace allocation");
+        }
+        p->ws_owned = true;
+    }
+    p->streams.assign(kMaxStreams, nullptr);
+    for (int s = 0; s < kMaxStreams; ++s) {
+        e = hipStreamCreateWithFlags(&p->streams[s], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            p->streams[s] = nullptr;
+            release(p);
+            return hip_fail(e, "hipStreamCreate");
+        }
+    }
+    const size_t max_tasks = 5 * (size_t)p1 * p2;
+    p->events.assign(max_tasks, nullptr);
+    for (size_t i = 0; i < max_tasks; ++i) {
+        e = hipEventCreateWithFlags(&p->events[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            p->events[i] = nullptr;
+            release(p);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        p->fork = nullptr;
+        release(p);
+        return hip_fail(e, "hipEventCreate");
+    }
+    *plan = p;
+    return FFT3D_OK;
+}
+
+fft3d_status fft3d_destroy(fft3d_plan_t plan)
+{
+    if (plan) release(plan);
+    return FFT3D_OK;
+}
+
+static fft3d_status c2c_or_r2c(fft3d_plan_t p, int op, const void* in, void* out, void* stream)
+{
+    fft3d_status st = check_plan_and_ptrs(p, in, out);
+    if (st != FFT3D_OK) return st;
+    const PlanDesc& d = p->d;
+    const size_t s = elem_bytes(d.dtype);
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    if (!d.r2c) {
+        if (in != out && ranges_overlap(in, n * s, out, n * s))
+            return fail(FFT3D_ERR_ALIAS, "in and out partially overlap");
+    } else {
+        const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.nxc() * d.ny * d.nz * s;
+        const size_t in_bytes = op == OP_FORWARD ? real_bytes : half_bytes;
+        const size_t out_bytes = op == OP_FORWARD ? half_bytes : real_bytes;
+        if (ranges_overlap(in, in_bytes, out, out_bytes))
+            return fail(FFT3D_ERR_ALIAS, "real-to-complex transforms cannot run in place");
+        if (op != OP_FORWARD &&
+            (ranges_overlap(p->ws, p->ws_bytes, in, in_bytes) || ranges_overlap(p->ws, p->ws_bytes, out, out_bytes)))
+            return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
+    }
+    return run(p, op, in, out, stream);
+}
+
+fft3d_status fft3d_forward(fft3d_plan_t p, const void* in, void* out, void* stream)
+{
+    return c2c_or_r2c(p, OP_FORWARD, in, out, stream);
+}
+
+fft3d_status fft3d_inverse(fft3d_plan_t p, const void* in, void* out, void* stream)
+{
+    return c2c_or_r2c(p, OP_INVERSE, in, out, stream);
+}
+
+fft3d_status fft3d_backward(fft3d_plan_t p, const void* in, void* out, void* stream)
+{
+    return c2c_or_r2c(p, OP_BACKWARD, in, out, stream);
+}
+
+static fft3d_status poisson_op(fft3d_plan_t p, int op, const void* f, void* phi, void* stream)
+{
+    fft3d_status st = check_plan_and_ptrs(p, f, phi);
+    if (st != FFT3D_OK) return st;
+    if (!p->d.r2c) return fail(FFT3D_ERR_WRONG_PLAN, "the Poisson solve needs a real-to-complex plan");
+    const size_t bytes = (size_t)p->d.nx * p->d.ny * p->d.nz * elem_bytes(p->d.dtype) / 2;
+    if (f != phi && ranges_overlap(f, bytes, phi, bytes))
+        return fail(FFT3D_ERR_ALIAS, "f and phi partially overlap");
+    if (ranges_overlap(p->ws, p->ws_bytes, f, bytes) || ranges_overlap(p->ws, p->ws_bytes, phi, bytes))
+        return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
+    return run(p, op, f, phi, stream);
+}
+
+fft3d_status fft3d_poisson(fft3d_plan_t p, const void* f, void* phi, void* stream)
+{
+    return poisson_op(p, OP_POISSON, f, phi, stream);
+}
+
+fft3d_status fft3d_poisson_adjoint(fft3d_plan_t p, const void* gphi, void* gf, void* stream)
+{
+    return poisson_op(p, OP_POISSON_ADJ, gphi, gf, stream);
+}
+
+size_t fft3d_workspace_bytes(fft3d_plan_t p)
+{
+    if (!p || !p->d.r2c) return 0;
+    return (size_t)p->d.nxc() * p->d.ny * p->d.nz * elem_bytes(p->d.dtype);
+}
+
+fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (!p->d.r2c) return ws ? fail(FFT3D_ERR_WRONG_PLAN, "C2C plans use no workspace") : FFT3D_OK;
+    const size_t need = fft3d_workspace_bytes(p);
+    if (ws && bytes < need) return fail(FFT3D_ERR_WORKSPACE, "workspace smaller than fft3d_workspace_bytes");
+    if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    // the old workspace may still be in use by enqueued work
+    for (hipStream_t s : p->streams) hipStreamSynchronize(s);
+    if (ws) {
+        if (p->ws_owned) hipFree(p->ws);
+        p->ws = ws;
+        p->ws_owned = false;
+        p->ws_bytes = bytes;
+        return FFT3D_OK;
+    }
+    if (p->ws_owned) return FFT3D_OK;
+    void* mine = nullptr;
+    hipError_t e = hipMalloc(&mine, need);
+    if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+    p->ws = mine;
+    p->ws_owned = true;
+    p->ws_bytes = need;
+    return FFT3D_OK;
+}
+
+fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (nstreams < 1 || nstreams > kMaxStreams) return fail(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
+    p->nstreams = nstreams;
+    return FFT3D_OK;
+}
+
+fft3d_status fft3d_set_lines_per_block(fft3d_plan_t p, int axis, int lw)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (axis < 0 || axis > 2 || lw < 0 || lw > 1024 || (lw & (lw - 1)) != 0)
+        return fail(FFT3D_ERR_INVALID_ARG, "axis 0..2 and lw a power of two (0 = default)");
+    // the kernel must fit: threads and LDS
+    const bool real = p->d.r2c && axis == 0;
+    const int64_t lens[3] = {p->d.nx, p->d.ny, p->d.nz};
+    const int nk = (int)(real ? lens[axis] / 2 : lens[axis]);
+    const int tpl = radix_plan(nk).tpl;
+    if (lw > 0 && ((int64_t)lw * tpl > 1024 || (size_t)lw * (nk + 1) * elem_bytes(p->d.dtype) > kMaxLdsBytes))
+        return fail(FFT3D_ERR_INVALID_ARG, "lines per block exceed 1024 threads or the LDS limit");
+    p->lw_override[axis] = lw;
+    return FFT3D_OK;
+}
+
+const char* fft3d_status_string(int status)
+{
+    switch (status) {
+    case FFT3D_OK: return "ok";
+    case FFT3D_ERR_INVALID_ARG: return "invalid argument";
+    case FFT3D_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+    case FFT3D_ERR_ALLOC: return "device allocation failed";
+    case FFT3D_ERR_HIP: return "HIP runtime error";
+    case FFT3D_ERR_ALIAS: return "buffers overlap";
+    case FFT3D_ERR_WORKSPACE: return "workspace too small";
+    case FFT3D_ERR_WRONG_PLAN: return "operation not available for this plan kind";
+    default: return "unknown status";
+    }
+}
+
+const char* fft3d_last_error(void) { return g_last_error.c_str(); }
+
+int fft3d_length_supported(int64_t n) { return length_supported(n) ? 1 : 0; }
+
+int fft3d_query_radix_plan(int64_t n, int* out, int cap)
+{
+    if (!length_supported(n) || !out) return -1;
+    const RadixPlan rp = radix_plan((int)n);
+    if (cap < rp.np + 2) return -1;
+    out[0] = rp.np;
+    for (int i = 0; i < rp.np; ++i) out[1 + i] = rp.r[i];
+    out[rp.np + 1] = rp.tpl;
+    return rp.np + 2;
+}
+
+fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out)
+{
+    if (n < 1 || !out) return fail(FFT3D_ERR_INVALID_ARG, "bad length or null output");
+    if (dtype == DT_F64) twiddles_f64(n, (double*)out);
+    else if (dtype == DT_F32) twiddles_f32(n, (float*)out);
+    else return fail(FFT3D_ERR_INVALID_ARG, "bad dtype");
+    return FFT3D_OK;
+}
+
+int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int op,
+                             int nstreams, int64_t* out, int64_t cap)
+{
+    PlanDesc d;
+    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = DT_F32; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
+    if (validate_desc(d) != FFT3D_OK) return -1;
+    if (op < 0 || op >= OP_COUNT || nstreams < 1 || nstreams > kMaxStreams) return -1;
+    const Pipeline pl = build_pipeline(d, op, nstreams);
+    std::vector<int64_t> v;
+    v.push_back((int64_t)pl.tasks.size());
+    v.push_back((int64_t)pl.stages.size());
+    for (const Stage& s : pl.stages) {
+        int64_t rec[7] = {s.kind, s.axis, s.n, s.conj, s.weight, s.src, s.dst};
+        v.insert(v.end(), rec, rec + 7);
+    }
+    for (const Task& t : pl.tasks) {
+        v.push_back(t.stage);
+        for (int ax = 0; ax < 3; ++ax) {
+            v.push_back(t.box.lo[ax]);
+            v.push_back(t.box.hi[ax]);
+        }
+        v.push_back(t.stream);
+        v.push_back((int64_t)t.deps.size());
+        v.insert(v.end(), t.deps.begin(), t.deps.end());
+        v.push_back((int64_t)t.waits.size());
+        v.insert(v.end(), t.waits.begin(), t.waits.end());
+    }
+    if (out && cap >= (int64_t)v.size()) memcpy(out, v.data(), v.size() * sizeof(int64_t));
+    return (int64_t)v.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+"""Python binding of the fft3d C ABI over torch tensors.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+transform runs in the library's own kernels.  Shapes are torch order
+``(nz, ny, nx)`` with x fastest in memory (the C ABI's x + Nx*(y + Ny*z)).
+
+Plans are cached per (shape, dtype, pencil grid, r2c, device), as the paper's
+plan cache is keyed by data type, size and transform type (Sec. V-B).
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+C64, C128 = 0, 1
+_COMPLEX = {C64: torch.complex64, C128: torch.complex128}
+_REAL = {C64: torch.float32, C128: torch.float64}
+
+
+def load():
+    """Load the HIP library (raises if it is not built)."""
+    return _lib.lib()
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (torch.complex64, torch.float32, "c64", "complex64", "f32", C64):
+        return C64
+    if dtype in (torch.complex128, torch.float64, "c128", "complex128", "f64", C128):
+        return C128
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+def _stream_handle(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind."""
+
+    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None):
+        nz, ny, nx = (int(v) for v in shape)
+        self.shape = (nz, ny, nx)
+        self.code = _dtype_code(dtype)
+        self.grid = (int(grid[0]), int(grid[1]))
+        self.r2c = bool(r2c)
+        h = ctypes.c_void_p()
+        check(_lib.lib().fft3d_plan(ctypes.byref(h), nx, ny, nz, self.code, self.grid[0],
+                                    self.grid[1], int(self.r2c)), "fft3d_plan")
+        self._h = h
+        self.device = torch.cuda.current_device()
+        self._ws = None
+        if streams is not None:
+            self.set_streams(streams)
+
+    # ------------------------------------------------------------ helpers
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def complex_dtype(self):
+        return _COMPLEX[self.code]
+
+    @property
+    def real_dtype(self):
+        return _REAL[self.code]
+
+    @property
+    def half_shape(self):
+        nz, ny, nx = self.shape
+        return (nz, ny, nx // 2 + 1)
+
+    def _check_tensor(self, t, dtype, shape, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _call(self, fn, x, out, in_dtype, in_shape, out_dtype, out_shape, stream):
+        self._check_tensor(x, in_dtype, in_shape, "input")
+        if out is None:
+            out = torch.empty(out_shape, dtype=out_dtype, device=x.device)
+        self._check_tensor(out, out_dtype, out_shape, "out")
+        check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                 ctypes.c_void_p(_stream_handle(stream))), fn.__name__)
+        return out
+
+    # ------------------------------------------------------------ transforms
+    def forward(self, x, out=None, stream=None):
+        """Forward 3D FFT (sign -1, unscaled)."""
+        L = _lib.lib()
+        if self.r2c:
+            return self._call(L.fft3d_forward, x, out, self.real_dtype, self.shape, self.complex_dtype,
+                              self.half_shape, stream)
+        return self._call(L.fft3d_forward, x, out, self.complex_dtype, self.shape, self.complex_dtype,
+                          self.shape, stream)
+
+    def inverse(self, x, out=None, stream=None):
+        """Inverse 3D FFT (sign +1, scaled by 1/N)."""
+        L = _lib.lib()
+        if self.r2c:
+            return self._call(L.fft3d_inverse, x, out, self.complex_dtype, self.half_shape,
+                              self.real_dtype, self.shape, stream)
+        return self._call(L.fft3d_inverse, x, out, self.complex_dtype, self.shape, self.complex_dtype,
+                          self.shape, stream)
+
+    def backward(self, x, out=None, stream=None):
+        """Adjoint of forward (C2C: unscaled sign +1 transform)."""
+        L = _lib.lib()
+        if self.r2c:
+            return self._call(L.fft3d_backward, x, out, self.complex_dtype, self.half_shape,
+                              self.real_dtype, self.shape, stream)
+        return self._call(L.fft3d_backward, x, out, self.complex_dtype, self.shape,
+                          self.complex_dtype, self.shape, stream)
+
+    def poisson(self, f, out=None, stream=None):
+        """phi = irfftn(M * rfftn(f)), M = -1/|k|^2, M(0) = 0 (R2C plans)."""
+        return self._call(_lib.lib().fft3d_poisson, f, out, self.real_dtype, self.shape,
+                          self.real_dtype, self.shape, stream)
+
+    def poisson_adjoint(self, g, out=None, stream=None):
+        """Adjoint of :meth:`poisson` applied to g."""
+        return self._call(_lib.lib().fft3d_poisson_adjoint, g, out, self.real_dtype, self.shape,
+                          self.real_dtype, self.shape, stream)
+
+    # ------------------------------------------------------------ tuning
+    def set_streams(self, n: int):
+        check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
+
+    def set_lines_per_block(self, axis: int, lw: int):
+        check(_lib.lib().fft3d_set_lines_per_block(self._h, int(axis), int(lw)),
+              "fft3d_set_lines_per_block")
+
+    def workspace_bytes(self) -> int:
+        return int(_lib.lib().fft3d_workspace_bytes(self._h))
+
+    def set_workspace(self, buf):
+        """Use a caller tensor as the workspace (None: back to a plan-owned one)."""
+        ptr = None if buf is None else ctypes.c_void_p(buf.data_ptr())
+        nbytes = 0 if buf is None else buf.numel() * buf.element_size()
+        check(_lib.lib().fft3d_set_workspace(self._h, ptr, nbytes), "fft3d_set_workspace")
+        self._ws = buf
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().fft3d_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache: dict = {}
+_cache_lock = threading.Lock()
+
+
+def get_plan(shape, dtype, grid=(1, 1), r2c=False) -> Plan:
+    """Plan cache keyed by (shape, precision, grid, r2c, device)."""
+    key = (tuple(int(v) for v in shape), _dtype_code(dtype), tuple(grid), bool(r2c),
+           torch.cuda.current_device())
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = Plan(shape, dtype, grid, r2c)
+            _cache[key] = p
+        return p
+
+
+def clear_plan_cache():
+    with _cache_lock:
+        for p in _cache.values():
+            p.close()
+        _cache.clear()
+
+
+def fftn(x, grid=(1, 1), out=None):
+    return get_plan(x.shape, x.dtype, grid).forward(x, out)
+
+
+def ifftn(x, grid=(1, 1), out=None):
+    return get_plan(x.shape, x.dtype, grid).inverse(x, out)
+
+
+def bfftn(x, grid=(1, 1), out=None):
+    return get_plan(x.shape, x.dtype, grid).backward(x, out)
+
+
+def rfftn(x, grid=(1, 1), out=None):
+    return get_plan(x.shape, x.dtype, grid, r2c=True).forward(x, out)
+
+
+def irfftn(h, nx: int, grid=(1, 1), out=None):
+    nz, ny, _ = h.shape
+    return get_plan((nz, ny, nx), h.dtype, grid, r2c=True).inverse(h, out)
+
+
+class SpectralPoisson(torch.autograd.Function):
+    """phi = irfftn(rfftn(f) / (-|k|^2)), k = 0 mode zeroed, differentiable in f.
+
+    The backward pass runs the library's adjoint entry point (each stage of the
+    solve replaced by its adjoint, in reverse order).
+    """
+
+    @staticmethod
+    def forward(ctx, f, grid=(1, 1)):
+        plan = get_plan(f.shape, f.dtype, grid, r2c=True)
+        ctx.plan = plan
+        return plan.poisson(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, gphi):
+        return ctx.plan.poisson_adjoint(gphi.contiguous()), None
+
+
+def poisson(f, grid=(1, 1)):
+    return SpectralPoisson.apply(f, grid)
+
+
+# ---------------------------------------------------------------- host queries
+def length_supported(n: int) -> bool:
+    return bool(_lib.lib().fft3d_length_supported(int(n)))
+
+
+def query_radix_plan(n: int):
+    buf = (ctypes.c_int * 16)()
+    k = _lib.lib().fft3d_query_radix_plan(int(n), buf, 16)
+    if k < 0:
+        raise ValueError(f"length {n} is not supported")
+    np_ = buf[0]
+    return list(buf[1:1 + np_]), buf[np_ + 1]
+
+
+def query_twiddles(n: int, dtype) -> np.ndarray:
+    code = _dtype_code(dtype)
+    out = np.empty(n, dtype=np.complex64 if code == C64 else np.complex128)
+    check(_lib.lib().fft3d_query_twiddles(int(n), code, out.ctypes.data), "fft3d_query_twiddles")
+    return out
+
+
+def query_pipeline(shape, grid, r2c=False, op=0, nstreams=4):
+    """Decoded task graph: (stages, tasks) with boxes over the complex (x, y, z) index space."""
+    nz, ny, nx = shape
+    L = _lib.lib()
+    need = L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), op, nstreams, None, 0)
+    if need < 0:
+        raise ValueError("invalid pipeline arguments")
+    buf = (ctypes.c_int64 * need)()
+    L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), op, nstreams, buf, need)
+    v = list(buf)
+    ntasks, nstages = v[0], v[1]
+    pos = 2
+    stages = []
+    for _ in range(nstages):
+        kind, axis, n, conj, weight, src, dst = v[pos:pos + 7]
+        stages.append(dict(kind=kind, axis=axis, n=n, conj=conj, weight=weight, src=src, dst=dst))
+        pos += 7
+    tasks = []
+    for _ in range(ntasks):
+        stage = v[pos]
+        box = tuple(v[pos + 1:pos + 7])  # x0, x1, y0, y1, z0, z1
+        stream = v[pos + 7]
+        nd = v[pos + 8]
+        deps = v[pos + 9:pos + 9 + nd]
+        pos += 9 + nd
+        nw = v[pos]
+        waits = v[pos + 1:pos + 1 + nw]
+        pos += 1 + nw
+        tasks.append(dict(stage=stage, box=box, stream=stream, deps=list(deps), waits=list(waits)))
+    return stages, tasks
