@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the pencil 3D FFT on one MI355X.
+
+One step = forward + inverse 3D C2C FFT of a 512^3 complex64 field (the
+headline workload): x, y, z stages forward, z, y, x inverse, every stage a
+batch of 1D Stockham FFTs over its pencil tiles.  The input (i.i.d. N(0,1)
+real and imaginary parts, seed 0) is resident in HBM before timing starts.
+
+Reported (one JSON line):
+  value       GFLOP/s = 2 transforms * 5 N log2 N / (seconds per step), FP32 path
+  fp64        the same workload in complex128, and the FP32/FP64 speedup
+  stages      per-stage milliseconds and achieved GB/s (2 * elem bytes * N per stage)
+  roofline    the slowest stage kernel against the 8 TB/s HBM peak
+  cpu_baseline the FP64 oracle on the same field on the host cores, with the
+              rel-L2 error of the GPU results against it
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+DEFAULT_GRID = (1, 1)
+DEFAULT_STREAMS = 1
+
+
+def _timed_steps(step, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def _stage_profile(plan, x, X, Y, reps, torch):
+    """Average per-stage milliseconds of forward and inverse (timing mode)."""
+    plan.set_timing(True)
+    fwd, inv = None, None
+    for _ in range(reps):
+        plan.forward(x, out=X)
+        f = plan.stage_times()
+        plan.inverse(X, out=Y)
+        i = plan.stage_times()
+        fwd = f if fwd is None else [a + b for a, b in zip(fwd, f)]
+        inv = i if inv is None else [a + b for a, b in zip(inv, i)]
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+    return [v / reps for v in fwd], [v / reps for v in inv]
+
+
+def _measure(dtype, shape, grid, streams, steps, warmup, a_host, torch, fft3d):
+    x = torch.from_numpy(a_host).to(device="cuda", dtype=dtype)
+    X = torch.empty_like(x)
+    Y = torch.empty_like(x)
+    plan = fft3d.Plan(shape, dtype, grid, streams=streams)
+
+    def step():
+        plan.forward(x, out=X)
+        plan.inverse(X, out=Y)
+
+    ms, wall = _timed_steps(step, steps, warmup, torch)
+    fwd_st, inv_st = _stage_profile(plan, x, X, Y, max(3, min(steps, 10)), torch)
+    plan.forward(x, out=X)
+    plan.inverse(X, out=Y)
+    torch.cuda.synchronize()
+    plan.close()
+    return dict(ms=ms, wall=wall, fwd_stages=fwd_st, inv_stages=inv_st, X=X, Y=Y)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512, help="grid edge (default 512)")
+    ap.add_argument("--grid", type=int, nargs=2, default=list(DEFAULT_GRID), help="pencil grid P1 P2")
+    ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 run")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle on the host")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy the complex64 field once with a plain device copy "
+                         "(a known-size reference for HBM byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the pencil FFT here runs on a single MI355X "
+              "(no multi-GPU path is built); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import synth
+    from paper_2601_12209_amd import fft3d
+
+    fft3d.load()
+    n_edge = args.size
+    shape = (n_edge, n_edge, n_edge)
+    N = n_edge ** 3
+    flop_per_transform = 5.0 * N * math.log2(N)
+    grid = tuple(args.grid)
+    print(f"# input: {shape} complex N(0,1), seed {synth.HEADLINE['seed']}", file=sys.stderr, flush=True)
+    a = synth.complex_normal(shape, synth.HEADLINE["seed"], np.complex64)
+
+    r32 = _measure(torch.complex64, shape, grid, args.streams, args.steps, args.warmup, a, torch, fft3d)
+    print(f"# c64: {r32['ms']:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        dst = torch.empty_like(r32["X"])
+        dst.copy_(r32["X"])
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {dst.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
+        del dst
+    r64 = None
+    if not args.no_fp64:
+        a64 = a.astype(np.complex128)
+        r64 = _measure(torch.complex128, shape, grid, args.streams, args.steps, args.warmup, a64, torch, fft3d)
+        del a64
+        print(f"# c128: {r64['ms']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    def stage_report(r, elem):
+        names = ["x", "y", "z"]
+        out = {}
+        for tag, st, order in (("fwd", r["fwd_stages"], names), ("inv", r["inv_stages"], names[::-1])):
+            for nm, ms in zip(order, st):
+                gbs = 2.0 * elem * N / (ms * 1e-3) / 1e9
+                out[f"{tag}_{nm}"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        return out
+
+    st32 = stage_report(r32, 8)
+    gflops32 = 2 * flop_per_transform / (r32["ms"] * 1e-3) / 1e9
+    # dominant kernel: the slowest stage (one kernel launch over the whole field at grid 1x1)
+    dom_name, dom = max(st32.items(), key=lambda kv: kv[1]["ms"])
+    bytes_per_launch = 2.0 * 8 * N
+    achieved = bytes_per_launch / (dom["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"stage {dom_name} (k_c2c<float, {n_edge}>)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    whole_frac = 6 * 2.0 * 8 * N / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    result = {
+        "metric": "3D FFT GFLOP/s (5N·log2N/t) + % HBM peak, 512^3 C2C, FP32 vs FP64",
+        "value": round(gflops32, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: complex N(0,1) field, seed 0, resident in HBM",
+        "config": {"workload": f"c2c_{n_edge}cubed_forward_plus_inverse", "nx": n_edge, "ny": n_edge,
+                   "nz": n_edge, "precision": "complex64", "pencil_grid": list(grid),
+                   "streams": args.streams},
+        "hbm_frac_whole_step": round(whole_frac, 4),
+        "stages_c64": st32,
+        "roofline": roofline,
+        "wall_s_timed": round(r32["wall"], 4),
+    }
+    if r64 is not None:
+        gflops64 = 2 * flop_per_transform / (r64["ms"] * 1e-3) / 1e9
+        result["fp64"] = {"value": round(gflops64, 1), "unit": "GFLOP/s", "ms_per_step": round(r64["ms"], 4),
+                          "hbm_frac_whole_step": round(6 * 2.0 * 16 * N / (r64["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "stages_c128": stage_report(r64, 16),
+                          "fp32_over_fp64_speedup": round(r64["ms"] / r32["ms"], 3)}
+
+    if not args.no_cpu_baseline:
+        import oracle  # test infrastructure: the CPU baseline leg only
+
+        a128 = a.astype(np.complex128)
+        t0 = time.perf_counter()
+        X_ref = oracle.fftn(a128)
+        Y_ref = oracle.ifftn(X_ref)
+        t_cpu = time.perf_counter() - t0
+        errs = {"c64_forward": oracle.rel_l2(r32["X"].cpu().numpy(), X_ref),
+                "c64_inverse_of_forward": oracle.rel_l2(r32["Y"].cpu().numpy(), a128)}
+        if r64 is not None:
+            errs["c128_forward"] = oracle.rel_l2(r64["X"].cpu().numpy(), X_ref)
+            errs["c128_inverse_of_forward"] = oracle.rel_l2(r64["Y"].cpu().numpy(), a128)
+        del Y_ref
+        result["cpu_baseline"] = {
+            "value": round(2 * flop_per_transform / t_cpu / 1e9, 3), "unit": "GFLOP/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one FP64 forward + inverse of the same {n_edge}^3 field ({t_cpu:.1f} s)",
+            "rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in errs.items()},
+        }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

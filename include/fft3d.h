@@ -135,11 +135,28 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
 /*
- * Override the lines-per-workgroup choice for one stage kernel of this plan
- * (axis 0..2; lw a power of two, 0 restores the default).  Used by the
- * autotuner; results do not depend on it.
+ * Override the launch shape of the stage kernels along one axis (0 = x,
+ * 1 = y, 2 = z) of this plan: lw lines per workgroup (a power of two; 0
+ * restores the default shape), tdiv divides the threads that cooperate on one
+ * line (each then takes tdiv times more butterflies), split = 1 exchanges real
+ * and imaginary parts through LDS one after the other (half the LDS), pad = 1
+ * pads contiguous LDS lines against bank conflicts.  FFT3D_ERR_INVALID_ARG if
+ * any stage kernel of that axis cannot run with it.  Used by the autotuner;
+ * results do not depend on the shape beyond rounding order.
  */
-fft3d_status fft3d_set_lines_per_block(fft3d_plan_t plan, int axis, int lw);
+fft3d_status fft3d_set_stage_config(fft3d_plan_t plan, int axis, int lw, int tdiv, int split, int pad);
+
+/*
+ * Per-stage timing (tracing).  While enabled, every call on the plan records
+ * a timing event on the caller's stream before its first stage and after each
+ * stage; the tiles of a stage are forked from and joined back onto the
+ * caller's stream, so stages do not overlap while timing is on.
+ * fft3d_stage_times waits for the most recent call to finish and writes the
+ * elapsed milliseconds of each of its stages to ms[0..k); it returns k, or -1
+ * if no timed call was made or cap < k.
+ */
+fft3d_status fft3d_set_timing(fft3d_plan_t plan, int enable);
+int fft3d_stage_times(fft3d_plan_t plan, float* ms, int cap);
 
 /* Text for a status code; and the calling thread's last failure detail. */
 const char* fft3d_status_string(int status);

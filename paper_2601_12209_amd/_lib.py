@@ -26,7 +26,9 @@ _SIGS = {
     "fft3d_workspace_bytes": (SZ, [P]),
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
-    "fft3d_set_lines_per_block": (I32, [P, I32, I32]),
+    "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
+    "fft3d_set_timing": (I32, [P, I32]),
+    "fft3d_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), I32]),
     "fft3d_status_string": (ctypes.c_char_p, [I32]),
     "fft3d_last_error": (ctypes.c_char_p, []),
     "fft3d_length_supported": (I32, [I64]),

@@ -25,6 +25,9 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    # no automatic multiply-add contraction: every launch-shape variant of a
+    # kernel then performs identical arithmetic (bitwise-equal results)
+    "-ffp-contract=off",
     # packed fp32 instructions stay off (the compiler would form them from float2 code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -4,7 +4,7 @@
 // A length-N line is transformed by the passes of radix_plan(N).  Pass p
 // (radix R, sub-transform length Ns before it) treats butterfly j < N/R:
 //   inputs   a[r] = data[j + r*N/R],               r < R
-//   twiddle  a[r] *= W_N^(r * (j mod Ns) * N/(Ns*R))
+//   twiddle  a[r] *= W_N^(r * (j mod Ns) * N/(Ns*R))   (staged in LDS)
 //   DFT_R    on a
 //   outputs  data'[(j / Ns)*Ns*R + (j mod Ns) + r*Ns] = a[r]
 // (the self-sorting Stockham formulation: natural order in and out, no bit
@@ -32,9 +32,14 @@ struct alignas(2 * sizeof(T)) cpx {
 template <typename T> FD cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T> FD cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename T> FD cpx<T> operator*(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+// Fused multiply-add, explicit so that every kernel variant rounds the same
+// way (the library is compiled without automatic contraction).
+FD float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+FD double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T> FD cpx<T> cmul(cpx<T> a, cpx<T> b)
 {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fmadd(a.re, b.re, -(a.im * b.im)), fmadd(a.re, b.im, a.im * b.re)};
 }
 template <typename T> FD cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
 template <typename T> FD cpx<T> mul_i(cpx<T> a) { return {-a.im, a.re}; }     // i * a
@@ -156,111 +161,193 @@ template <int R, typename T> FD void dft_radix(cpx<T>* v)
 }
 
 // ------------------------------------------------------------ pass driver
+//
+// TPL threads cooperate on one line; pass p has N/R butterflies, thread tj
+// takes butterflies tj, tj + TPL, ... (the last may be masked).  TPL defaults
+// to N / (largest radix), one butterfly per thread in the widest pass; a
+// smaller TPL gives each thread more butterflies, so more lines fit in a
+// workgroup.  Between passes the outputs go through LDS: either as complex
+// values, or (SPLIT) real parts first and imaginary parts second through a
+// real-valued buffer of half the size.
 
-template <int N, int P>
+template <int N, int TPL_, int P>
 struct PassInfo {
     static constexpr RadixPlan PL = radix_plan(N);
     static constexpr int R = PL.r[P];
-    static constexpr int BF = N / R;          // butterflies in this pass
-    static constexpr int NS = radix_ns(PL, P);  // sub-transform length before it
-    static constexpr int TPL = PL.tpl;
+    static constexpr int BF = N / R;             // butterflies in this pass
+    static constexpr int NS = radix_ns(PL, P);   // sub-transform length before it
+    static constexpr int TPL = TPL_;
     static constexpr int NB = (BF + TPL - 1) / TPL;  // butterflies per thread
     static constexpr bool FULL = (BF % TPL) == 0;
     static constexpr int TWSTEP = N / (NS * R);
     static constexpr bool LAST = (P + 1 == PL.np);
 };
 
-// LDS view of the lines of a workgroup: element e of this thread's line sits
-// at base + e * es.
-template <typename T>
-struct LdsLine {
-    cpx<T>* base;
+template <int N, int TPL>
+constexpr int driver_ept()
+{
+    constexpr RadixPlan PL = radix_plan(N);
+    int e = 1;
+    for (int i = 0; i < PL.np; ++i) {
+        const int bf = N / PL.r[i];
+        const int nb = (bf + TPL - 1) / TPL;
+        e = nb * PL.r[i] > e ? nb * PL.r[i] : e;
+    }
+    return e;
+}
+
+// LDS view of one line: element e sits at base[e * es + (e >> 3) * pad].
+// The optional pad (one slot per eight elements) breaks the power-of-two
+// strides of the Stockham writes on contiguous lines across LDS banks.
+template <typename U>
+struct LdsView {
+    U* base;
     int es;
-    FD cpx<T>& operator[](int e) const { return base[e * es]; }
+    int pad;
+    FD U& operator[](int e) const { return base[e * es + (e >> 3) * pad]; }
 };
 
-// One Stockham pass.  `Load(e)` supplies pass-0 inputs, `Store(e, v)` takes
-// final outputs; other passes use the LDS line.  tw is the forward root table
-// W_N^m = exp(-2 pi i m / N) read at index m * TWM.
-// SRC_LDS: the loader reads this workgroup's LDS, so pass 0 must not write
-// LDS before every thread has loaded.  DST_LDS: the storer writes LDS, so the
-// last pass must not store before every thread has read its inputs.
-template <typename T, int N, int P, int TWM, bool SRC_LDS, bool DST_LDS, class Load, class Store>
-FD void stockham_pass(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw,
-                      Load& load, Store& store)
+// Pass-0 inputs through the loader.
+template <typename T, int N, int TPL, class Load>
+FD void load_first(cpx<T>* v, int tj, Load& load)
 {
-    using PI = PassInfo<N, P>;
-    constexpr int R = PI::R, BF = PI::BF, NS = PI::NS, TPL = PI::TPL, NB = PI::NB;
-    cpx<T> v[NB][R];
+    using PI = PassInfo<N, TPL, 0>;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
+    for (int i = 0; i < PI::NB; ++i) {
         const int j = tj + i * TPL;
-        if (PI::FULL || j < BF) {
+        if (PI::FULL || j < PI::BF) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if constexpr (P == 0) v[i][r] = load(j + r * BF);
-                else v[i][r] = L[j + r * BF];
-            }
+            for (int r = 0; r < PI::R; ++r) v[i * PI::R + r] = load(j + r * PI::BF);
         }
     }
+}
+
+// Twiddles and the radix-R DFTs of pass P, in registers.  twl is the
+// per-pass twiddle table staged in LDS (layout in fft_lengths.hpp): the roots
+// of butterfly k are R contiguous entries, so they load as wide LDS reads.
+template <typename T, int N, int TPL, int P>
+FD void compute_pass(cpx<T>* v, int tj, const cpx<T>* twl)
+{
+    using PI = PassInfo<N, TPL, P>;
+    constexpr int R = PI::R;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
+    for (int i = 0; i < PI::NB; ++i) {
         const int j = tj + i * TPL;
-        if (PI::FULL || j < BF) {
-            if constexpr (NS > 1) {
-                const int k = j % NS;
+        if (PI::FULL || j < PI::BF) {
+            if constexpr (PI::NS > 1) {
+                const cpx<T>* w = twl + pass_table_offset(PI::PL, P) + (j % PI::NS) * R;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(r * k * PI::TWSTEP) * TWM]);
+                for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], w[r]);
             }
-            dft_radix<R>(v[i]);
+            dft_radix<R>(v + i * R);
         }
     }
-    if constexpr (PI::LAST) {
-        if constexpr (DST_LDS && (P > 0 || SRC_LDS)) __syncthreads();
+}
+
+// Copy the per-pass twiddle table of the length-N kernel from global memory
+// into LDS (all threads of the workgroup; visible after the next barrier).
+template <typename T, int N>
+FD void stage_pass_twiddles(cpx<T>* twl, const cpx<T>* __restrict__ twp, int t, int nthreads)
+{
+    constexpr int S = pass_table_size(radix_plan(N));
+    for (int i = t; i < S; i += nthreads) twl[i] = twp[i];
+}
+
+template <typename T, int N>
+constexpr size_t pass_table_bytes()
+{
+    return (size_t)pass_table_size(radix_plan(N)) * sizeof(cpx<T>);
+}
+
+// Bytes of a kernel's LDS data region rounded up so the twiddle table that
+// follows it is 16-byte aligned.
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Visit every output of pass P: f(register index, output element).
+template <int N, int TPL, int P, class F>
+FD void for_outputs(int tj, F&& f)
+{
+    using PI = PassInfo<N, TPL, P>;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int j = tj + i * TPL;  // last pass: j < NS, output j + r*NS
-            if (PI::FULL || j < BF) {
+    for (int i = 0; i < PI::NB; ++i) {
+        const int j = tj + i * TPL;
+        if (PI::FULL || j < PI::BF) {
+            const int k = j % PI::NS;
+            const int o = (j / PI::NS) * PI::NS * PI::R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) store(j + r * NS, v[i][r]);
-            }
+            for (int r = 0; r < PI::R; ++r) f(i * PI::R + r, o + r * PI::NS);
         }
+    }
+}
+
+// Visit every input of pass P: f(register index, input element).
+template <int N, int TPL, int P, class F>
+FD void for_inputs(int tj, F&& f)
+{
+    using PI = PassInfo<N, TPL, P>;
+#pragma unroll
+    for (int i = 0; i < PI::NB; ++i) {
+        const int j = tj + i * TPL;
+        if (PI::FULL || j < PI::BF) {
+#pragma unroll
+            for (int r = 0; r < PI::R; ++r) f(i * PI::R + r, j + r * PI::BF);
+        }
+    }
+}
+
+// Outputs of pass P -> LDS -> inputs of pass P+1.  LEAD: a barrier is needed
+// first because other threads may still read this LDS.
+template <typename T, int N, int TPL, int P, bool SPLIT, bool LEAD>
+FD void exchange(cpx<T>* v, int tj, const LdsView<cpx<T>>& L, const LdsView<T>& Ls)
+{
+    if constexpr (!SPLIT) {
+        if constexpr (LEAD) __syncthreads();
+        for_outputs<N, TPL, P>(tj, [&](int q, int e) { L[e] = v[q]; });
+        __syncthreads();
+        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q] = L[e]; });
     } else {
-        if constexpr (P > 0 || SRC_LDS) __syncthreads();  // every read of this pass is done
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int j = tj + i * TPL;
-            if (PI::FULL || j < BF) {
-                const int k = j % NS;
-                const int o = (j / NS) * NS * R + k;
-#pragma unroll
-                for (int r = 0; r < R; ++r) L[o + r * NS] = v[i][r];
-            }
-        }
-        __syncthreads();  // the next pass reads what this one wrote
+        if constexpr (LEAD) __syncthreads();
+        for_outputs<N, TPL, P>(tj, [&](int q, int e) { Ls[e] = v[q].re; });
+        __syncthreads();
+        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q].re = Ls[e]; });
+        __syncthreads();
+        for_outputs<N, TPL, P>(tj, [&](int q, int e) { Ls[e] = v[q].im; });
+        __syncthreads();
+        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q].im = Ls[e]; });
     }
 }
 
-template <typename T, int N, int P, int TWM, bool SRC_LDS, bool DST_LDS, class Load, class Store>
-FD void stockham_from(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw, Load& load,
-                      Store& store)
+template <typename T, int N, int TPL, int P, bool SPLIT, bool SRC_LDS, bool DST_LDS, class Store>
+FD void passes_from(cpx<T>* v, int tj, const cpx<T>* twl, const LdsView<cpx<T>>& L,
+                    const LdsView<T>& Ls, Store& store)
 {
-    stockham_pass<T, N, P, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
-    if constexpr (P + 1 < radix_plan(N).np)
-        stockham_from<T, N, P + 1, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
+    compute_pass<T, N, TPL, P>(v, tj, twl);
+    if constexpr (PassInfo<N, TPL, P>::LAST) {
+        if constexpr (DST_LDS && (P > 0 || SRC_LDS)) __syncthreads();
+        for_outputs<N, TPL, P>(tj, [&](int q, int e) { store(e, v[q]); });
+    } else {
+        exchange<T, N, TPL, P, SPLIT, (P > 0 || SRC_LDS)>(v, tj, L, Ls);
+        passes_from<T, N, TPL, P + 1, SPLIT, SRC_LDS, DST_LDS>(v, tj, twl, L, Ls, store);
+    }
 }
 
-// Full length-N forward FFT of one line.  For N == 1 it is a copy.  When the
-// kernel loops over several line batches it must __syncthreads() between
-// batches (pass 0 writes LDS without a leading barrier).
-template <typename T, int N, int TWM = 1, bool SRC_LDS = false, bool DST_LDS = false, class Load,
-          class Store>
-FD void fft_line(const LdsLine<T>& L, int tj, const cpx<T>* __restrict__ tw, Load& load, Store& store)
+// Full length-N forward FFT of one line by TPL cooperating threads (thread
+// index tj < TPL), twiddles from the LDS table twl (staged beforehand).  SRC_LDS: the loader reads this workgroup's LDS, so no
+// LDS write may happen before every thread has loaded.  DST_LDS: the storer
+// writes LDS, so no store may happen before every thread has read its
+// inputs.  The loader is called for pass-0 inputs, the storer for the final
+// outputs (natural order).  For N == 1 it is a copy.
+template <typename T, int N, int TPL = radix_plan(N).tpl, bool SPLIT = false, bool SRC_LDS = false,
+          bool DST_LDS = false, class Load, class Store>
+FD void fft_line(const LdsView<cpx<T>>& L, const LdsView<T>& Ls, int tj, const cpx<T>* twl, Load& load,
+                 Store& store)
 {
     if constexpr (N == 1) {
         if (tj == 0) store(0, load(0));  // one slot per line, touched by one thread
     } else {
-        stockham_from<T, N, 0, TWM, SRC_LDS, DST_LDS>(L, tj, tw, load, store);
+        cpx<T> v[driver_ept<N, TPL>()];
+        load_first<T, N, TPL>(v, tj, load);
+        passes_from<T, N, TPL, 0, SPLIT, SRC_LDS, DST_LDS>(v, tj, twl, L, Ls, store);
     }
 }
 

@@ -92,6 +92,21 @@ constexpr int radix_ept(const RadixPlan& p)
     return e;
 }
 
+// Per-pass twiddle table: pass p (radix R, sub-length Ns > 1) stores, for each
+// k < Ns, the R roots W_n^(r * k * n / (Ns*R)), r = 0..R-1 (r = 0 is 1), so one
+// butterfly's roots are contiguous.  Offsets are in complex entries.
+constexpr int pass_table_offset(const RadixPlan& p, int pass)
+{
+    int off = 0;
+    for (int i = 1; i < pass; ++i) off += radix_ns(p, i) * p.r[i];
+    return off;
+}
+
+constexpr int pass_table_size(const RadixPlan& p)
+{
+    return p.np < 2 ? 0 : pass_table_offset(p, p.np);
+}
+
 inline bool length_supported(long long n)
 {
 #define FFT3D_LEN_CASE(L) case L:

@@ -9,42 +9,53 @@
 // lines element-major, line index fastest).  x-stage lines are contiguous, so
 // there the lanes walk along one line instead.  Every stage reads and writes
 // each element of the tile once.
+//
+// Variants: TDIV divides the threads per line (more butterflies per thread, so
+// more lines per workgroup and longer row segments); SPLIT halves the LDS tile
+// by exchanging real and imaginary parts one after the other.
 #include "device_fft.hpp"
 #include "kernels.hpp"
 #include "stage_args.hpp"
 
 namespace fft3d {
 
-template <typename T, int N>
+template <typename T, int N, int TDIV, bool SPLIT>
 __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
 {
-    constexpr int TPL = radix_plan(N).tpl;
+    constexpr int TPL = radix_plan(N).tpl / TDIV;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    T* ldsr = reinterpret_cast<T*>(smem_raw);
     const int t = threadIdx.x;
-    int lw, tj;
+    int tj;
     int64_t base;
     bool ok;
-    LdsLine<T> L;
+    LdsView<cpx<T>> L;
+    LdsView<T> Ls;
     if (a.strided) {
-        lw = t % a.lw;
+        const int lw = t % a.lw;
         tj = t / a.lw;
         const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
         ok = aa < a.A;
         base = a.off + aa + (int64_t)blockIdx.y * a.sb;
-        L = LdsLine<T>{lds + lw, a.lw};
+        L = LdsView<cpx<T>>{lds + lw, a.lw, 0};
+        Ls = LdsView<T>{ldsr + lw, a.lw, 0};
     } else {
         tj = t % TPL;
-        lw = t / TPL;
+        const int lw = t / TPL;
         const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
         ok = l < a.A * a.B;
         const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
         base = a.off + aa * a.sa + bb * a.sb;
-        L = LdsLine<T>{lds + lw * N, 1};
+        const int stride = N + a.pad * (N / 8);
+        L = LdsView<cpx<T>>{lds + lw * stride, 1, a.pad};
+        Ls = LdsView<T>{ldsr + lw * stride, 1, a.pad};
     }
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
+    const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * line * (SPLIT ? sizeof(T) : sizeof(cpx<T>))));
+    stage_pass_twiddles<T, N>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const int64_t se = a.se;
     const bool cj = a.conj != 0;
     const T scale = (T)a.scale;
@@ -56,25 +67,53 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
         if (cj) v = conj(v);
         if (ok) out[e * se] = v * scale;
     };
-    fft_line<T, N>(L, tj, tw, load, store);
+    fft_line<T, N, TPL, SPLIT>(L, Ls, tj, twl, load, store);
+}
+
+template <typename T, int N, int TDIV, bool SPLIT>
+static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
+{
+    constexpr int TPL = radix_plan(N).tpl / TDIV;
+    const int threads = a.lw * TPL;
+    const size_t elem = SPLIT ? sizeof(T) : sizeof(cpx<T>);
+    const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
+    const size_t lds = align16((size_t)a.lw * line * elem) + pass_table_bytes<T, N>();
+    dim3 grid;
+    if (a.strided) grid = dim3((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
+    else grid = dim3((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
+    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    (void)attr;
+    hipLaunchKernelGGL((k_c2c<T, N, TDIV, SPLIT>), grid, dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+// Lengths that also get the TDIV = 2, 4 and SPLIT variants.
+template <int N>
+constexpr bool has_variants()
+{
+    return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096;
 }
 
 template <typename T, int N>
 static hipError_t launch_c2c_n(const StageArgs& a, hipStream_t s)
 {
-    constexpr int TPL = radix_plan(N).tpl;
-    const int threads = a.lw * TPL;
-    const size_t lds = (size_t)a.lw * N * sizeof(cpx<T>);
-    dim3 grid;
-    if (a.strided) grid = dim3((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
-    else grid = dim3((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
-    if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_c2c<T, N>), hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)kMaxLdsBytes);
-    (void)attr;
-    hipLaunchKernelGGL((k_c2c<T, N>), grid, dim3(threads), lds, s, a);
-    return hipGetLastError();
+    const int tdiv = a.tdiv < 1 ? 1 : a.tdiv;
+    if (tdiv == 1 && !a.split) return launch_c2c_v<T, N, 1, false>(a, s);
+    if constexpr (has_variants<N>()) {
+        constexpr int tpl = radix_plan(N).tpl;
+        if (tdiv == 1) return launch_c2c_v<T, N, 1, true>(a, s);
+        if constexpr (tpl % 2 == 0) {
+            if (tdiv == 2) return a.split ? launch_c2c_v<T, N, 2, true>(a, s) : launch_c2c_v<T, N, 2, false>(a, s);
+        }
+        if constexpr (tpl % 4 == 0) {
+            if (tdiv == 4) return a.split ? launch_c2c_v<T, N, 4, true>(a, s) : launch_c2c_v<T, N, 4, false>(a, s);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -88,6 +127,15 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
         return hipErrorInvalidValue;
     }
 #undef FFT3D_C2C_CASE
+}
+
+bool c2c_variant_available(int n, int tdiv, int split)
+{
+    const bool var = n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096;
+    if (tdiv == 1 && !split) return length_supported(n);
+    if (!var) return false;
+    const int tpl = radix_plan(n).tpl;
+    return tdiv == 1 || (tdiv == 2 && tpl % 2 == 0) || (tdiv == 4 && tpl % 4 == 0);
 }
 
 }  // namespace fft3d

@@ -34,9 +34,12 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     const int64_t base = a.off + aa + (int64_t)blockIdx.y * a.sb;
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
     const int64_t se = a.se;
-    LdsLine<T> L{lds + lw, a.lw};
+    LdsView<cpx<T>> L{lds + lw, a.lw, 0};
+    LdsView<T> Ls{nullptr, 0, 0};
+    constexpr int TPL = radix_plan(N).tpl;
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * N * sizeof(cpx<T>)));
+    stage_pass_twiddles<T, N>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
 
     // wavenumbers of this line: kx from the half-spectrum column, ky from the row
     const T kx = (T)(a.kx0 + aa);
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
 
     auto load = [&](int e) -> cpx<T> { return ok ? in[e * se] : cpx<T>{(T)0, (T)0}; };
     auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
-    fft_line<T, N, 1, false, true>(L, tj, tw, load, store_lds);
+    fft_line<T, N, TPL, false, false, true>(L, Ls, tj, twl, load, store_lds);
     __syncthreads();
     // inverse transform of M .* Xhat as conj(F(conj(M .* Xhat))), M real
     auto load_mul = [&](int e) -> cpx<T> {
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     auto store = [&](int e, cpx<T> v) {
         if (ok) out[e * se] = conj(v);
     };
-    fft_line<T, N, 1, true, false>(L, tj, tw, load_mul, store);
+    fft_line<T, N, TPL, false, true, false>(L, Ls, tj, twl, load_mul, store);
 }
 
 template <typename T, int N>
@@ -66,7 +69,7 @@ static hipError_t launch_poisson_n(const StageArgs& a, hipStream_t s)
 {
     constexpr int TPL = radix_plan(N).tpl;
     const int threads = a.lw * TPL;
-    const size_t lds = (size_t)a.lw * N * sizeof(cpx<T>);
+    const size_t lds = align16((size_t)a.lw * N * sizeof(cpx<T>)) + pass_table_bytes<T, N>();
     const dim3 grid((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     static const hipError_t attr = hipFuncSetAttribute(

@@ -33,12 +33,14 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table
-    LdsLine<T> L{lds + lw * H, 1};
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table (pre/post-processing)
+    LdsView<cpx<T>> L{lds + lw * H, 1, 0};
+    LdsView<T> Ls{nullptr, 0, 0};
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * H * sizeof(cpx<T>)));
+    stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     auto load = [&](int e) -> cpx<T> { return ok ? in[e] : cpx<T>{(T)0, (T)0}; };
     auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
-    // W_H^m = W_N^(2m): the half-length passes read the length-N table at stride 2
-    fft_line<T, H, 2, false, true>(L, tj, tw, load, store_lds);
+    fft_line<T, H, TPL, false, false, true>(L, Ls, tj, twl, load, store_lds);
     __syncthreads();
     const T half = (T)0.5;
     const T wgt = a.weight ? (T)2 : (T)1;
@@ -69,8 +71,11 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table
-    LdsLine<T> L{lds + lw * (H + 1), 1};
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table (pre/post-processing)
+    LdsView<cpx<T>> L{lds + lw * (H + 1), 1, 0};
+    LdsView<T> Ls{nullptr, 0, 0};
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * (H + 1) * sizeof(cpx<T>)));
+    stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const T wgt = a.weight ? (T)0.5 : (T)1;
     for (int k = tj; k <= H; k += TPL) {
         cpx<T> v = ok ? in[k] : cpx<T>{(T)0, (T)0};
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     auto store = [&](int e, cpx<T> v) {
         if (ok) out[e] = conj(v) * scale;
     };
-    fft_line<T, H, 2, true, false>(L, tj, tw, load, store);
+    fft_line<T, H, TPL, false, true, false>(L, Ls, tj, twl, load, store);
 }
 
 template <typename T, int N>
@@ -102,7 +107,7 @@ static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
         constexpr int H = N / 2;
         constexpr int TPL = radix_plan(H).tpl;
         const int threads = a.lw * TPL;
-        const size_t lds = (size_t)a.lw * (H + 1) * sizeof(cpx<T>);
+        const size_t lds = align16((size_t)a.lw * (H + 1) * sizeof(cpx<T>)) + pass_table_bytes<T, H>();
         const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
         if (grid.x == 0) return hipSuccess;
         if (r2c) {

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 
+#include "fft_lengths.hpp"
 #include "stage_args.hpp"
 
 namespace fft3d {
@@ -213,6 +214,42 @@ void twiddles_f32(int64_t n, float* out)
     std::vector<double> d((size_t)(2 * n));
     twiddles_f64(n, d.data());
     for (int64_t i = 0; i < 2 * n; ++i) out[i] = (float)d[(size_t)i];
+}
+
+}  // namespace fft3d
+
+namespace fft3d {
+
+int64_t pass_twiddles_f64(int64_t n, double* out)
+{
+    if (!length_supported(n)) return -1;
+    const RadixPlan rp = radix_plan((int)n);
+    const int64_t total = pass_table_size(rp);
+    if (!out || total == 0) return total;
+    std::vector<double> w((size_t)(2 * n));
+    twiddles_f64(n, w.data());
+    for (int p = 1; p < rp.np; ++p) {
+        const int R = rp.r[p], ns = radix_ns(rp, p), step = (int)n / (ns * R);
+        const int off = pass_table_offset(rp, p);
+        for (int k = 0; k < ns; ++k) {
+            for (int r = 0; r < R; ++r) {
+                const int64_t m = ((int64_t)r * k * step) % n;
+                out[2 * (off + k * R + r)] = w[(size_t)(2 * m)];
+                out[2 * (off + k * R + r) + 1] = w[(size_t)(2 * m + 1)];
+            }
+        }
+    }
+    return total;
+}
+
+int64_t pass_twiddles_f32(int64_t n, float* out)
+{
+    const int64_t total = pass_twiddles_f64(n, nullptr);
+    if (!out || total <= 0) return total;
+    std::vector<double> d((size_t)(2 * total));
+    pass_twiddles_f64(n, d.data());
+    for (int64_t i = 0; i < 2 * total; ++i) out[i] = (float)d[(size_t)i];
+    return total;
 }
 
 }  // namespace fft3d

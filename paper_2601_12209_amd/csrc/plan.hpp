@@ -83,4 +83,10 @@ void place_tasks(Pipeline& p, int nstreams);
 void twiddles_f64(int64_t n, double* out);
 void twiddles_f32(int64_t n, float* out);  // round-to-nearest-even of the f64 table
 
+// Per-pass table of the length-n Stockham kernel (layout in fft_lengths.hpp),
+// built from the same FP64 roots (entries are copies of table values).
+// Returns the number of complex entries; writes them if out is non-null.
+int64_t pass_twiddles_f64(int64_t n, double* out);
+int64_t pass_twiddles_f32(int64_t n, float* out);
+
 }  // namespace fft3d

@@ -42,6 +42,14 @@ constexpr int kDefaultStreams = 4;
 
 }  // namespace
 
+// Launch shape of one stage kernel.
+struct KConf {
+    int lw = 0;      // lines per workgroup (0: use the default shape)
+    int tdiv = 1;    // threads-per-line divisor
+    int split = 0;   // split re/im LDS exchange
+    int pad = 0;     // padded contiguous LDS lines
+};
+
 struct fft3d_plan_s {
     PlanDesc d{};
     int device = 0;
@@ -49,14 +57,19 @@ struct fft3d_plan_s {
     std::vector<hipStream_t> streams;  // kMaxStreams, created up front
     std::vector<hipEvent_t> events;    // one per task of the largest pipeline
     hipEvent_t fork = nullptr;
-    void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis forward root tables
+    void* tw[3] = {nullptr, nullptr, nullptr};   // per-axis forward root tables
+    void* twp[3] = {nullptr, nullptr, nullptr};  // per-axis per-pass tables of the kernel length
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = false;
     Pipeline pipes[OP_COUNT];
     bool pipe_ok[OP_COUNT] = {};
     std::vector<char> needs_event[OP_COUNT];
-    int lw_override[3] = {0, 0, 0};
+    KConf conf_override[3];  // per axis; lw == 0: default
+    // per-stage timing (tracing): events around every stage of the last call
+    bool timing = false;
+    std::vector<hipEvent_t> tev;  // 6 timing events (up to 5 stages)
+    int timed_stages = 0;
 };
 
 namespace {
@@ -70,27 +83,61 @@ int64_t next_pow2(int64_t v)
     return p;
 }
 
-// Lines per workgroup.  Strided stages (y, z): enough neighbouring lines that
-// one row segment is >= 128 bytes and a workgroup holds >= 256 threads, within
-// 1024 threads and 64 KiB of LDS.  Contiguous stages (x): ~256 threads.
-int default_lw(const PlanDesc& d, const Stage& st, const Box& b)
+int kernel_length(const Stage& st)
 {
     const bool real = st.kind == K_R2C_X || st.kind == K_C2R_X;
-    const int nk = real ? st.n / 2 : st.n;
+    return real ? st.n / 2 : st.n;
+}
+
+// Threads and LDS bytes a configuration needs, or false if it cannot run.
+bool conf_fits(const Stage& st, int dtype, const KConf& c, bool strided)
+{
+    const int nk = kernel_length(st);
+    const RadixPlan rp = radix_plan(nk);
+    if (c.lw < 1 || c.tdiv < 1 || rp.tpl % c.tdiv != 0) return false;
+    if (st.kind != K_C2C && (c.tdiv != 1 || c.split || c.pad)) return false;
+    if (st.kind == K_C2C && !c2c_variant_available(nk, c.tdiv, c.split)) return false;
+    const int threads = c.lw * (rp.tpl / c.tdiv);
+    const size_t s = elem_bytes(dtype) / (c.split ? 2 : 1);
+    const size_t line = strided ? (size_t)nk : (size_t)(nk + 1 + (c.pad ? nk / 8 : 0));
+    const size_t tw = (size_t)pass_table_size(rp) * elem_bytes(dtype) + 16;
+    return threads <= 1024 && (size_t)c.lw * line * s + tw <= kMaxLdsBytes;
+}
+
+// Default launch shape.  Strided stages (y, z): enough neighbouring lines that
+// one row segment is 256 bytes (32 complex64 or 16 complex128 values), the
+// threads per line halved if the workgroup would exceed 1024 threads; LDS up
+// to 128 KiB.  Contiguous stages (x): ~256 threads, padded LDS lines.
+KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
+{
+    const int nk = kernel_length(st);
     const int tpl = radix_plan(nk).tpl;
     const size_t s = elem_bytes(d.dtype);
-    const size_t lds_cap = 64 * 1024;
+    const size_t twb = (size_t)pass_table_size(radix_plan(nk)) * s + 16;
+    KConf c;
     if (st.axis != 0) {
-        int lw = d.dtype == DT_F64 ? 8 : 16;
+        const size_t lds_cap = 128 * 1024 + twb;
+        int lw = d.dtype == DT_F64 ? 16 : 32;
         while (lw * tpl < 256 && lw < 64) lw *= 2;
         const int64_t a = b.hi[0] - b.lo[0];
         lw = (int)std::min<int64_t>(lw, next_pow2(a));
-        while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * nk * s > lds_cap)) lw /= 2;
-        return lw;
+        int tdiv = 1;
+        while (lw * (tpl / tdiv) > 1024 && st.kind == K_C2C && tdiv < 4 && tpl % (2 * tdiv) == 0 &&
+               c2c_variant_available(nk, 2 * tdiv, 0))
+            tdiv *= 2;
+        while (lw > 1 && (lw * (tpl / tdiv) > 1024 || (size_t)lw * nk * s + twb > lds_cap)) lw /= 2;
+        c.lw = lw;
+        c.tdiv = tdiv;
+    } else {
+        const size_t lds_cap = 64 * 1024;
+        int lw = std::max(1, 256 / tpl);
+        while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * (nk + 1 + nk / 8) * s + twb > lds_cap)) lw /= 2;
+        c.lw = lw;
+        c.pad = st.kind == K_C2C ? 1 : 0;
     }
-    int lw = std::max(1, 256 / tpl);
-    while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * (nk + 1) * s > lds_cap)) lw /= 2;
-    return lw;
+    // the hard limits (1024 threads, 160 KiB of LDS) always hold
+    while (c.lw > 1 && !conf_fits(st, d.dtype, c, st.axis != 0)) c.lw /= 2;
+    return c;
 }
 
 StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* const bufs[3])
@@ -103,6 +150,7 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.in = bufs[st.src];
     a.out = bufs[st.dst];
     a.tw = p->tw[st.axis];
+    a.twp = p->twp[st.axis];
     a.conj = st.conj;
     a.weight = st.weight;
     a.scale = st.scale;
@@ -143,8 +191,16 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
         a.kx0 = b.lo[0];
         a.ky0 = b.lo[1];
     }
-    const int ov = p->lw_override[st.axis];
-    a.lw = ov > 0 ? ov : default_lw(d, st, b);
+    KConf c = default_conf(d, st, b);
+    const KConf& ov = p->conf_override[st.axis];
+    if (ov.lw > 0) {
+        KConf o = ov;
+        if (conf_fits(st, d.dtype, o, st.axis != 0)) c = o;
+    }
+    a.lw = c.lw;
+    a.tdiv = c.tdiv;
+    a.split = c.split;
+    a.pad = c.pad;
     return a;
 }
 
@@ -203,6 +259,49 @@ const Pipeline& get_pipeline(fft3d_plan_s* p, int op)
     return p->pipes[op];
 }
 
+// Timed issue: every stage is its own fork/join region on the caller's stream,
+// with a timing event after it, so stage durations can be read back.
+fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipStream_t user)
+{
+    hipError_t e = hipEventRecord(p->tev[0], user);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
+    size_t i = 0;
+    for (int st = 0; st < (int)pl.stages.size(); ++st) {
+        const bool fork = p->nstreams > 1;
+        if (fork) {
+            e = hipEventRecord(p->fork, user);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
+        }
+        std::vector<char> used(p->nstreams, 0);
+        std::vector<int> last(p->nstreams, -1);
+        for (; i < pl.tasks.size() && pl.tasks[i].stage == st; ++i) {
+            const Task& t = pl.tasks[i];
+            hipStream_t s = fork ? p->streams[t.stream] : user;
+            if (fork && !used[t.stream]) {
+                e = hipStreamWaitEvent(s, p->fork, 0);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
+                used[t.stream] = 1;
+            }
+            const Stage& sg = pl.stages[t.stage];
+            e = launch_task(p, sg, make_args(p, sg, t.box, bufs), s);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+            last[t.stream] = (int)i;
+        }
+        if (fork) {
+            for (int s = 0; s < p->nstreams; ++s) {
+                if (last[s] < 0) continue;
+                e = hipEventRecord(p->events[last[s]], p->streams[s]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(user, p->events[last[s]], 0);
+                if (e != hipSuccess) return hip_fail(e, "stage join");
+            }
+        }
+        e = hipEventRecord(p->tev[st + 1], user);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
+    }
+    p->timed_stages = (int)pl.stages.size();
+    return FFT3D_OK;
+}
+
 fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* stream)
 {
     const Pipeline& pl = get_pipeline(p, op);
@@ -211,6 +310,7 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
     void* bufs[3] = {const_cast<void*>(in), out, p->ws};
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (p->timing) return run_timed(p, pl, bufs, user);
     if (p->nstreams == 1) {
         for (const Task& t : pl.tasks) {
             const Stage& st = pl.stages[t.stage];
@@ -262,8 +362,12 @@ void release(fft3d_plan_s* p)
         }
     for (hipEvent_t ev : p->events)
         if (ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : p->tev)
+        if (ev) hipEventDestroy(ev);
     if (p->fork) hipEventDestroy(p->fork);
     for (void* t : p->tw)
+        if (t) hipFree(t);
+    for (void* t : p->twp)
         if (t) hipFree(t);
     if (p->ws && p->ws_owned) hipFree(p->ws);
     delete p;
@@ -307,6 +411,19 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         else twiddles_f32(n, (float*)host.data());
         e = hipMalloc(&p->tw[ax], bytes);
         if (e == hipSuccess) e = hipMemcpy(p->tw[ax], host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            release(p);
+            return hip_fail(e, "twiddle upload");
+        }
+        // per-pass table of the FFT length the axis kernels run (half of nx for r2c x)
+        const int64_t nk = (r2c && ax == 0) ? n / 2 : n;
+        const int64_t entries = std::max<int64_t>(1, pass_twiddles_f64(nk, nullptr));
+        const size_t pbytes = (size_t)entries * elem_bytes(dtype);
+        std::vector<char> phost(pbytes, 0);
+        if (dtype == DT_F64) pass_twiddles_f64(nk, (double*)phost.data());
+        else pass_twiddles_f32(nk, (float*)phost.data());
+        e = hipMalloc(&p->twp[ax], pbytes);
+        if (e == hipSuccess) e = hipMemcpy(p->twp[ax], phost.data(), pbytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             release(p);
             return hip_fail(e, "twiddle upload");
@@ -458,20 +575,74 @@ fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
     return FFT3D_OK;
 }
 
-fft3d_status fft3d_set_lines_per_block(fft3d_plan_t p, int axis, int lw)
+fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, int split, int pad)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    if (axis < 0 || axis > 2 || lw < 0 || lw > 1024 || (lw & (lw - 1)) != 0)
-        return fail(FFT3D_ERR_INVALID_ARG, "axis 0..2 and lw a power of two (0 = default)");
-    // the kernel must fit: threads and LDS
-    const bool real = p->d.r2c && axis == 0;
-    const int64_t lens[3] = {p->d.nx, p->d.ny, p->d.nz};
-    const int nk = (int)(real ? lens[axis] / 2 : lens[axis]);
-    const int tpl = radix_plan(nk).tpl;
-    if (lw > 0 && ((int64_t)lw * tpl > 1024 || (size_t)lw * (nk + 1) * elem_bytes(p->d.dtype) > kMaxLdsBytes))
-        return fail(FFT3D_ERR_INVALID_ARG, "lines per block exceed 1024 threads or the LDS limit");
-    p->lw_override[axis] = lw;
+    if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
+    if (lw == 0) {
+        p->conf_override[axis] = KConf();
+        return FFT3D_OK;
+    }
+    KConf c;
+    c.lw = lw;
+    c.tdiv = tdiv;
+    c.split = split;
+    c.pad = pad;
+    if (lw < 1 || lw > 1024 || (lw & (lw - 1)) != 0 || tdiv < 1 || split < 0 || split > 1 || pad < 0 || pad > 1)
+        return fail(FFT3D_ERR_INVALID_ARG, "lw a power of two <= 1024, tdiv >= 1, split and pad 0 or 1");
+    // every stage kernel of this axis in every operation must accept the shape
+    for (int op = 0; op < OP_COUNT; ++op) {
+        for (const Stage& st : op_stages(p->d, op)) {
+            if (st.axis == axis && !conf_fits(st, p->d.dtype, c, axis != 0))
+                return fail(FFT3D_ERR_INVALID_ARG, "shape does not fit a stage kernel of this axis "
+                                                   "(threads, LDS, or no such kernel variant)");
+        }
+    }
+    p->conf_override[axis] = c;
     return FFT3D_OK;
+}
+
+fft3d_status fft3d_set_timing(fft3d_plan_t p, int enable)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (enable && p->tev.empty()) {
+        p->tev.assign(6, nullptr);
+        for (auto& ev : p->tev) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) {
+                ev = nullptr;
+                return hip_fail(e, "hipEventCreate(timing)");
+            }
+        }
+    }
+    p->timing = enable != 0;
+    p->timed_stages = 0;
+    return FFT3D_OK;
+}
+
+int fft3d_stage_times(fft3d_plan_t p, float* ms, int cap)
+{
+    if (!p || !ms || p->timed_stages == 0) {
+        fail(FFT3D_ERR_INVALID_ARG, "no timed call recorded");
+        return -1;
+    }
+    if (cap < p->timed_stages) {
+        fail(FFT3D_ERR_INVALID_ARG, "cap smaller than the number of stages");
+        return -1;
+    }
+    hipError_t e = hipEventSynchronize(p->tev[p->timed_stages]);
+    if (e != hipSuccess) {
+        hip_fail(e, "hipEventSynchronize");
+        return -1;
+    }
+    for (int i = 0; i < p->timed_stages; ++i) {
+        e = hipEventElapsedTime(&ms[i], p->tev[i], p->tev[i + 1]);
+        if (e != hipSuccess) {
+            hip_fail(e, "hipEventElapsedTime");
+            return -1;
+        }
+    }
+    return p->timed_stages;
 }
 
 const char* fft3d_status_string(int status)

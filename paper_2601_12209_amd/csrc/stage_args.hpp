@@ -22,12 +22,16 @@ enum DType : int { DT_F32 = 0, DT_F64 = 1 };
 struct StageArgs {
     const void* in;
     void* out;
-    const void* tw;  // forward roots W_n^m = exp(-2 pi i m/n), m < n, n = kernel length
+    const void* tw;   // forward roots W_n^m = exp(-2 pi i m/n), m < n, n = axis length
+    const void* twp;  // per-pass twiddle table of the kernel's FFT length
     int64_t A, B;
     int64_t off, sa, sb, se;
     int64_t off_o, sa_o, sb_o;
     int strided;  // 1: lanes of a wavefront walk neighbouring lines (requires sa == 1)
     int lw;       // lines per workgroup
+    int tdiv;     // threads per line = (default threads per line) / tdiv
+    int split;    // 1: exchange real and imaginary parts through LDS separately
+    int pad;      // 1: pad contiguous LDS lines by one slot per 8 elements
     int conj;     // 1: conjugate-sign transform, taken as conj(F(conj x))
     int weight;   // R2C: interior bins x2 / C2R: interior bins x1/2 (adjoint paths)
     double scale; // multiplies every output

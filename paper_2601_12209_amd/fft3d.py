@@ -138,9 +138,22 @@ class Plan:
     def set_streams(self, n: int):
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
 
-    def set_lines_per_block(self, axis: int, lw: int):
-        check(_lib.lib().fft3d_set_lines_per_block(self._h, int(axis), int(lw)),
-              "fft3d_set_lines_per_block")
+    def set_stage_config(self, axis: int, lw: int, tdiv: int = 1, split: int = 0, pad: int = 0):
+        """Launch shape of the stage kernels along one axis (lw = 0: default)."""
+        check(_lib.lib().fft3d_set_stage_config(self._h, int(axis), int(lw), int(tdiv), int(split),
+                                                int(pad)), "fft3d_set_stage_config")
+
+    def set_timing(self, enable: bool = True):
+        """Record a HIP event after every stage of each call (stages then run one after another)."""
+        check(_lib.lib().fft3d_set_timing(self._h, int(bool(enable))), "fft3d_set_timing")
+
+    def stage_times(self):
+        """Milliseconds of each stage of the most recent timed call (waits for it)."""
+        buf = (ctypes.c_float * 8)()
+        k = _lib.lib().fft3d_stage_times(self._h, buf, 8)
+        if k < 0:
+            raise RuntimeError("fft3d_stage_times: " + _lib.lib().fft3d_last_error().decode())
+        return list(buf[:k])
 
     def workspace_bytes(self) -> int:
         return int(_lib.lib().fft3d_workspace_bytes(self._h))

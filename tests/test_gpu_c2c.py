@@ -125,3 +125,37 @@ def test_alias_and_argument_errors(gpu_lib):
     with pytest.raises(Fft3dError):  # partial overlap
         plan.forward(buf[:512].view(8, 8, 8), out=buf[256:768].view(8, 8, 8))
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape", [(64, 64, 512), (512, 16, 64), (16, 512, 32), (8, 256, 256), (32, 1024, 8)])
+def test_kernel_shape_variants_bitwise(gpu_lib, shape, dtype):
+    """Launch shapes (lines per block, threads per line, split exchange, padding) reorder
+    no arithmetic: every accepted shape gives the default shape's bits."""
+    a = synth.complex_normal(shape, 9)
+    x = to_dev(a, dtype)
+    base = gpu_lib.Plan(shape, dtype)
+    ref = base.forward(x).clone()
+    torch.cuda.synchronize()
+    assert rel(to_host(ref), oracle.fftn(promoted(a, dtype))) <= bound(dtype, a.size)
+    base.close()
+    from paper_2601_12209_amd._lib import Fft3dError
+
+    tried = 0
+    for axis in (0, 1, 2):
+        for lw in (1, 2, 4, 8, 16, 32, 64):
+            for tdiv in (1, 2, 4):
+                for split in (0, 1):
+                    for pad in ((0, 1) if axis == 0 else (0,)):
+                        plan = gpu_lib.Plan(shape, dtype)
+                        try:
+                            plan.set_stage_config(axis, lw, tdiv, split, pad)
+                        except Fft3dError:
+                            plan.close()
+                            continue
+                        y = plan.forward(x)
+                        torch.cuda.synchronize()
+                        assert torch.equal(y, ref), (axis, lw, tdiv, split, pad)
+                        tried += 1
+                        plan.close()
+    assert tried > 10

@@ -1,0 +1,95 @@
+"""GPU parity of the real-to-complex / complex-to-real pencil 3D FFT.
+
+R2C keeps kx = 0..nx/2 of the forward DFT (Hermitian symmetry); C2R is its
+inverse along z, y and then x, ignoring the imaginary parts of the kx = 0 and
+kx = nx/2 bins.  Compared element by element with the FP64 oracle on the same
+(precision-rounded) inputs.  The R2C adjoint is checked against its defining
+identity Re<G, rfftn(f)> = <f, backward(G)> and against the oracle composition.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _util import bound, promoted, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+REAL = [torch.float32, torch.float64]
+CPLX = {torch.float32: torch.complex64, torch.float64: torch.complex128}
+
+CASES = [
+    ((8, 8, 8), (1, 1)),
+    ((32, 32, 32), (2, 2)),
+    ((16, 12, 20), (2, 3)),
+    ((5, 6, 4), (2, 2)),
+    ((1, 1, 2), (1, 1)),
+    ((3, 4, 2), (1, 1)),
+    ((64, 48, 100), (3, 3)),
+    ((40, 30, 96), (4, 4)),
+    ((8, 16, 512), (1, 1)),
+    ((4, 4, 1024), (1, 1)),
+    ((2, 3, 2048), (1, 1)),
+]
+
+
+@pytest.mark.parametrize("dtype", REAL, ids=["f32", "f64"])
+@pytest.mark.parametrize("shape,grid", CASES, ids=[f"{s}-{g}" for s, g in CASES])
+def test_r2c_c2r(gpu_lib, shape, grid, dtype):
+    print(f"case shape={shape} grid={grid} dtype={dtype}", flush=True)
+    nz, ny, nx = shape
+    f = synth.real_normal(shape, 200 + sum(shape))
+    f_in = promoted(f, dtype)
+    n = f.size
+    plan = gpu_lib.Plan(shape, dtype, grid, r2c=True)
+    x = to_dev(f, dtype)
+    H = plan.forward(x)
+    torch.cuda.synchronize()
+    assert rel(to_host(H), oracle.rfftn(f_in)) <= bound(dtype, n)
+    # inverse of a consistent half spectrum, and of an arbitrary one
+    h_cons = oracle.rfftn(f_in)
+    h_rand = synth.complex_normal((nz, ny, nx // 2 + 1), 300 + sum(shape))
+    for h in (h_cons, h_rand):
+        h_in = promoted(h, CPLX[dtype])
+        hd = to_dev(h, CPLX[dtype])
+        y = plan.inverse(hd)
+        torch.cuda.synchronize()
+        assert rel(to_host(y), oracle.irfftn(h_in, nx)) <= bound(dtype, n)
+        assert torch.equal(hd, to_dev(h, CPLX[dtype]))  # input half spectrum left intact
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", REAL, ids=["f32", "f64"])
+@pytest.mark.parametrize("shape,grid", [((8, 6, 10), (2, 2)), ((16, 32, 64), (1, 1)), ((15, 10, 12), (3, 2))])
+def test_r2c_backward_is_adjoint(gpu_lib, shape, grid, dtype):
+    nz, ny, nx = shape
+    f = synth.real_normal(shape, 11)
+    G = synth.complex_normal((nz, ny, nx // 2 + 1), 12)
+    plan = gpu_lib.Plan(shape, dtype, grid, r2c=True)
+    g = plan.backward(to_dev(G, CPLX[dtype]))
+    torch.cuda.synchronize()
+    g = to_host(g).astype(np.float64)
+    G_in = promoted(G, CPLX[dtype])
+    lhs = np.vdot(G_in, oracle.rfftn(f)).real  # Re <G, rfftn f>
+    rhs = float(np.dot(f.ravel(), g.ravel()))
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert abs(lhs - rhs) <= tol * (abs(lhs) + np.linalg.norm(f) * np.linalg.norm(g))
+    # the same operator written with oracle pieces: unscaled c2r of G with interior bins halved
+    Gh = G_in.copy()
+    Gh[:, :, 1:(nx + 1) // 2] *= 0.5
+    assert rel(g, oracle.irfftn(Gh, nx, scale=False)) <= bound(dtype, f.size)
+    plan.close()
+
+
+def test_r2c_errors(gpu_lib):
+    from paper_2601_12209_amd._lib import Fft3dError
+
+    with pytest.raises(Fft3dError):
+        gpu_lib.Plan((4, 4, 5), torch.float32, r2c=True)  # odd nx
+    plan = gpu_lib.Plan((4, 4, 8), torch.float32, r2c=True)
+    buf = torch.zeros(4 * 4 * 5 * 2, dtype=torch.complex64, device="cuda")
+    real_view = buf.view(torch.float32)[: 4 * 4 * 8].view(4, 4, 8)
+    with pytest.raises(Fft3dError):  # out overlaps in
+        plan.forward(real_view, out=buf[:80].view(4, 4, 5))
+    plan.close()
