@@ -24,6 +24,37 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_c2c_512cubed.json")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the library sources (kernels and launch shapes); a counter record is
+    valid only for the sources it was taken with."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_12209_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+                    + glob.glob(os.path.join(csrc, "*.cpp"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n_edge):
+    """HBM bytes per launch of the dominant stage kernel from the committed
+    rocprofv3 counter record, or None if it is absent or the kernels changed."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("n_edge") != n_edge:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 DEFAULT_GRID = (1, 1)
 DEFAULT_STREAMS = 1
 
@@ -149,7 +180,7 @@ def main():
     achieved = bytes_per_launch / (dom["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": f"stage {dom_name} (k_c2c<float, {n_edge}>)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n_edge),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
     whole_frac = 6 * 2.0 * 8 * N / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
 

@@ -184,7 +184,11 @@ fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out);
  * 4 Poisson adjoint) for the given plan parameters and stream count, written
  * as int64 records:
  *   header: [ntasks, nstages]
- *   per stage: [kind, axis, n, conj, weight, src, dst]
+ *   per stage: [kind, axis, n, conj, weight, src, dst, scale]
+ *     kind 0 C2C, 1 R2C along x, 2 C2R along x, 3 fused Poisson z stage;
+ *     axis 0..2; n the line length; conj 1 for the sign +1 transform; weight 1
+ *     for the adjoint bin weighting; src/dst 0 = in, 1 = out, 2 = workspace;
+ *     scale the output factor as the bit pattern of an IEEE double
  *   per task:  [stage, x0, x1, y0, y1, z0, z1, stream, ndeps, deps..., nwaits, waits...]
  * Boxes are half-open ranges over the complex array.  Returns the number of
  * int64 values needed; writes them only if cap is large enough.  Negative on

@@ -171,8 +171,48 @@ Pipeline build_pipeline(const PlanDesc& d, int op, int nstreams)
         prev_begin = begin;
         prev_end = (int)p.tasks.size();
     }
+    issue_order(p);
     place_tasks(p, nstreams);
     return p;
+}
+
+void issue_order(Pipeline& p)
+{
+    // Immediate dispatch (the paper's data-dependency queue, Sec. IV-D): a
+    // tile is issued as soon as its producers are, deeper stages first.  A
+    // consumer then runs right after the tiles that wrote its input, while
+    // that data is still in the GPU's caches.
+    const int n = (int)p.tasks.size();
+    std::vector<int> missing(n, 0);
+    std::vector<std::vector<int>> users(n);
+    for (int i = 0; i < n; ++i) {
+        missing[i] = (int)p.tasks[i].deps.size();
+        for (int d : p.tasks[i].deps) users[d].push_back(i);
+    }
+    std::vector<char> ready(n, 0), done(n, 0);
+    for (int i = 0; i < n; ++i) ready[i] = missing[i] == 0;
+    std::vector<int> order;
+    order.reserve(n);
+    for (int step = 0; step < n; ++step) {
+        int best = -1;
+        for (int i = 0; i < n; ++i) {
+            if (!ready[i] || done[i]) continue;
+            if (best < 0 || p.tasks[i].stage > p.tasks[best].stage) best = i;
+        }
+        done[best] = 1;
+        order.push_back(best);
+        for (int u : users[best])
+            if (--missing[u] == 0) ready[u] = 1;
+    }
+    std::vector<int> pos(n);
+    for (int k = 0; k < n; ++k) pos[order[k]] = k;
+    std::vector<Task> re(n);
+    for (int k = 0; k < n; ++k) {
+        re[k] = p.tasks[order[k]];
+        for (int& d : re[k].deps) d = pos[d];
+        std::sort(re[k].deps.begin(), re[k].deps.end());
+    }
+    p.tasks.swap(re);
 }
 
 // cos and sin of (pi/2) * num / n for 0 <= num <= n, evaluated on an angle

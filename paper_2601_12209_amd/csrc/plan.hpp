@@ -56,7 +56,7 @@ struct Task {
 
 struct Pipeline {
     std::vector<Stage> stages;
-    std::vector<Task> tasks;  // stage by stage: a topological order
+    std::vector<Task> tasks;  // issue order: a topological order (see issue_order)
     int nstreams = 1;
 };
 
@@ -73,6 +73,10 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op);
 
 // Full task graph of an operation placed on nstreams streams.
 Pipeline build_pipeline(const PlanDesc& d, int op, int nstreams);
+
+// Reorder tasks for immediate dispatch: each tile right after its producers,
+// deeper stages first (a topological order).
+void issue_order(Pipeline& p);
 
 // Locality-aware placement (paper Alg. 3 on one device): each tile goes to
 // the least-loaded stream, ties broken by the number of its producers already

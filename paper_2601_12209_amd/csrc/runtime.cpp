@@ -104,36 +104,36 @@ bool conf_fits(const Stage& st, int dtype, const KConf& c, bool strided)
     return threads <= 1024 && (size_t)c.lw * line * s + tw <= kMaxLdsBytes;
 }
 
-// Default launch shape.  Strided stages (y, z): enough neighbouring lines that
-// one row segment is 256 bytes (32 complex64 or 16 complex128 values), the
-// threads per line halved if the workgroup would exceed 1024 threads; LDS up
-// to 128 KiB.  Contiguous stages (x): ~256 threads, padded LDS lines.
+// Default launch shape (chosen from measured sweeps on MI355X at 512^3).
+// Strided stages (y, z): 16 neighbouring lines per workgroup (128-byte row
+// segments for complex64, 256 for complex128), more for short lines so a
+// workgroup has >= 256 threads, threads per line divided down to fit 1024,
+// split re/im exchange (half the LDS).  Contiguous stages (x): ~128 threads,
+// split exchange and padded LDS lines.
 KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
 {
     const int nk = kernel_length(st);
     const int tpl = radix_plan(nk).tpl;
-    const size_t s = elem_bytes(d.dtype);
-    const size_t twb = (size_t)pass_table_size(radix_plan(nk)) * s + 16;
     KConf c;
+    const bool c2c = st.kind == K_C2C;
     if (st.axis != 0) {
-        const size_t lds_cap = 128 * 1024 + twb;
-        int lw = d.dtype == DT_F64 ? 16 : 32;
+        int lw = 16;
         while (lw * tpl < 256 && lw < 64) lw *= 2;
         const int64_t a = b.hi[0] - b.lo[0];
         lw = (int)std::min<int64_t>(lw, next_pow2(a));
         int tdiv = 1;
-        while (lw * (tpl / tdiv) > 1024 && st.kind == K_C2C && tdiv < 4 && tpl % (2 * tdiv) == 0 &&
-               c2c_variant_available(nk, 2 * tdiv, 0))
+        while (c2c && lw * (tpl / tdiv) > 1024 && tdiv < 4 && tpl % (2 * tdiv) == 0 &&
+               c2c_variant_available(nk, 2 * tdiv, 1))
             tdiv *= 2;
-        while (lw > 1 && (lw * (tpl / tdiv) > 1024 || (size_t)lw * nk * s + twb > lds_cap)) lw /= 2;
         c.lw = lw;
         c.tdiv = tdiv;
+        c.split = c2c && c2c_variant_available(nk, tdiv, 1) ? 1 : 0;
     } else {
-        const size_t lds_cap = 64 * 1024;
-        int lw = std::max(1, 256 / tpl);
-        while (lw > 1 && (lw * tpl > 1024 || (size_t)lw * (nk + 1 + nk / 8) * s + twb > lds_cap)) lw /= 2;
+        int lw = 1;
+        while (2 * lw * tpl <= 128) lw *= 2;
         c.lw = lw;
-        c.pad = st.kind == K_C2C ? 1 : 0;
+        c.split = c2c && c2c_variant_available(nk, 1, 1) ? 1 : 0;
+        c.pad = c2c ? 1 : 0;
     }
     // the hard limits (1024 threads, 160 KiB of LDS) always hold
     while (c.lw > 1 && !conf_fits(st, d.dtype, c, st.axis != 0)) c.lw /= 2;
@@ -265,7 +265,6 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
 {
     hipError_t e = hipEventRecord(p->tev[0], user);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
-    size_t i = 0;
     for (int st = 0; st < (int)pl.stages.size(); ++st) {
         const bool fork = p->nstreams > 1;
         if (fork) {
@@ -274,8 +273,9 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
         }
         std::vector<char> used(p->nstreams, 0);
         std::vector<int> last(p->nstreams, -1);
-        for (; i < pl.tasks.size() && pl.tasks[i].stage == st; ++i) {
+        for (size_t i = 0; i < pl.tasks.size(); ++i) {
             const Task& t = pl.tasks[i];
+            if (t.stage != st) continue;
             hipStream_t s = fork ? p->streams[t.stream] : user;
             if (fork && !used[t.stream]) {
                 e = hipStreamWaitEvent(s, p->fork, 0);
@@ -696,8 +696,10 @@ int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2,
     v.push_back((int64_t)pl.tasks.size());
     v.push_back((int64_t)pl.stages.size());
     for (const Stage& s : pl.stages) {
-        int64_t rec[7] = {s.kind, s.axis, s.n, s.conj, s.weight, s.src, s.dst};
-        v.insert(v.end(), rec, rec + 7);
+        int64_t scale_bits;
+        memcpy(&scale_bits, &s.scale, sizeof scale_bits);
+        int64_t rec[8] = {s.kind, s.axis, s.n, s.conj, s.weight, s.src, s.dst, scale_bits};
+        v.insert(v.end(), rec, rec + 8);
     }
     for (const Task& t : pl.tasks) {
         v.push_back(t.stage);

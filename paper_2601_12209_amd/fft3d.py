@@ -278,9 +278,11 @@ def query_pipeline(shape, grid, r2c=False, op=0, nstreams=4):
     pos = 2
     stages = []
     for _ in range(nstages):
-        kind, axis, n, conj, weight, src, dst = v[pos:pos + 7]
-        stages.append(dict(kind=kind, axis=axis, n=n, conj=conj, weight=weight, src=src, dst=dst))
-        pos += 7
+        kind, axis, n, conj, weight, src, dst, sbits = v[pos:pos + 8]
+        scale = float(np.array([sbits], dtype=np.int64).view(np.float64)[0])
+        stages.append(dict(kind=kind, axis=axis, n=n, conj=conj, weight=weight, src=src, dst=dst,
+                           scale=scale))
+        pos += 8
     tasks = []
     for _ in range(ntasks):
         stage = v[pos]

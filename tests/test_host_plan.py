@@ -1,0 +1,291 @@
+"""Host-side checks of the library (no GPU): exported C ABI, radix plans,
+twiddle tables, pencil tiles, the tile dependency graph, stream placement and
+its event waits, and a CPU simulation of the task graph.
+
+The simulator executes the library's own task graph (as returned by
+fft3d_query_pipeline) tile by tile, in random orders that respect only the
+stream order and the event waits the library would issue, applying the
+oracle's 1D DFT to every line of each tile.  A missing dependency edge, a
+wrong stage kind, sign, scale or bin weighting makes its result differ from
+the oracle's 3D transform.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fft3d.h")
+
+
+@pytest.fixture(scope="module")
+def fft3d():
+    from paper_2601_12209_amd import _lib, build
+
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build(verbose=False)
+    from paper_2601_12209_amd import fft3d as mod
+
+    mod.load()
+    return mod
+
+
+def test_header_symbols_exported(fft3d):
+    names = re.findall(r"^\s*[a-z_0-9 \*]+?\b(fft3d_[a-z_0-9]+)\s*\(", open(HEADER).read(), re.M)
+    assert len(set(names)) >= 18
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2601_12209_amd", "libfft3d.so"))
+    for n in set(names):
+        assert hasattr(lib, n), f"{n} declared in fft3d.h but not exported"
+
+
+SUPPORTED = [1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 60, 64, 75, 80, 96,
+             100, 120, 125, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 384, 400, 480, 500, 512,
+             600, 640, 750, 768, 800, 960, 1000, 1024, 2048, 4096]
+
+
+def test_supported_lengths_and_radix_plans(fft3d):
+    for n in range(1, 4100):
+        assert fft3d.length_supported(n) == (n in SUPPORTED), n
+    for n in SUPPORTED:
+        radices, tpl = fft3d.query_radix_plan(n)
+        assert int(np.prod(radices)) == n
+        assert set(radices) <= {2, 3, 4, 5, 8, 16}
+        assert tpl == (n // max(radices) if radices else 1)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 12, 100, 120, 512, 1000, 1024, 4096])
+def test_twiddles(fft3d, n):
+    w64 = fft3d.query_twiddles(n, "c128")
+    m = np.arange(n, dtype=np.longdouble)
+    pi = np.longdouble("3.14159265358979323846264338327950288")  # pi to long double precision
+    ang = np.longdouble(-2) * pi * m / np.longdouble(n)
+    ref = (np.cos(ang), np.sin(ang))
+    ulp_re = np.spacing(np.abs(w64.real).astype(np.float64)) + np.finfo(np.float64).tiny
+    ulp_im = np.spacing(np.abs(w64.imag).astype(np.float64)) + np.finfo(np.float64).tiny
+    # within one ulp of the extended-precision value (x86 long double, ~1e-19 relative)
+    assert np.all(np.abs(w64.real - ref[0]) <= ulp_re + 1e-18)
+    assert np.all(np.abs(w64.imag - ref[1]) <= ulp_im + 1e-18)
+    # exact special values
+    assert w64[0] == 1
+    if n % 2 == 0:
+        assert w64[n // 2] == -1
+    if n % 4 == 0:
+        assert w64[n // 4] == -1j and w64[3 * n // 4] == 1j
+    # the complex64 table is the round-to-nearest-even of the complex128 table
+    w32 = fft3d.query_twiddles(n, "c64")
+    assert np.array_equal(w32.real, w64.real.astype(np.float32))
+    assert np.array_equal(w32.imag, w64.imag.astype(np.float32))
+
+
+# ------------------------------------------------------------------ task graph
+
+def _cover(shape_c, tasks, stage):
+    nz, ny, nxc = shape_c
+    count = np.zeros((nz, ny, nxc), dtype=np.int64)
+    for t in tasks:
+        if t["stage"] != stage:
+            continue
+        x0, x1, y0, y1, z0, z1 = t["box"]
+        count[z0:z1, y0:y1, x0:x1] += 1
+    return count
+
+
+def _overlap(a, b):
+    return all(a[2 * d] < b[2 * d + 1] and b[2 * d] < a[2 * d + 1] for d in range(3))
+
+
+GRAPH_CASES = [((8, 8, 8), (1, 1), 0, 1), ((8, 8, 8), (2, 2), 0, 2), ((12, 10, 20), (3, 4), 0, 4),
+               ((12, 10, 20), (3, 4), 1, 3), ((16, 8, 6), (4, 2), 2, 8), ((6, 10, 16), (2, 3), 3, 4),
+               ((6, 10, 16), (5, 3), 4, 2), ((32, 32, 32), (8, 8), 0, 16), ((5, 6, 4), (3, 5), 1, 1)]
+
+
+@pytest.mark.parametrize("shape,grid,op,ns", GRAPH_CASES)
+def test_tiles_partition_and_dependencies(fft3d, shape, grid, op, ns):
+    r2c = op >= 3
+    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=ns)
+    nz, ny, nx = shape
+    nxc = nx // 2 + 1 if r2c else nx
+    assert len(tasks) == len(stages) * grid[0] * grid[1]
+    for s in range(len(stages)):
+        assert np.all(_cover((nz, ny, nxc), tasks, s) == 1), "tiles of a stage partition the array"
+    pos = {}
+    for i, t in enumerate(tasks):
+        # topological issue order; deps are exactly the overlapping tiles of the previous stage
+        want = sorted(j for j, u in enumerate(tasks)
+                      if u["stage"] == t["stage"] - 1 and _overlap(u["box"], t["box"]))
+        assert sorted(t["deps"]) == want
+        assert all(d < i for d in t["deps"])
+        assert 0 <= t["stream"] < ns
+        pos[i] = i
+    # happens-before: stream order + event waits cover every dependency
+    last_on = {}
+    hb = []
+    for i, t in enumerate(tasks):
+        before = set()
+        if t["stream"] in last_on:
+            j = last_on[t["stream"]]
+            before |= {j} | hb[j]
+        for w in t["waits"]:
+            assert tasks[w]["stream"] != t["stream"]
+            before |= {w} | hb[w]
+        hb.append(before)
+        last_on[t["stream"]] = i
+        assert set(t["deps"]) <= before, f"task {i} can start before a producer"
+
+
+def test_immediate_dispatch_order(fft3d):
+    """With a grid of z-slabs, each y tile is issued right after the x tiles of its slab."""
+    _, tasks = fft3d.query_pipeline((16, 16, 16), (1, 4), op=0, nstreams=1)
+    assert [t["stage"] for t in tasks] == [0, 1] * 4 + [2] * 4
+    for k in range(4):
+        assert tasks[2 * k + 1]["deps"] == [2 * k]
+
+
+def test_placement_balances_streams(fft3d):
+    _, tasks = fft3d.query_pipeline((32, 32, 32), (4, 4), op=0, nstreams=4)
+    for s in range(3):
+        per = [sum(1 for t in tasks if t["stage"] == s and t["stream"] == q) for q in range(4)]
+        assert max(per) - min(per) <= 1
+
+
+# ------------------------------------------------------------------ simulator
+
+def _wavenumber(j, n):
+    return np.where(2 * j <= n, j, j - n)
+
+
+def _apply_stage(st, box, bufs, shape):
+    nz, ny, nx = shape
+    x0, x1, y0, y1, z0, z1 = box
+    kind, axis, n, conj, weight, scale = (st[k] for k in ("kind", "axis", "n", "conj", "weight", "scale"))
+    src, dst = bufs[st["src"]], bufs[st["dst"]]
+    sign = 1 if conj else -1
+    if kind == 0:  # C2C along axis
+        sub = src[z0:z1, y0:y1, x0:x1]
+        ax = {0: 2, 1: 1, 2: 0}[axis]
+        res = np.apply_along_axis(lambda v: oracle.dft1d(v, sign), ax, sub) * scale
+        dst[z0:z1, y0:y1, x0:x1] = res
+    elif kind == 1:  # R2C along x: rows (y, z) of the real source
+        h = nx // 2
+        rows = src[z0:z1, y0:y1, :]
+        res = np.apply_along_axis(lambda v: oracle.dft1d(v.astype(complex))[: h + 1], 2, rows)
+        if weight:
+            res[..., 1:h] *= 2
+        dst[z0:z1, y0:y1, :] = res * scale
+    elif kind == 2:  # C2R along x
+        h = nx // 2
+        rows = src[z0:z1, y0:y1, :].copy()
+        rows[..., 0] = rows[..., 0].real
+        rows[..., h] = rows[..., h].real
+        if weight:
+            rows[..., 1:h] *= 0.5
+
+        def c2r(v):
+            full = np.concatenate([v, np.conj(v[1:h][::-1])])
+            return oracle.dft1d(full, +1).real
+
+        dst[z0:z1, y0:y1, :] = np.apply_along_axis(c2r, 2, rows) * scale
+    elif kind == 3:  # Poisson z stage
+        sub = src[z0:z1, y0:y1, x0:x1]
+        kz = _wavenumber(np.arange(nz), nz)[:, None, None]
+        ky = _wavenumber(np.arange(y0, y1), ny)[None, :, None]
+        kx = np.arange(x0, x1)[None, None, :]
+        k2 = (kx * kx + ky * ky + kz * kz).astype(float)
+        m = np.where(k2 == 0, 0.0, -1.0 / np.where(k2 == 0, 1, k2)) * scale
+        f = np.apply_along_axis(lambda v: oracle.dft1d(v, -1), 0, sub)
+        dst[z0:z1, y0:y1, x0:x1] = np.apply_along_axis(lambda v: oracle.dft1d(v, +1), 0, f * m)
+    else:
+        raise AssertionError(kind)
+
+
+def _simulate(fft3d, shape, grid, op, ns, inp, rng):
+    r2c = op >= 3 or np.isrealobj(inp) or inp.shape[2] != shape[2]
+    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=ns)
+    nz, ny, nx = shape
+    nxc = nx // 2 + 1
+    if not r2c:
+        out = np.full(shape, np.nan + 0j)
+        ws = None
+    else:
+        out_real = op in (1, 2, 3, 4)
+        out = np.full(shape, np.nan) if out_real else np.full((nz, ny, nxc), np.nan + 0j)
+        ws = np.full((nz, ny, nxc), np.nan + 0j)
+    bufs = [inp.copy(), out, ws]
+    # a task may run once the previous task of its stream and every waited task have run
+    done = [False] * len(tasks)
+    per_stream = {}
+    for i, t in enumerate(tasks):
+        per_stream.setdefault(t["stream"], []).append(i)
+    head = {s: 0 for s in per_stream}
+    for _ in range(len(tasks)):
+        runnable = []
+        for s, lst in per_stream.items():
+            if head[s] < len(lst):
+                i = lst[head[s]]
+                if all(done[w] for w in tasks[i]["waits"]):
+                    runnable.append((s, i))
+        assert runnable, "deadlock"
+        s, i = runnable[rng.integers(len(runnable))]
+        _apply_stage(stages[tasks[i]["stage"]], tasks[i]["box"], bufs, shape)
+        done[i] = True
+        head[s] += 1
+    return bufs[1]
+
+
+SIM_CASES = [((6, 4, 8), (2, 2), 2), ((5, 6, 10), (3, 2), 4), ((8, 6, 4), (1, 3), 1), ((4, 4, 6), (2, 1), 3)]
+
+
+@pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
+def test_simulated_c2c(fft3d, shape, grid, ns):
+    rng = np.random.default_rng(0)
+    a = synth.complex_normal(shape, 1)
+    for trial in range(3):
+        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 0, ns, a, rng), oracle.fftn(a)) < 1e-14
+        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 1, ns, a, rng), oracle.ifftn(a)) < 1e-14
+        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 2, ns, a, rng), oracle.bfftn(a)) < 1e-14
+
+
+@pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
+def test_simulated_r2c_family(fft3d, shape, grid, ns):
+    rng = np.random.default_rng(1)
+    nz, ny, nx = shape
+    f = synth.real_normal(shape, 2)
+    w = synth.real_normal(shape, 3)
+    H = synth.complex_normal((nz, ny, nx // 2 + 1), 4)
+    got = _simulate(fft3d, shape, grid, 0, ns, f, rng)
+    assert oracle.rel_l2(got, oracle.rfftn(f)) < 1e-14
+    got = _simulate(fft3d, shape, grid, 1, ns, H, rng)
+    assert oracle.rel_l2(got, oracle.irfftn(H, nx)) < 1e-14
+    # backward = adjoint of rfftn: Re<H, rfftn f> = <f, backward H>
+    g = _simulate(fft3d, shape, grid, 2, ns, H, rng)
+    lhs = np.vdot(H, oracle.rfftn(f)).real
+    assert abs(lhs - np.dot(f.ravel(), g.ravel())) < 1e-12 * abs(lhs)
+    phi = _simulate(fft3d, shape, grid, 3, ns, f, rng)
+    assert oracle.rel_l2(phi, oracle.poisson(f)) < 1e-13
+    gf = _simulate(fft3d, shape, grid, 4, ns, w, rng)
+    assert oracle.rel_l2(gf, oracle.poisson_grad(w)) < 1e-13
+
+
+def test_simulator_catches_a_missing_edge(fft3d, monkeypatch):
+    """Drop one dependency from the library's graph: some random order then goes wrong."""
+    real_query = fft3d.query_pipeline
+
+    def broken(*args, **kw):
+        stages, tasks = real_query(*args, **kw)
+        for t in tasks:  # forget the waits of the first stage-1 task placed on stream 0
+            if t["stage"] == 1 and t["stream"] == 0 and t["waits"]:
+                t["waits"] = []
+                break
+        return stages, tasks
+
+    monkeypatch.setattr(fft3d, "query_pipeline", broken)
+    shape, grid = (6, 4, 8), (2, 2)
+    a = synth.complex_normal(shape, 1)
+    rng = np.random.default_rng(3)
+    errs = [oracle.rel_l2(_simulate(fft3d, shape, grid, 0, 2, a, rng), oracle.fftn(a)) for _ in range(12)]
+    assert max(e if np.isfinite(e) else np.inf for e in errs) > 1e-3
