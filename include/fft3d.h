@@ -162,6 +162,56 @@ int fft3d_stage_times(fft3d_plan_t plan, float* ms, int cap);
 const char* fft3d_status_string(int status);
 const char* fft3d_last_error(void);
 
+/* --------------------------------------------------------- batches
+ * Many independent complex64 3D transforms of (possibly) different sizes in
+ * one persistent kernel launch.  The kernel takes work items (a batch of lines
+ * of one stage of one transform) from a device-side queue that lists every
+ * first stage before any second stage; an item waits on a per-(transform,
+ * stage) completion counter, so the stages of different transforms overlap
+ * freely with no global barrier (the paper's dynamically scheduled FFT tasks,
+ * Sec. III-C and IV-D).  The launch (a counter reset and the persistent
+ * kernel) is captured into a hipGraph on first use and replayed afterwards;
+ * if the caller's stream is itself being captured, the kernels are launched
+ * into that capture instead. */
+typedef struct fft3d_batch_s* fft3d_batch_t;
+
+/* dims holds count triples (nx, ny, nz); every length must be a supported
+ * length <= 512; dtype must be FFT3D_C64.  Allocates the plan's twiddle and
+ * queue tables. */
+fft3d_status fft3d_plan_batch(fft3d_batch_t* plan, int count, const int64_t* dims, int dtype);
+
+/* Forward (sign -1, unscaled) / inverse (sign +1, scaled 1/N per transform)
+ * of every transform: in[f], out[f] are device pointers to Nx*Ny*Nz complex64
+ * values (x fastest); in[f] == out[f] is allowed, partial overlap and overlap
+ * between different transforms are FFT3D_ERR_ALIAS.  When the pointer set
+ * differs from the previous call the plan waits for `stream` and uploads a new
+ * queue table (a synchronous copy); with unchanged pointers nothing blocks. */
+fft3d_status fft3d_batch_forward(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
+fft3d_status fft3d_batch_inverse(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
+
+/* Lines per work item for lines of length n (strided: 1 for y/z lines, 0 for
+ * x lines); 0 restores the default.  Used by the autotuner; the results do not
+ * depend on it. */
+fft3d_status fft3d_batch_set_lines(fft3d_batch_t plan, int64_t n, int strided, int lw);
+
+/* 0: persistent kernel replayed from a hipGraph (default); 1: persistent
+ * kernel launched directly; 2: one launch per stage, no device-side waits
+ * (for comparison). */
+fft3d_status fft3d_batch_set_mode(fft3d_batch_t plan, int mode);
+
+/* Wait for the plan's last call and report FFT3D_ERR_HIP if a work item gave
+ * up waiting on a dependency (a bounded spin; then every workgroup exits). */
+fft3d_status fft3d_batch_check(fft3d_batch_t plan);
+
+fft3d_status fft3d_batch_destroy(fft3d_batch_t plan);
+
+/* Host-only: the work queue of a batch (op 0 forward, 1 inverse) as int64
+ * records [nseg] then per segment [fft, stage, axis, n, strided, lines per
+ * item, items, first item, dependency segment (-1: none), items it needs,
+ * counter index].  Returns the number of values needed; writes them if cap is
+ * large enough; -1 on invalid arguments. */
+int64_t fft3d_query_batch_queue(int count, const int64_t* dims, int op, int64_t* out, int64_t cap);
+
 /* ----------------------------------------------------- host-side queries
  * These run on the host only and need no GPU; tests use them to check the
  * planner. */

@@ -38,6 +38,16 @@ fft3d_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr int kMaxStreams = 16;
+
+}  // namespace
+
+namespace fft3d {
+// error reporting shared with the batch entry points (batch.cpp)
+fft3d_status set_error(fft3d_status st, const std::string& msg) { return fail(st, msg); }
+fft3d_status set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace fft3d
+
+namespace {
 constexpr int kDefaultStreams = 4;
 
 }  // namespace

@@ -177,6 +177,81 @@ class Plan:
             pass
 
 
+class BatchPlan:
+    """Many complex64 3D FFTs of different shapes in one persistent launch."""
+
+    def __init__(self, shapes, mode=0):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        dims = (ctypes.c_int64 * (3 * len(self.shapes)))()
+        for i, (nz, ny, nx) in enumerate(self.shapes):
+            dims[3 * i], dims[3 * i + 1], dims[3 * i + 2] = nx, ny, nz
+        h = ctypes.c_void_p()
+        check(_lib.lib().fft3d_plan_batch(ctypes.byref(h), len(self.shapes), dims, C64), "fft3d_plan_batch")
+        self._h = h
+        self.set_mode(mode)
+
+    def set_mode(self, mode: int):
+        check(_lib.lib().fft3d_batch_set_mode(self._h, int(mode)), "fft3d_batch_set_mode")
+
+    def set_lines(self, n: int, strided: bool, lw: int):
+        check(_lib.lib().fft3d_batch_set_lines(self._h, int(n), int(bool(strided)), int(lw)),
+              "fft3d_batch_set_lines")
+
+    def _run(self, fn, xs, outs, stream):
+        if len(xs) != len(self.shapes):
+            raise ValueError("one input per transform")
+        for x, s in zip(xs, self.shapes):
+            if not (x.is_cuda and x.dtype == torch.complex64 and tuple(x.shape) == s and x.is_contiguous()):
+                raise ValueError(f"inputs must be contiguous complex64 CUDA tensors of shapes {self.shapes}")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for o, s in zip(outs, self.shapes):
+            if not (o.is_cuda and o.dtype == torch.complex64 and tuple(o.shape) == s and o.is_contiguous()):
+                raise ValueError("outputs must match the inputs")
+        n = len(xs)
+        ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ous = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        check(fn(self._h, ins, ous, ctypes.c_void_p(_stream_handle(stream))), fn.__name__)
+        return outs
+
+    def forward(self, xs, outs=None, stream=None):
+        return self._run(_lib.lib().fft3d_batch_forward, xs, outs, stream)
+
+    def inverse(self, xs, outs=None, stream=None):
+        return self._run(_lib.lib().fft3d_batch_inverse, xs, outs, stream)
+
+    def check(self):
+        check(_lib.lib().fft3d_batch_check(self._h), "fft3d_batch_check")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().fft3d_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def query_batch_queue(shapes, op=0):
+    """Decoded work queue of a batch (host-only)."""
+    n = len(shapes)
+    dims = (ctypes.c_int64 * (3 * n))()
+    for i, (nz, ny, nx) in enumerate(shapes):
+        dims[3 * i], dims[3 * i + 1], dims[3 * i + 2] = nx, ny, nz
+    L = _lib.lib()
+    need = L.fft3d_query_batch_queue(n, dims, op, None, 0)
+    if need < 0:
+        raise ValueError("invalid batch")
+    buf = (ctypes.c_int64 * need)()
+    L.fft3d_query_batch_queue(n, dims, op, buf, need)
+    v = list(buf)
+    keys = ("fft", "stage", "axis", "n", "strided", "lw", "items", "first", "dep", "dep_count", "done_idx")
+    return [dict(zip(keys, v[1 + 11 * i: 12 + 11 * i])) for i in range(v[0])]
+
+
 _cache: dict = {}
 _cache_lock = threading.Lock()
 
