@@ -110,6 +110,117 @@ def _measure(dtype, shape, grid, streams, steps, warmup, a_host, torch, fft3d):
     return dict(ms=ms, wall=wall, fwd_stages=fwd_st, inv_stages=inv_st, X=X, Y=Y)
 
 
+def _time(fn, reps, torch):
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def _extras(reps, torch, fft3d, synth, np):
+    """The other workloads, timed on the GPU.  Returns (report, checks) where
+    checks holds (name, GPU result on the host, function giving the FP64 oracle
+    result) for the CPU-baseline leg."""
+    rep, checks = {}, []
+    n = 512
+    N = n ** 3
+    nh = (n // 2 + 1) * n * n
+    for dt, tag, sr, npdt in ((torch.float32, "f32", 4, np.float32), (torch.float64, "f64", 8, np.float64)):
+        f = synth.real_normal((n, n, n), 10, npdt)
+        x = torch.from_numpy(f).cuda()
+        p = fft3d.Plan((n, n, n), dt, r2c=True)
+        H = p.forward(x)
+        y = p.inverse(H)
+        ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), reps, torch)
+        bytes_moved = 2 * N * sr + 10 * nh * 2 * sr  # x stage real in/out, 5 half-spectrum passes each way
+        rep[f"r2c_512cubed_fwd_inv_{tag}"] = {
+            "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        Hh, yh = H.cpu().numpy(), y.cpu().numpy()
+        checks.append((f"r2c_512cubed_{tag}_forward", Hh, lambda f=f: _oracle().rfftn(f.astype(np.float64))))
+        checks.append((f"r2c_512cubed_{tag}_roundtrip", yh, lambda f=f: f.astype(np.float64)))
+        p.close()
+        del x, H, y
+        torch.cuda.empty_cache()
+    # 256^3 C2C on the 4x4 pencil grid of tiles (and 1x1 for comparison)
+    cfg = synth.CFG2
+    m = cfg["shape"][0] ** 3
+    a = synth.complex_normal(cfg["shape"], cfg["seed"], np.complex64)
+    for dt, tag, es in ((torch.complex64, "c64", 8), (torch.complex128, "c128", 16)):
+        x = torch.from_numpy(a).to("cuda", dt)
+        for grid, ns in ((tuple(cfg["grid"]), 4), ((1, 1), 1)):
+            p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns)
+            X = p.forward(x)
+            Y = torch.empty_like(X)
+            ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), reps, torch)
+            rep[f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}"] = {
+                "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if grid != (1, 1):
+                checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),
+                               lambda: _oracle().fftn(a.astype(np.complex128))))
+            p.close()
+        del x
+        torch.cuda.empty_cache()
+    # 64 uneven transforms issued as one task graph, on a non-default stream
+    shapes = synth.batch_sizes()
+    host = synth.batch_inputs(shapes, synth.CFG4["seed"])
+    xs = [torch.from_numpy(h).cuda() for h in host]
+    outs = [torch.empty_like(t) for t in xs]
+    pts = sum(int(np.prod(sh)) for sh in shapes)
+    flops = sum(5 * np.prod(sh) * math.log2(np.prod(sh)) for sh in shapes)
+    brep = {"transforms": len(shapes), "points": pts}
+    side = torch.cuda.Stream()
+    for mode, name in ((0, "graph_4_streams"), (1, "direct_4_streams"), (2, "serial_one_stream")):
+        bp = fft3d.BatchPlan(shapes, mode=mode)
+        with torch.cuda.stream(side):
+            ms = _time(lambda: bp.forward(xs, outs), reps, torch)
+        brep[name] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+                      "hbm_frac": round(3 * 2 * 8 * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        bp.close()
+    bp = fft3d.BatchPlan(shapes)
+    with torch.cuda.stream(side):
+        bp.forward(xs, outs)
+    torch.cuda.synchronize()
+    bp.close()
+    rep["batched_64_uneven_c64"] = brep
+    checks.append(("batched_64_uneven_forward_worst", [o.cpu().numpy() for o in outs],
+                   lambda: [_oracle().fftn(h.astype(np.complex128)) for h in host]))
+    del xs, outs
+    torch.cuda.empty_cache()
+    # differentiable Poisson solve, 256^3 float32: forward solve + adjoint (one gradient step)
+    c5 = synth.CFG5
+    f = synth.smooth_field(c5["shape"], c5["seed_f"], c5["sigma"], np.float32)
+    w = synth.real_normal(c5["shape"], c5["seed_w"], np.float32)
+    fd, wd = torch.from_numpy(f).cuda(), torch.from_numpy(w).cuda()
+    p = fft3d.Plan(c5["shape"], torch.float32, r2c=True)
+    phi = p.poisson(fd)
+    g = p.poisson_adjoint(wd)
+    ms = _time(lambda: (p.poisson(fd, out=phi), p.poisson_adjoint(wd, out=g)), reps, torch)
+    m = int(np.prod(c5["shape"]))
+    mh = (c5["shape"][2] // 2 + 1) * c5["shape"][0] * c5["shape"][1]
+    pbytes = 2 * (2 * m * 4 + 8 * mh * 8)  # per solve: real in/out + 4 half-spectrum passes
+    rep["poisson_256cubed_f32_solve_plus_adjoint"] = {
+        "ms": round(ms, 4), "hbm_frac": round(pbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    checks.append(("poisson_256cubed_solution", phi.cpu().numpy(), lambda: _oracle().poisson(f.astype(np.float64))))
+    checks.append(("poisson_256cubed_gradient", g.cpu().numpy(), lambda: _oracle().poisson_grad(w.astype(np.float64))))
+    p.close()
+    return rep, checks
+
+
+def _oracle():
+    import oracle  # test infrastructure: used by the CPU-baseline leg only
+
+    return oracle
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +231,8 @@ def main():
     ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS)
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 run")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle on the host")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (R2C 512^3, 256^3 grid, batch, Poisson)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy the complex64 field once with a plain device copy "
                          "(a known-size reference for HBM byte counters)")
@@ -212,6 +325,18 @@ def main():
                           "stages_c128": stage_report(r64, 16),
                           "fp32_over_fp64_speedup": round(r64["ms"] / r32["ms"], 3)}
 
+    checks = []
+    if not args.no_extras:
+        # keep the headline results on the host for the oracle comparison, free the GPU
+        for r in (r32, r64):
+            if r is not None and not args.no_cpu_baseline:
+                r["X"], r["Y"] = r["X"].cpu().numpy(), r["Y"].cpu().numpy()
+            elif r is not None:
+                r.pop("X"), r.pop("Y")
+        torch.cuda.empty_cache()
+        print("# extras", file=sys.stderr, flush=True)
+        result["extras"], checks = _extras(max(3, min(args.steps, 10)), torch, fft3d, synth, np)
+
     if not args.no_cpu_baseline:
         import oracle  # test infrastructure: the CPU baseline leg only
 
@@ -220,11 +345,23 @@ def main():
         X_ref = oracle.fftn(a128)
         Y_ref = oracle.ifftn(X_ref)
         t_cpu = time.perf_counter() - t0
-        errs = {"c64_forward": oracle.rel_l2(r32["X"].cpu().numpy(), X_ref),
-                "c64_inverse_of_forward": oracle.rel_l2(r32["Y"].cpu().numpy(), a128)}
+        def host(v):
+            return v.cpu().numpy() if hasattr(v, "cpu") else v
+
+        errs = {}
+        if "X" in r32:
+            errs["c64_forward"] = oracle.rel_l2(host(r32["X"]), X_ref)
+            errs["c64_inverse_of_forward"] = oracle.rel_l2(host(r32["Y"]), a128)
         if r64 is not None:
-            errs["c128_forward"] = oracle.rel_l2(r64["X"].cpu().numpy(), X_ref)
-            errs["c128_inverse_of_forward"] = oracle.rel_l2(r64["Y"].cpu().numpy(), a128)
+            errs["c128_forward"] = oracle.rel_l2(host(r64["X"]), X_ref)
+            errs["c128_inverse_of_forward"] = oracle.rel_l2(host(r64["Y"]), a128)
+        del X_ref
+        for name, got, ref_fn in checks:
+            ref = ref_fn()
+            if isinstance(got, list):
+                errs[name] = max(oracle.rel_l2(g, r) for g, r in zip(got, ref))
+            else:
+                errs[name] = oracle.rel_l2(got, ref)
         del Y_ref
         result["cpu_baseline"] = {
             "value": round(2 * flop_per_transform / t_cpu / 1e9, 3), "unit": "GFLOP/s",

@@ -130,7 +130,9 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
 
 /*
  * Number of internal HIP streams the tiles are placed on (1..16; default 4).
- * With 1, every tile is enqueued directly on the caller's stream.
+ * The streams are created by the first call that needs them.  With 1 stream,
+ * or a 1x1 pencil grid (one tile per stage), every tile is enqueued directly
+ * on the caller's stream in dependency order.
  */
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
@@ -163,54 +165,47 @@ const char* fft3d_status_string(int status);
 const char* fft3d_last_error(void);
 
 /* --------------------------------------------------------- batches
- * Many independent complex64 3D transforms of (possibly) different sizes in
- * one persistent kernel launch.  The kernel takes work items (a batch of lines
- * of one stage of one transform) from a device-side queue that lists every
- * first stage before any second stage; an item waits on a per-(transform,
- * stage) completion counter, so the stages of different transforms overlap
- * freely with no global barrier (the paper's dynamically scheduled FFT tasks,
- * Sec. III-C and IV-D).  The launch (a counter reset and the persistent
- * kernel) is captured into a hipGraph on first use and replayed afterwards;
- * if the caller's stream is itself being captured, the kernels are launched
- * into that capture instead. */
+ * Many independent 3D transforms of (possibly) different sizes issued as one
+ * task graph: every transform runs the stage kernels of its shape on one of
+ * four internal streams, transforms placed in decreasing order of cost on the
+ * least-loaded stream (Alg. 3 placement), so the stages of different
+ * transforms overlap with no barrier between them (the paper's dynamically
+ * scheduled FFT tasks, Sec. III-C and IV-D).  On a non-default stream the
+ * whole batch (fork, per-stream launches, join) is captured into a hipGraph
+ * on first use for each operation and pointer set, and replayed afterwards;
+ * if the caller is capturing the stream, the launches join that capture. */
 typedef struct fft3d_batch_s* fft3d_batch_t;
 
-/* dims holds count triples (nx, ny, nz); every length must be a supported
- * length <= 512; dtype must be FFT3D_C64.  Allocates the plan's twiddle and
- * queue tables. */
+/* dims holds count triples (nx, ny, nz), each a shape fft3d_plan accepts;
+ * dtype FFT3D_C64 or FFT3D_C128.  Creates one plan per distinct shape, the
+ * streams and events. */
 fft3d_status fft3d_plan_batch(fft3d_batch_t* plan, int count, const int64_t* dims, int dtype);
 
-/* Forward (sign -1, unscaled) / inverse (sign +1, scaled 1/N per transform)
- * of every transform: in[f], out[f] are device pointers to Nx*Ny*Nz complex64
- * values (x fastest); in[f] == out[f] is allowed, partial overlap and overlap
- * between different transforms are FFT3D_ERR_ALIAS.  When the pointer set
- * differs from the previous call the plan waits for `stream` and uploads a new
- * queue table (a synchronous copy); with unchanged pointers nothing blocks. */
+/* Forward (sign -1, unscaled) / inverse (sign +1, 1/N per transform) of every
+ * transform: in[f], out[f] are device pointers to Nx*Ny*Nz complex values (x
+ * fastest); in[f] == out[f] is allowed, a partial overlap is FFT3D_ERR_ALIAS,
+ * and so is any overlap between buffers of different transforms. */
 fft3d_status fft3d_batch_forward(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
 fft3d_status fft3d_batch_inverse(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
 
-/* Lines per work item for lines of length n (strided: 1 for y/z lines, 0 for
- * x lines); 0 restores the default.  Used by the autotuner; the results do not
- * depend on it. */
-fft3d_status fft3d_batch_set_lines(fft3d_batch_t plan, int64_t n, int strided, int lw);
+/* Launch shape of one stage of the transforms of one shape (arguments as
+ * fft3d_set_stage_config); drops the captured graphs.  Used by the
+ * autotuner; results do not depend on it. */
+fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
+                                          int lw, int tdiv, int split, int pad);
 
-/* 0: persistent kernel replayed from a hipGraph (default); 1: persistent
- * kernel launched directly; 2: one launch per stage, no device-side waits
- * (for comparison). */
+/* 0: graph replay on non-default streams (default); 1: direct launches on the
+ * internal streams; 2: all transforms one after another on the caller's
+ * stream (for comparison). */
 fft3d_status fft3d_batch_set_mode(fft3d_batch_t plan, int mode);
-
-/* Wait for the plan's last call and report FFT3D_ERR_HIP if a work item gave
- * up waiting on a dependency (a bounded spin; then every workgroup exits). */
-fft3d_status fft3d_batch_check(fft3d_batch_t plan);
 
 fft3d_status fft3d_batch_destroy(fft3d_batch_t plan);
 
-/* Host-only: the work queue of a batch (op 0 forward, 1 inverse) as int64
- * records [nseg] then per segment [fft, stage, axis, n, strided, lines per
- * item, items, first item, dependency segment (-1: none), items it needs,
- * counter index].  Returns the number of values needed; writes them if cap is
- * large enough; -1 on invalid arguments. */
-int64_t fft3d_query_batch_queue(int count, const int64_t* dims, int op, int64_t* out, int64_t cap);
+/* Host-only: placement of a batch on nstreams streams as int64 records
+ * [nstreams] then per stream [n, transform indices in issue order...].
+ * Returns the number of values needed; writes them if cap is large enough;
+ * -1 on invalid arguments. */
+int64_t fft3d_query_batch_placement(int count, const int64_t* dims, int nstreams, int64_t* out, int64_t cap);
 
 /* ----------------------------------------------------- host-side queries
  * These run on the host only and need no GPU; tests use them to check the

@@ -32,11 +32,10 @@ _SIGS = {
     "fft3d_plan_batch": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64), I32]),
     "fft3d_batch_forward": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
     "fft3d_batch_inverse": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
-    "fft3d_batch_set_lines": (I32, [P, I64, I32, I32]),
+    "fft3d_batch_set_stage_config": (I32, [P, I64, I64, I64, I32, I32, I32, I32, I32]),
     "fft3d_batch_set_mode": (I32, [P, I32]),
-    "fft3d_batch_check": (I32, [P]),
     "fft3d_batch_destroy": (I32, [P]),
-    "fft3d_query_batch_queue": (I64, [I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I64), I64]),
+    "fft3d_query_batch_placement": (I64, [I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I64), I64]),
     "fft3d_status_string": (ctypes.c_char_p, [I32]),
     "fft3d_last_error": (ctypes.c_char_p, []),
     "fft3d_length_supported": (I32, [I64]),

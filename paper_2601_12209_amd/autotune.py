@@ -1,13 +1,11 @@
-"""Autotuner for the launch shapes of the stage kernels and the batch kernel.
+"""Autotuner for the launch shapes of the stage kernels.
 
-Single-transform plans: for every axis it times the candidate shapes (lines
-per workgroup, threads-per-line divisor, split exchange, padding) that the
-library accepts for that stage, using the per-stage timing events, and keeps
-the fastest.  Batches: for every (length, layout) present it times the whole
-persistent launch with each candidate lines-per-item value, one coordinate at a
-time, and keeps the fastest.  The shapes only change how work is mapped onto
-threads, never the arithmetic, so results are bitwise identical whatever is
-chosen.
+For every axis of a plan it times the candidate shapes (lines per workgroup,
+threads-per-line divisor, split exchange, padding) that the library accepts
+for that stage, using the per-stage timing events, and keeps the fastest; a
+batch is tuned shape by shape the same way.  The shapes only change how work
+is mapped onto threads, never the arithmetic, so results are bitwise
+identical whatever is chosen.
 
 Choices are cached in a JSON file (``FFT3D_TUNE_CACHE``, default
 ``~/.cache/fft3d_tune.json``) keyed by GPU architecture, precision, length,
@@ -131,60 +129,15 @@ def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: 
     return chosen
 
 
-def _time_batch(bp, xs, outs, reps):
-    for _ in range(2):
-        bp.forward(xs, outs)
-    torch.cuda.synchronize()
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        bp.forward(xs, outs)
-    e.record()
-    torch.cuda.synchronize()
-    bp.check()
-    return s.elapsed_time(e) / reps
-
-
-def tune_batch(bp: fft3d.BatchPlan, xs, reps: int = 5, use_cache: bool = True, verbose: bool = False):
-    """Pick lines per item for every (length, layout) of the batch; returns {(n, strided): lw}."""
-    with _lock:
-        cache = _load() if use_cache else {}
-    outs = [torch.empty_like(x) for x in xs]
-    keys = set()
-    for nz, ny, nx in bp.shapes:
-        keys |= {(nx, 0), (ny, 1), (nz, 1)}
+def tune_batch(bp: fft3d.BatchPlan, reps: int = 5, use_cache: bool = True, verbose: bool = False):
+    """Tune the stage launch shapes of every distinct shape of the batch (on a
+    stand-alone plan of that shape) and apply them to the batch."""
     chosen = {}
-    pending = []
-    for n, strided in sorted(keys):
-        ck = f"{_arch()}|batch|c64|n{n}|strided{strided}"
-        if ck in cache:
-            bp.set_lines(n, strided, int(cache[ck]))
-            chosen[(n, strided)] = int(cache[ck])
-        else:
-            pending.append((n, strided, ck))
-    for n, strided, ck in pending:
-        _, tpl = fft3d.query_radix_plan(n)
-        best = (_time_batch(bp, xs, outs, reps), 0)
-        lw_max = max(1, 256 // tpl)
-        cands = sorted({max(1, lw_max // d) for d in (1, 2, 3, 4, 6, 8)})
-        for lw in cands:
-            try:
-                bp.set_lines(n, strided, lw)
-            except RuntimeError:
-                continue
-            t = _time_batch(bp, xs, outs, reps)
-            if verbose:
-                print(f"n={n} strided={strided} lw={lw}: {t:.4f} ms")
-            if t < best[0]:
-                best = (t, lw)
-        bp.set_lines(n, strided, best[1])
-        if best[1]:
-            chosen[(n, strided)] = best[1]
-            cache[ck] = best[1]
-    if use_cache:
-        with _lock:
-            merged = _load()
-            merged.update(cache)
-            _save(merged)
+    for shape in sorted(set(bp.shapes)):
+        p = fft3d.Plan(shape, fft3d._COMPLEX[bp.code])
+        got = tune_plan(p, reps=reps, use_cache=use_cache, verbose=verbose)
+        p.close()
+        for axis, cfg in got.items():
+            bp.set_stage_config(shape, axis, *cfg)
+        chosen[shape] = got
     return chosen

@@ -1,19 +1,25 @@
-// C ABI of batched transforms: many independent, unevenly sized 3D FFTs in
-// one persistent launch (work queue + per-stage completion counters, see
-// k_batch.hip), captured once into a hipGraph and replayed.
+// C ABI of batched transforms: many independent, unevenly sized 3D FFTs
+// issued as one task graph.  Every transform runs its x, y, z stage kernels
+// (the single-transform plan of its shape) on one of several internal
+// streams; transforms are placed on the least-loaded stream in decreasing
+// order of cost (the paper's Alg. 3 placement), so the GPU's hardware queues
+// overlap the stages of different transforms with no barrier between them.
+// The whole fork / per-stream work / join sequence is captured once into a
+// hipGraph per operation and pointer set, and replayed.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fft3d.h"
-#include "batch_args.hpp"
 #include "fft_lengths.hpp"
-#include "kernels.hpp"
 #include "plan.hpp"
 #include "stage_args.hpp"
 
@@ -26,134 +32,116 @@ using namespace fft3d;
 
 namespace {
 
-constexpr int kSpinLimit = 1 << 24;  // ~10^7 sleeps of 128 clocks: about half a second
+constexpr int kBatchStreams = 4;
+constexpr size_t kMaxGraphs = 8;
 
-struct OpState {
-    std::vector<BatchSegDesc> q;
-    std::vector<BatchSeg> hsegs;
-    BatchSeg* dsegs = nullptr;
-    int* ctl = nullptr;  // [0] head, [1] error, [2..] one counter per segment
-    size_t lds = 0;
-    int grid = 0;
-    int64_t total = 0;
-    int64_t stage_end[3] = {0, 0, 0};  // one past the last queue index of each stage
+using Shape = std::tuple<int64_t, int64_t, int64_t>;
+
+struct CachedGraph {
+    int op;
+    std::vector<const void*> in;
+    std::vector<void*> out;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<const void*> in_ptrs;
-    std::vector<void*> out_ptrs;
-    bool uploaded = false;
 };
 
 }  // namespace
 
 struct fft3d_batch_s {
     std::vector<PlanDesc> ffts;
+    int dtype = 0;
     int device = 0;
-    int cus = 1;
     int mode = 0;
-    std::map<int, void*> twp;  // length -> device per-pass twiddle table (complex64)
-    std::map<std::pair<int, int>, int> lw_override;
-    OpState ops[2];
+    std::map<Shape, fft3d_plan_t> plans;  // one single-stream plan per distinct shape
+    std::vector<std::vector<int>> placement;
+    std::vector<hipStream_t> streams;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    std::vector<CachedGraph> graphs;
     hipStream_t last_stream = nullptr;
     bool used = false;
 };
 
 namespace {
 
-int lw_for(void* ctx, int n, int strided)
-{
-    const fft3d_batch_s* b = (const fft3d_batch_s*)ctx;
-    auto it = b->lw_override.find({n, strided});
-    return it != b->lw_override.end() ? it->second : batch_default_lw(n, strided);
-}
+Shape shape_of(const PlanDesc& d) { return Shape(d.nx, d.ny, d.nz); }
 
-size_t seg_lds(int n, int lw)
+void drop_graphs(fft3d_batch_s* b)
 {
-    const size_t data = ((size_t)(lw + 1) * n * 8 + 15) & ~(size_t)15;
-    return data + (size_t)pass_table_size(radix_plan(n)) * 8;
-}
-
-void free_op(OpState& o)
-{
-    if (o.exec) hipGraphExecDestroy(o.exec);
-    if (o.graph) hipGraphDestroy(o.graph);
-    if (o.dsegs) hipFree(o.dsegs);
-    if (o.ctl) hipFree(o.ctl);
-    o = OpState();
-}
-
-// (Re)build the queue of one operation and its device tables.
-fft3d_status prepare_op(fft3d_batch_s* b, int opi)
-{
-    OpState& o = b->ops[opi];
-    free_op(o);
-    o.q = build_batch_queue(b->ffts, opi == 0 ? OP_FORWARD : OP_INVERSE, lw_for, b);
-    o.hsegs.assign(o.q.size(), BatchSeg());
-    size_t lds = 0;
-    for (size_t i = 0; i < o.q.size(); ++i) {
-        const BatchSegDesc& d = o.q[i];
-        BatchSeg& s = o.hsegs[i];
-        memset(&s, 0, sizeof s);
-        s.twp = b->twp[d.n];
-        s.first = d.first;
-        s.items = d.items;
-        s.A = d.A; s.B = d.B; s.off = d.off; s.sa = d.sa; s.sb = d.sb; s.se = d.se;
-        s.blocks_a = d.blocks_a;
-        s.n = d.n; s.strided = d.strided; s.lw = d.lw; s.conj = d.conj;
-        s.dep = d.dep;
-        s.done_idx = d.done_idx;
-        s.dep_count = d.dep_count;
-        s.scale = (float)d.scale;
-        lds = std::max(lds, seg_lds(d.n, d.lw));
-        o.total = d.first + d.items;
-        o.stage_end[d.stage] = std::max(o.stage_end[d.stage], d.first + d.items);
+    for (auto& g : b->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
     }
-    if (lds > kMaxLdsBytes) return set_error(FFT3D_ERR_INVALID_ARG, "lines per item exceed the LDS limit");
-    o.lds = lds;
-    o.grid = b->cus * batch_max_blocks_per_cu(lds);
-    hipError_t e = hipMalloc(&o.dsegs, sizeof(BatchSeg) * o.hsegs.size());
-    if (e == hipSuccess) e = hipMalloc(&o.ctl, sizeof(int) * (2 + o.hsegs.size()));
-    if (e != hipSuccess) {
-        free_op(o);
-        return set_hip_error(e, "batch table allocation");
+    b->graphs.clear();
+}
+
+void release(fft3d_batch_s* b)
+{
+    if (b->used) hipStreamSynchronize(b->last_stream);
+    for (hipStream_t s : b->streams)
+        if (s) {
+            hipStreamSynchronize(s);
+            hipStreamDestroy(s);
+        }
+    drop_graphs(b);
+    for (hipEvent_t e : b->joins)
+        if (e) hipEventDestroy(e);
+    if (b->fork) hipEventDestroy(b->fork);
+    for (auto& kv : b->plans) fft3d_destroy(kv.second);
+    delete b;
+}
+
+bool overlap(const void* a, size_t na, const void* c, size_t nc)
+{
+    const char* pa = (const char*)a;
+    const char* pc = (const char*)c;
+    return pa < pc + nc && pc < pa + na;
+}
+
+fft3d_status run_one(fft3d_batch_s* b, int op, int f, const void* in, void* out, hipStream_t s)
+{
+    fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
+    return op == 0 ? fft3d_forward(p, in, out, s) : fft3d_inverse(p, in, out, s);
+}
+
+// Enqueue the whole batch on `s`: fork, per-stream transforms, join.
+fft3d_status issue(fft3d_batch_s* b, int op, const void* const* in, void* const* out, hipStream_t s)
+{
+    if (b->mode == 2) {  // one stream, transforms one after another
+        for (const auto& per : b->placement)
+            for (int f : per) {
+                fft3d_status st = run_one(b, op, f, in[f], out[f], s);
+                if (st != FFT3D_OK) return st;
+            }
+        return FFT3D_OK;
+    }
+    hipError_t e = hipEventRecord(b->fork, s);
+    if (e != hipSuccess) return set_hip_error(e, "hipEventRecord(fork)");
+    for (size_t k = 0; k < b->placement.size(); ++k) {
+        if (b->placement[k].empty()) continue;
+        e = hipStreamWaitEvent(b->streams[k], b->fork, 0);
+        if (e != hipSuccess) return set_hip_error(e, "hipStreamWaitEvent(fork)");
+        for (int f : b->placement[k]) {
+            fft3d_status st = run_one(b, op, f, in[f], out[f], b->streams[k]);
+            if (st != FFT3D_OK) return st;
+        }
+        e = hipEventRecord(b->joins[k], b->streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[k], 0);
+        if (e != hipSuccess) return set_hip_error(e, "batch join");
     }
     return FFT3D_OK;
 }
 
-BatchCtl make_ctl(const OpState& o, int64_t base, int64_t end, int ignore)
-{
-    BatchCtl c;
-    memset(&c, 0, sizeof c);
-    c.head = o.ctl;
-    c.error = o.ctl + 1;
-    c.done = o.ctl + 2;
-    c.segs = o.dsegs;
-    c.nsegs = (int)o.hsegs.size();
-    c.spin_limit = kSpinLimit;
-    c.item_base = base;
-    c.total = end;
-    c.ignore_deps = ignore;
-    return c;
-}
-
-bool overlap(const void* a, size_t na, const void* b, size_t nb)
-{
-    const char* pa = (const char*)a;
-    const char* pb = (const char*)b;
-    return pa < pb + nb && pb < pa + na;
-}
-
-fft3d_status run_batch(fft3d_batch_t b, int opi, const void* const* in, void* const* out, void* stream)
+fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* const* out, void* stream)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
     if (!in || !out) return set_error(FFT3D_ERR_INVALID_ARG, "null pointer array");
     const int count = (int)b->ffts.size();
+    const size_t es = b->dtype == DT_F64 ? 16 : 8;
     std::vector<size_t> bytes(count);
     for (int f = 0; f < count; ++f) {
         if (!in[f] || !out[f]) return set_error(FFT3D_ERR_INVALID_ARG, "null buffer");
-        bytes[f] = (size_t)b->ffts[f].nx * b->ffts[f].ny * b->ffts[f].nz * 8;
-        if (in[f] != out[f] && overlap(in[f], bytes[f], out[f], bytes[f]))
-            return set_error(FFT3D_ERR_ALIAS, "in and out of one transform partially overlap");
+        bytes[f] = (size_t)b->ffts[f].nx * b->ffts[f].ny * b->ffts[f].nz * es;
     }
     for (int f = 0; f < count; ++f)
         for (int g = 0; g < count; ++g)
@@ -161,61 +149,65 @@ fft3d_status run_batch(fft3d_batch_t b, int opi, const void* const* in, void* co
                 return set_error(FFT3D_ERR_ALIAS, "buffers of two transforms of the batch overlap");
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return set_hip_error(e, "hipSetDevice");
-    OpState& o = b->ops[opi];
     hipStream_t s = (hipStream_t)stream;
-    bool same = o.uploaded && (int)o.in_ptrs.size() == count;
-    for (int f = 0; same && f < count; ++f) same = o.in_ptrs[f] == in[f] && o.out_ptrs[f] == out[f];
-    if (!same) {
-        for (size_t i = 0; i < o.q.size(); ++i) {
-            const BatchSegDesc& d = o.q[i];
-            o.hsegs[i].in = d.src == BUF_IN ? in[d.fft] : out[d.fft];
-            o.hsegs[i].out = out[d.fft];
-        }
-        // the table may still be read by work enqueued earlier on this stream
-        e = hipStreamSynchronize(s);
-        if (e == hipSuccess)
-            e = hipMemcpy(o.dsegs, o.hsegs.data(), sizeof(BatchSeg) * o.hsegs.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return set_hip_error(e, "batch table upload");
-        o.in_ptrs.assign(in, in + count);
-        o.out_ptrs.assign(out, out + count);
-        o.uploaded = true;
-    }
-    const int nd = (int)o.hsegs.size();
     b->last_stream = s;
     b->used = true;
-    if (b->mode == 2) {  // one launch per stage: the stream orders the stages
-        int64_t base = 0;
-        for (int st = 0; st < 3; ++st) {
-            e = launch_batch(make_ctl(o, base, o.stage_end[st], 1), nd, o.grid, o.lds, s);
-            if (e != hipSuccess) return set_hip_error(e, "batch launch");
-            base = o.stage_end[st];
-        }
-        return FFT3D_OK;
-    }
-    const BatchCtl c = make_ctl(o, 0, o.total, 0);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    e = hipStreamIsCapturing(s, &cap);
-    if (e != hipSuccess) return set_hip_error(e, "hipStreamIsCapturing");
-    if (b->mode == 1 || cap != hipStreamCaptureStatusNone || s == nullptr) {
-        // direct launch (also when the caller is capturing this stream itself)
-        e = launch_batch(c, nd, o.grid, o.lds, s);
-        return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "batch launch");
+    if (s != nullptr) {
+        e = hipStreamIsCapturing(s, &cap);
+        if (e != hipSuccess) return set_hip_error(e, "hipStreamIsCapturing");
     }
-    if (!o.exec) {
+    // the legacy default stream cannot be captured; a stream the caller is
+    // capturing records our launches into the caller's graph
+    if (b->mode != 0 || s == nullptr || cap != hipStreamCaptureStatusNone) return issue(b, op, in, out, s);
+    CachedGraph* hit = nullptr;
+    for (auto& g : b->graphs) {
+        if (g.op != op) continue;
+        bool same = true;
+        for (int f = 0; same && f < count; ++f) same = g.in[f] == in[f] && g.out[f] == out[f];
+        if (same) {
+            hit = &g;
+            break;
+        }
+    }
+    if (!hit) {
+        if (b->graphs.size() >= kMaxGraphs) {
+            hipStreamSynchronize(s);
+            drop_graphs(b);
+        }
+        CachedGraph g;
+        g.op = op;
+        g.in.assign(in, in + count);
+        g.out.assign(out, out + count);
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return set_hip_error(e, "hipStreamBeginCapture");
-        hipError_t le = launch_batch(c, nd, o.grid, o.lds, s);
-        e = hipStreamEndCapture(s, &o.graph);
-        if (le != hipSuccess) return set_hip_error(le, "batch launch (capture)");
+        fft3d_status st = issue(b, op, in, out, s);
+        e = hipStreamEndCapture(s, &g.graph);
+        if (st != FFT3D_OK) {
+            if (g.graph) hipGraphDestroy(g.graph);
+            return st;
+        }
         if (e != hipSuccess) return set_hip_error(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&o.exec, o.graph, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            o.exec = nullptr;
+            hipGraphDestroy(g.graph);
             return set_hip_error(e, "hipGraphInstantiate");
         }
+        b->graphs.push_back(g);
+        hit = &b->graphs.back();
     }
-    e = hipGraphLaunch(o.exec, s);
+    e = hipGraphLaunch(hit->exec, s);
     return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch");
+}
+
+std::vector<double> batch_costs(const std::vector<PlanDesc>& ffts)
+{
+    std::vector<double> c;
+    for (const PlanDesc& d : ffts) {
+        const double n = (double)d.nx * d.ny * d.nz;
+        c.push_back(n * log2(std::max(2.0, n)));
+    }
+    return c;
 }
 
 }  // namespace
@@ -227,47 +219,47 @@ fft3d_status fft3d_plan_batch(fft3d_batch_t* out, int count, const int64_t* dims
     if (!out) return set_error(FFT3D_ERR_INVALID_ARG, "null plan pointer");
     *out = nullptr;
     if (count < 1 || !dims) return set_error(FFT3D_ERR_INVALID_ARG, "count >= 1 and dims required");
-    if (dtype != DT_F32) return set_error(FFT3D_ERR_UNSUPPORTED_SIZE, "batched transforms are complex64 only");
+    if (dtype != DT_F32 && dtype != DT_F64) return set_error(FFT3D_ERR_INVALID_ARG, "dtype must be 0 or 1");
     fft3d_batch_s* b = new fft3d_batch_s();
+    b->dtype = dtype;
     for (int f = 0; f < count; ++f) {
         PlanDesc d{};
         d.nx = dims[3 * f]; d.ny = dims[3 * f + 1]; d.nz = dims[3 * f + 2];
         d.dtype = dtype; d.p1 = 1; d.p2 = 1; d.r2c = 0;
-        if (!batch_length_supported(d.nx) || !batch_length_supported(d.ny) || !batch_length_supported(d.nz)) {
-            delete b;
-            return set_error(FFT3D_ERR_UNSUPPORTED_SIZE, "batched lengths must be supported lengths <= 512");
-        }
         b->ffts.push_back(d);
-    }
-    hipError_t e = hipGetDevice(&b->device);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    if (e != hipSuccess) {
-        delete b;
-        return set_hip_error(e, "device query");
-    }
-    for (const PlanDesc& d : b->ffts) {
-        for (int64_t n : {d.nx, d.ny, d.nz}) {
-            if (b->twp.count((int)n)) continue;
-            const int64_t entries = std::max<int64_t>(1, pass_twiddles_f32(n, nullptr));
-            std::vector<float> h((size_t)(2 * entries), 0.f);
-            pass_twiddles_f32(n, h.data());
-            void* p = nullptr;
-            e = hipMalloc(&p, h.size() * sizeof(float));
-            if (e == hipSuccess) e = hipMemcpy(p, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                if (p) hipFree(p);
-                fft3d_batch_destroy(b);
-                return set_hip_error(e, "twiddle upload");
-            }
-            b->twp[(int)n] = p;
-        }
-    }
-    for (int opi = 0; opi < 2; ++opi) {
-        fft3d_status st = prepare_op(b, opi);
+        const Shape sh = shape_of(d);
+        if (b->plans.count(sh)) continue;
+        fft3d_plan_t p = nullptr;
+        fft3d_status st = fft3d_plan(&p, d.nx, d.ny, d.nz, dtype, 1, 1, 0);
+        if (st == FFT3D_OK) st = fft3d_set_streams(p, 1);
         if (st != FFT3D_OK) {
-            fft3d_batch_destroy(b);
+            if (p) fft3d_destroy(p);
+            release(b);
             return st;
         }
+        b->plans[sh] = p;
+    }
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        release(b);
+        return set_hip_error(e, "hipGetDevice");
+    }
+    const int ns = std::min(kBatchStreams, count);
+    b->placement = place_batch(batch_costs(b->ffts), ns);
+    b->streams.assign(ns, nullptr);
+    b->joins.assign(ns, nullptr);
+    for (int k = 0; k < ns; ++k) {
+        e = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release(b);
+            return set_hip_error(e, "batch stream creation");
+        }
+    }
+    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        release(b);
+        return set_hip_error(e, "hipEventCreate");
     }
     *out = b;
     return FFT3D_OK;
@@ -283,22 +275,15 @@ fft3d_status fft3d_batch_inverse(fft3d_batch_t b, const void* const* in, void* c
     return run_batch(b, 1, in, out, stream);
 }
 
-fft3d_status fft3d_batch_set_lines(fft3d_batch_t b, int64_t n, int strided, int lw)
+fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int axis, int lw,
+                                          int tdiv, int split, int pad)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
-    if (!batch_length_supported(n) || strided < 0 || strided > 1 || lw < 0)
-        return set_error(FFT3D_ERR_INVALID_ARG, "bad length, layout or lines per item");
-    const int tpl = radix_plan((int)n).tpl;
-    if (lw > 0 && (lw * tpl > kBatchThreadsPerBlock || seg_lds((int)n, lw) > kMaxLdsBytes))
-        return set_error(FFT3D_ERR_INVALID_ARG, "lines per item exceed 256 threads or the LDS limit");
-    if (b->last_stream || b->used) hipStreamSynchronize(b->last_stream);
-    if (lw == 0) b->lw_override.erase({(int)n, strided});
-    else b->lw_override[{(int)n, strided}] = lw;
-    for (int opi = 0; opi < 2; ++opi) {
-        fft3d_status st = prepare_op(b, opi);
-        if (st != FFT3D_OK) return st;
-    }
-    return FFT3D_OK;
+    auto it = b->plans.find(Shape(nx, ny, nz));
+    if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
+    if (b->used) hipStreamSynchronize(b->last_stream);
+    drop_graphs(b);  // launch shapes are baked into the captured graphs
+    return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
 }
 
 fft3d_status fft3d_batch_set_mode(fft3d_batch_t b, int mode)
@@ -309,50 +294,28 @@ fft3d_status fft3d_batch_set_mode(fft3d_batch_t b, int mode)
     return FFT3D_OK;
 }
 
-fft3d_status fft3d_batch_check(fft3d_batch_t b)
-{
-    if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
-    if (!b->used) return FFT3D_OK;
-    hipError_t e = hipStreamSynchronize(b->last_stream);
-    if (e != hipSuccess) return set_hip_error(e, "hipStreamSynchronize");
-    for (int opi = 0; opi < 2; ++opi) {
-        int flag = 0;
-        if (!b->ops[opi].ctl) continue;
-        e = hipMemcpy(&flag, b->ops[opi].ctl + 1, sizeof flag, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return set_hip_error(e, "error flag read");
-        if (flag) return set_error(FFT3D_ERR_HIP, "a batched transform gave up waiting on a dependency");
-    }
-    return FFT3D_OK;
-}
-
 fft3d_status fft3d_batch_destroy(fft3d_batch_t b)
 {
-    if (!b) return FFT3D_OK;
-    if (b->used) hipStreamSynchronize(b->last_stream);
-    for (OpState& o : b->ops) free_op(o);
-    for (auto& kv : b->twp) hipFree(kv.second);
-    delete b;
+    if (b) release(b);
     return FFT3D_OK;
 }
 
-int64_t fft3d_query_batch_queue(int count, const int64_t* dims, int op, int64_t* out, int64_t cap)
+int64_t fft3d_query_batch_placement(int count, const int64_t* dims, int nstreams, int64_t* out, int64_t cap)
 {
-    if (count < 1 || !dims || (op != 0 && op != 1)) return -1;
+    if (count < 1 || !dims || nstreams < 1) return -1;
     std::vector<PlanDesc> ffts;
     for (int f = 0; f < count; ++f) {
         PlanDesc d{};
         d.nx = dims[3 * f]; d.ny = dims[3 * f + 1]; d.nz = dims[3 * f + 2];
-        if (!batch_length_supported(d.nx) || !batch_length_supported(d.ny) || !batch_length_supported(d.nz))
-            return -1;
+        if (d.nx < 1 || d.ny < 1 || d.nz < 1) return -1;
         ffts.push_back(d);
     }
-    const auto q = build_batch_queue(ffts, op == 0 ? OP_FORWARD : OP_INVERSE, nullptr, nullptr);
+    const auto per = place_batch(batch_costs(ffts), nstreams);
     std::vector<int64_t> v;
-    v.push_back((int64_t)q.size());
-    for (const auto& s : q) {
-        int64_t rec[11] = {s.fft, s.stage, s.axis, s.n, s.strided, s.lw, s.items, s.first, s.dep, s.dep_count,
-                           s.done_idx};
-        v.insert(v.end(), rec, rec + 11);
+    v.push_back((int64_t)per.size());
+    for (const auto& p : per) {
+        v.push_back((int64_t)p.size());
+        v.insert(v.end(), p.begin(), p.end());
     }
     if (out && cap >= (int64_t)v.size()) memcpy(out, v.data(), v.size() * sizeof(int64_t));
     return (int64_t)v.size();

@@ -18,14 +18,6 @@
     X(384) X(400) X(480) X(500) X(512) X(600) X(640) X(750) X(768) X(800) X(960)      \
     X(1000) X(1024) X(2048) X(4096)
 
-// Lengths the persistent batch kernel handles (one kernel, dispatching on the
-// length of each work item): the supported lengths up to 512.
-#define FFT3D_FOR_EACH_BATCH_LENGTH(X)                                                \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(25)      \
-    X(30) X(32) X(40) X(48) X(50) X(60) X(64) X(75) X(80) X(96) X(100) X(120)         \
-    X(125) X(128) X(150) X(160) X(192) X(200) X(240) X(250) X(256) X(300) X(320)      \
-    X(384) X(400) X(480) X(500) X(512)
-
 namespace fft3d {
 
 // Radix sequence of a length-n Stockham FFT.  np passes with radices r[0..np);
@@ -113,18 +105,6 @@ constexpr int pass_table_offset(const RadixPlan& p, int pass)
 constexpr int pass_table_size(const RadixPlan& p)
 {
     return p.np < 2 ? 0 : pass_table_offset(p, p.np);
-}
-
-inline bool batch_length_supported(long long n)
-{
-#define FFT3D_BLEN_CASE(L) case L:
-    switch (n) {
-        FFT3D_FOR_EACH_BATCH_LENGTH(FFT3D_BLEN_CASE)
-        return true;
-    default:
-        return false;
-    }
-#undef FFT3D_BLEN_CASE
 }
 
 inline bool length_supported(long long n)

@@ -32,40 +32,45 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     bool ok;
     LdsView<cpx<T>> L;
     LdsView<T> Ls;
+    // Lanes past the last line load a valid line (the last one) and never
+    // store: the loads then need no branch, so all of them are in flight at once.
     if (a.strided) {
         const int lw = t % a.lw;
         tj = t / a.lw;
         const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
         ok = aa < a.A;
-        base = a.off + aa + (int64_t)blockIdx.y * a.sb;
+        base = a.off + (ok ? aa : a.A - 1) + (int64_t)blockIdx.y * a.sb;
         L = LdsView<cpx<T>>{lds + lw, a.lw, 0};
         Ls = LdsView<T>{ldsr + lw, a.lw, 0};
     } else {
         tj = t % TPL;
         const int lw = t / TPL;
-        const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
-        ok = l < a.A * a.B;
-        const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
+        const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+        ok = l0 < a.A * a.B;
+        const int64_t l = ok ? l0 : a.A * a.B - 1;
+        const int64_t aa = l % a.A, bb = l / a.A;
         base = a.off + aa * a.sa + bb * a.sb;
         const int stride = N + a.pad * (N / 8);
         L = LdsView<cpx<T>>{lds + lw * stride, 1, a.pad};
         Ls = LdsView<T>{ldsr + lw * stride, 1, a.pad};
     }
-    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base;
     const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * line * (SPLIT ? sizeof(T) : sizeof(cpx<T>))));
     stage_pass_twiddles<T, N>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const int64_t se = a.se;
+    // element e of this thread's line sits (e - tj) * se past the thread base;
+    // e - tj is a compile-time constant at every call site
+    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base + tj * se;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base + tj * se;
     const bool cj = a.conj != 0;
     const T scale = (T)a.scale;
     auto load = [&](int e) -> cpx<T> {
-        cpx<T> v = ok ? in[e * se] : cpx<T>{(T)0, (T)0};
+        const cpx<T> v = in[(e - tj) * se];
         return cj ? conj(v) : v;
     };
     auto store = [&](int e, cpx<T> v) {
         if (cj) v = conj(v);
-        if (ok) out[e * se] = v * scale;
+        if (ok) out[(e - tj) * se] = v * scale;
     };
     fft_line<T, N, TPL, SPLIT>(L, Ls, tj, twl, load, store);
 }
@@ -83,12 +88,10 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     else grid = dim3((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
-    (void)attr;
-    hipLaunchKernelGGL((k_c2c<T, N, TDIV, SPLIT>), grid, dim3(threads), lds, s, a);
-    return hipGetLastError();
+    StageArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT>), grid, dim3(threads),
+                           args, lds, s);
 }
 
 // Lengths that also get the TDIV = 2, 4 and SPLIT variants.

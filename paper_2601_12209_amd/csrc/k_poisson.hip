@@ -31,10 +31,10 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     const int lw = t % a.lw, tj = t / a.lw;
     const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
     const bool ok = aa < a.A;
-    const int64_t base = a.off + aa + (int64_t)blockIdx.y * a.sb;
-    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base;
+    const int64_t base = a.off + (ok ? aa : a.A - 1) + (int64_t)blockIdx.y * a.sb;  // see k_c2c
     const int64_t se = a.se;
+    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base + tj * se;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base + tj * se;
     LdsView<cpx<T>> L{lds + lw, a.lw, 0};
     LdsView<T> Ls{nullptr, 0, 0};
     constexpr int TPL = radix_plan(N).tpl;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     const T kxy2 = kx * kx + ky * ky;
     const T scale = (T)a.scale;
 
-    auto load = [&](int e) -> cpx<T> { return ok ? in[e * se] : cpx<T>{(T)0, (T)0}; };
+    auto load = [&](int e) -> cpx<T> { return in[(e - tj) * se]; };
     auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
     fft_line<T, N, TPL, false, false, true>(L, Ls, tj, twl, load, store_lds);
     __syncthreads();
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
         return conj(L[e] * m);
     };
     auto store = [&](int e, cpx<T> v) {
-        if (ok) out[e * se] = conj(v);
+        if (ok) out[(e - tj) * se] = conj(v);
     };
     fft_line<T, N, TPL, false, true, false>(L, Ls, tj, twl, load_mul, store);
 }
@@ -72,12 +72,10 @@ static hipError_t launch_poisson_n(const StageArgs& a, hipStream_t s)
     const size_t lds = align16((size_t)a.lw * N * sizeof(cpx<T>)) + pass_table_bytes<T, N>();
     const dim3 grid((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_poisson_z<T, N>), hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)kMaxLdsBytes);
-    (void)attr;
-    hipLaunchKernelGGL((k_poisson_z<T, N>), grid, dim3(threads), lds, s, a);
-    return hipGetLastError();
+    StageArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_poisson_z<T, N>), grid, dim3(threads), args, lds,
+                           s);
 }
 
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)

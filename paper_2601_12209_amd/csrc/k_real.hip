@@ -27,9 +27,10 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int tj = t % TPL, lw = t / TPL;
-    const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
-    const bool ok = l < a.A * a.B;
-    const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
+    const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+    const bool ok = l0 < a.A * a.B;
+    const int64_t l = ok ? l0 : a.A * a.B - 1;  // past the end: load the last line, store nothing
+    const int64_t aa = l % a.A, bb = l / a.A;
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     LdsView<T> Ls{nullptr, 0, 0};
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * H * sizeof(cpx<T>)));
     stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
-    auto load = [&](int e) -> cpx<T> { return ok ? in[e] : cpx<T>{(T)0, (T)0}; };
+    auto load = [&](int e) -> cpx<T> { return in[e]; };
     auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
     fft_line<T, H, TPL, false, false, true>(L, Ls, tj, twl, load, store_lds);
     __syncthreads();
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int tj = t % TPL, lw = t / TPL;
-    const int64_t l = (int64_t)blockIdx.x * a.lw + lw;
-    const bool ok = l < a.A * a.B;
-    const int64_t aa = ok ? l % a.A : 0, bb = ok ? l / a.A : 0;
+    const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+    const bool ok = l0 < a.A * a.B;
+    const int64_t l = ok ? l0 : a.A * a.B - 1;  // past the end: load the last line, store nothing
+    const int64_t aa = l % a.A, bb = l / a.A;
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const T wgt = a.weight ? (T)0.5 : (T)1;
     for (int k = tj; k <= H; k += TPL) {
-        cpx<T> v = ok ? in[k] : cpx<T>{(T)0, (T)0};
+        cpx<T> v = in[k];
         if (k == 0 || k == H) v.im = (T)0;
         else v = v * wgt;
         L[k] = v;
@@ -111,19 +113,16 @@ static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
         const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
         if (grid.x == 0) return hipSuccess;
         if (r2c) {
-            static const hipError_t attr = hipFuncSetAttribute(
-                reinterpret_cast<const void*>(&k_r2c_x<T, N>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
-            (void)attr;
-            hipLaunchKernelGGL((k_r2c_x<T, N>), grid, dim3(threads), lds, s, a);
+            StageArgs arg = a;
+            void* args[] = {&arg};
+            return hipLaunchKernel(reinterpret_cast<const void*>(&k_r2c_x<T, N>), grid, dim3(threads), args,
+                                   lds, s);
         } else {
-            static const hipError_t attr = hipFuncSetAttribute(
-                reinterpret_cast<const void*>(&k_c2r_x<T, N>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
-            (void)attr;
-            hipLaunchKernelGGL((k_c2r_x<T, N>), grid, dim3(threads), lds, s, a);
+            StageArgs arg = a;
+            void* args[] = {&arg};
+            return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2r_x<T, N>), grid, dim3(threads), args,
+                                   lds, s);
         }
-        return hipGetLastError();
     }
 }
 

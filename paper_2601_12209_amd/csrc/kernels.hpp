@@ -21,11 +21,4 @@ hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s);
 hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s);
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s);
 
-// Persistent batch kernel (preceded by a fill kernel that zeroes the head,
-// ndone counters and the error flag) on `grid` workgroups with `lds` bytes.
-struct BatchCtl;
-hipError_t launch_batch(const BatchCtl& c, int ndone, int grid, size_t lds, hipStream_t s);
-int batch_max_blocks_per_cu(size_t lds);
-constexpr int kBatchThreadsPerBlock = 256;
-
 }  // namespace fft3d

@@ -296,80 +296,22 @@ int64_t pass_twiddles_f32(int64_t n, float* out)
 
 namespace fft3d {
 
-int batch_default_lw(int n, int strided)
+std::vector<std::vector<int>> place_batch(const std::vector<double>& cost, int nstreams)
 {
-    (void)strided;
-    const int tpl = radix_plan(n).tpl;
-    int lw = 256 / tpl;
-    if (lw < 1) lw = 1;
-    // keep the LDS tile (lw + 1 lines) within 48 KiB so several workgroups fit per CU
-    while (lw > 1 && (size_t)(lw + 1) * n * 8 > 48 * 1024) --lw;
-    return lw;
-}
-
-std::vector<BatchSegDesc> build_batch_queue(const std::vector<PlanDesc>& ffts, int op,
-                                            int (*lw_of)(void*, int, int), void* ctx)
-{
-    std::vector<BatchSegDesc> per_stage[3];
-    const bool inv = op != OP_FORWARD;
-    for (int f = 0; f < (int)ffts.size(); ++f) {
-        const PlanDesc& d = ffts[f];
-        const int axes_fwd[3] = {0, 1, 2}, axes_inv[3] = {2, 1, 0};
-        for (int st = 0; st < 3; ++st) {
-            const int axis = inv ? axes_inv[st] : axes_fwd[st];
-            BatchSegDesc s{};
-            s.fft = f;
-            s.stage = st;
-            s.axis = axis;
-            s.conj = inv ? 1 : 0;
-            s.scale = (op == OP_INVERSE && st == 2) ? 1.0 / ((double)d.nx * d.ny * d.nz) : 1.0;
-            s.src = st == 0 ? BUF_IN : BUF_OUT;
-            const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
-            if (axis == 0) {
-                s.n = (int)nx; s.strided = 0;
-                s.A = ny; s.B = nz; s.off = 0; s.sa = nx; s.sb = nx * ny; s.se = 1;
-            } else if (axis == 1) {
-                s.n = (int)ny; s.strided = 1;
-                s.A = nx; s.B = nz; s.off = 0; s.sa = 1; s.sb = nx * ny; s.se = nx;
-            } else {
-                s.n = (int)nz; s.strided = 1;
-                s.A = nx; s.B = ny; s.off = 0; s.sa = 1; s.sb = nx; s.se = nx * ny;
-            }
-            s.lw = lw_of ? lw_of(ctx, s.n, s.strided) : batch_default_lw(s.n, s.strided);
-            if (s.lw < 1) s.lw = 1;
-            if (s.strided) {
-                s.blocks_a = (s.A + s.lw - 1) / s.lw;
-                s.items = s.blocks_a * s.B;
-            } else {
-                s.blocks_a = 0;
-                s.items = (s.A * s.B + s.lw - 1) / s.lw;
-            }
-            per_stage[st].push_back(s);
-        }
+    if (nstreams < 1) nstreams = 1;
+    std::vector<int> order(cost.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<int>> per(nstreams);
+    std::vector<double> load(nstreams, 0.0);
+    for (int f : order) {
+        int best = 0;
+        for (int s = 1; s < nstreams; ++s)
+            if (load[s] < load[best]) best = s;
+        per[best].push_back(f);
+        load[best] += cost[f];
     }
-    std::vector<BatchSegDesc> q;
-    std::vector<int> seg_of((size_t)ffts.size() * 3, -1);
-    int64_t first = 0;
-    for (int st = 0; st < 3; ++st) {
-        auto& v = per_stage[st];
-        std::stable_sort(v.begin(), v.end(),
-                         [](const BatchSegDesc& a, const BatchSegDesc& b) { return a.items > b.items; });
-        for (auto& s : v) {
-            s.first = first;
-            first += s.items;
-            s.done_idx = (int)q.size();
-            seg_of[(size_t)s.fft * 3 + st] = s.done_idx;
-            if (st == 0) {
-                s.dep = -1;
-                s.dep_count = 0;
-            } else {
-                s.dep = seg_of[(size_t)s.fft * 3 + st - 1];
-                s.dep_count = q[s.dep].items;
-            }
-            q.push_back(s);
-        }
-    }
-    return q;
+    return per;
 }
 
 }  // namespace fft3d

@@ -95,25 +95,9 @@ int64_t pass_twiddles_f32(int64_t n, float* out);
 
 // ---------------------------------------------------------------- batches
 
-// One (FFT, stage) segment of the persistent kernel's queue (host view).
-struct BatchSegDesc {
-    int fft, stage, axis, n, strided, lw, conj;
-    double scale;
-    int src;  // BUF_IN or BUF_OUT of this FFT
-    int64_t A, B, off, sa, sb, se, blocks_a, items, first;
-    int dep, done_idx;
-    int64_t dep_count;
-};
-
-// Lines per item for length n (strided or contiguous lines) with 256-thread
-// workgroups: as many lines as fit, which for strided lines also makes the
-// row segments as long as possible.
-int batch_default_lw(int n, int strided);
-
-// Queue of a batch: every FFT's stages (forward x, y, z; inverse z, y, x),
-// all first-stage items before any second-stage item, and within a stage the
-// FFTs with the most items first.  lw_of(n, strided) gives lines per item.
-std::vector<BatchSegDesc> build_batch_queue(const std::vector<PlanDesc>& ffts, int op,
-                                            int (*lw_of)(void*, int, int), void* ctx);
+// Placement of the transforms of a batch on nstreams streams (Alg. 3 with
+// estimated costs): transforms in decreasing cost, each on the currently
+// least-loaded stream.  Returns, per stream, the transforms in issue order.
+std::vector<std::vector<int>> place_batch(const std::vector<double>& cost, int nstreams);
 
 }  // namespace fft3d

@@ -64,7 +64,7 @@ struct fft3d_plan_s {
     PlanDesc d{};
     int device = 0;
     int nstreams = kDefaultStreams;
-    std::vector<hipStream_t> streams;  // kMaxStreams, created up front
+    std::vector<hipStream_t> streams;  // kMaxStreams slots, created when a multi-stream issue needs them
     std::vector<hipEvent_t> events;    // one per task of the largest pipeline
     hipEvent_t fork = nullptr;
     void* tw[3] = {nullptr, nullptr, nullptr};   // per-axis forward root tables
@@ -269,6 +269,25 @@ const Pipeline& get_pipeline(fft3d_plan_s* p, int op)
     return p->pipes[op];
 }
 
+// Whether calls fork onto the plan's streams: only with more than one stream
+// and more than one tile per stage (a 1x1 grid issues straight onto the
+// caller's stream, in task order).
+bool forks(const fft3d_plan_s* p) { return p->nstreams > 1 && (int64_t)p->d.p1 * p->d.p2 > 1; }
+
+// Create the first `count` streams if they do not exist yet.
+hipError_t ensure_streams(fft3d_plan_s* p, int count)
+{
+    for (int s = 0; s < count; ++s) {
+        if (p->streams[s]) continue;
+        hipError_t e = hipStreamCreateWithFlags(&p->streams[s], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            p->streams[s] = nullptr;
+            return e;
+        }
+    }
+    return hipSuccess;
+}
+
 // Timed issue: every stage is its own fork/join region on the caller's stream,
 // with a timing event after it, so stage durations can be read back.
 fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipStream_t user)
@@ -276,7 +295,7 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
     hipError_t e = hipEventRecord(p->tev[0], user);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
     for (int st = 0; st < (int)pl.stages.size(); ++st) {
-        const bool fork = p->nstreams > 1;
+        const bool fork = forks(p);
         if (fork) {
             e = hipEventRecord(p->fork, user);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
@@ -321,7 +340,7 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (p->timing) return run_timed(p, pl, bufs, user);
-    if (p->nstreams == 1) {
+    if (!forks(p)) {
         for (const Task& t : pl.tasks) {
             const Stage& st = pl.stages[t.stage];
             e = launch_task(p, st, make_args(p, st, t.box, bufs), user);
@@ -450,10 +469,9 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         p->ws_owned = true;
     }
     p->streams.assign(kMaxStreams, nullptr);
-    for (int s = 0; s < kMaxStreams; ++s) {
-        e = hipStreamCreateWithFlags(&p->streams[s], hipStreamNonBlocking);
+    if (forks(p)) {
+        e = ensure_streams(p, p->nstreams);
         if (e != hipSuccess) {
-            p->streams[s] = nullptr;
             release(p);
             return hip_fail(e, "hipStreamCreate");
         }
@@ -559,7 +577,8 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
     if (ws && bytes < need) return fail(FFT3D_ERR_WORKSPACE, "workspace smaller than fft3d_workspace_bytes");
     if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     // the old workspace may still be in use by enqueued work
-    for (hipStream_t s : p->streams) hipStreamSynchronize(s);
+    for (hipStream_t s : p->streams)
+        if (s) hipStreamSynchronize(s);
     if (ws) {
         if (p->ws_owned) hipFree(p->ws);
         p->ws = ws;
@@ -582,6 +601,10 @@ fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
     if (nstreams < 1 || nstreams > kMaxStreams) return fail(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
     p->nstreams = nstreams;
+    if (forks(p)) {
+        hipError_t e = ensure_streams(p, nstreams);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
     return FFT3D_OK;
 }
 

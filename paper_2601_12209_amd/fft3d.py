@@ -178,35 +178,39 @@ class Plan:
 
 
 class BatchPlan:
-    """Many complex64 3D FFTs of different shapes in one persistent launch."""
+    """Many 3D FFTs of different shapes issued as one task graph."""
 
-    def __init__(self, shapes, mode=0):
+    def __init__(self, shapes, dtype=torch.complex64, mode=0):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.code = _dtype_code(dtype)
         dims = (ctypes.c_int64 * (3 * len(self.shapes)))()
         for i, (nz, ny, nx) in enumerate(self.shapes):
             dims[3 * i], dims[3 * i + 1], dims[3 * i + 2] = nx, ny, nz
         h = ctypes.c_void_p()
-        check(_lib.lib().fft3d_plan_batch(ctypes.byref(h), len(self.shapes), dims, C64), "fft3d_plan_batch")
+        check(_lib.lib().fft3d_plan_batch(ctypes.byref(h), len(self.shapes), dims, self.code),
+              "fft3d_plan_batch")
         self._h = h
         self.set_mode(mode)
 
     def set_mode(self, mode: int):
         check(_lib.lib().fft3d_batch_set_mode(self._h, int(mode)), "fft3d_batch_set_mode")
 
-    def set_lines(self, n: int, strided: bool, lw: int):
-        check(_lib.lib().fft3d_batch_set_lines(self._h, int(n), int(bool(strided)), int(lw)),
-              "fft3d_batch_set_lines")
+    def set_stage_config(self, shape, axis: int, lw: int, tdiv: int = 1, split: int = 0, pad: int = 0):
+        nz, ny, nx = shape
+        check(_lib.lib().fft3d_batch_set_stage_config(self._h, nx, ny, nz, int(axis), int(lw), int(tdiv),
+                                                      int(split), int(pad)), "fft3d_batch_set_stage_config")
 
     def _run(self, fn, xs, outs, stream):
+        dt = _COMPLEX[self.code]
         if len(xs) != len(self.shapes):
             raise ValueError("one input per transform")
         for x, s in zip(xs, self.shapes):
-            if not (x.is_cuda and x.dtype == torch.complex64 and tuple(x.shape) == s and x.is_contiguous()):
-                raise ValueError(f"inputs must be contiguous complex64 CUDA tensors of shapes {self.shapes}")
+            if not (x.is_cuda and x.dtype == dt and tuple(x.shape) == s and x.is_contiguous()):
+                raise ValueError(f"inputs must be contiguous {dt} CUDA tensors of shapes {self.shapes}")
         if outs is None:
             outs = [torch.empty_like(x) for x in xs]
         for o, s in zip(outs, self.shapes):
-            if not (o.is_cuda and o.dtype == torch.complex64 and tuple(o.shape) == s and o.is_contiguous()):
+            if not (o.is_cuda and o.dtype == dt and tuple(o.shape) == s and o.is_contiguous()):
                 raise ValueError("outputs must match the inputs")
         n = len(xs)
         ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
@@ -220,9 +224,6 @@ class BatchPlan:
     def inverse(self, xs, outs=None, stream=None):
         return self._run(_lib.lib().fft3d_batch_inverse, xs, outs, stream)
 
-    def check(self):
-        check(_lib.lib().fft3d_batch_check(self._h), "fft3d_batch_check")
-
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().fft3d_batch_destroy(self._h)
@@ -235,21 +236,25 @@ class BatchPlan:
             pass
 
 
-def query_batch_queue(shapes, op=0):
-    """Decoded work queue of a batch (host-only)."""
+def query_batch_placement(shapes, nstreams=4):
+    """Transform indices per stream, in issue order (host-only)."""
     n = len(shapes)
     dims = (ctypes.c_int64 * (3 * n))()
     for i, (nz, ny, nx) in enumerate(shapes):
         dims[3 * i], dims[3 * i + 1], dims[3 * i + 2] = nx, ny, nz
     L = _lib.lib()
-    need = L.fft3d_query_batch_queue(n, dims, op, None, 0)
+    need = L.fft3d_query_batch_placement(n, dims, nstreams, None, 0)
     if need < 0:
         raise ValueError("invalid batch")
     buf = (ctypes.c_int64 * need)()
-    L.fft3d_query_batch_queue(n, dims, op, buf, need)
+    L.fft3d_query_batch_placement(n, dims, nstreams, buf, need)
     v = list(buf)
-    keys = ("fft", "stage", "axis", "n", "strided", "lw", "items", "first", "dep", "dep_count", "done_idx")
-    return [dict(zip(keys, v[1 + 11 * i: 12 + 11 * i])) for i in range(v[0])]
+    out, pos = [], 1
+    for _ in range(v[0]):
+        k = v[pos]
+        out.append(v[pos + 1:pos + 1 + k])
+        pos += 1 + k
+    return out
 
 
 _cache: dict = {}

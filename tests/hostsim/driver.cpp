@@ -1,0 +1,294 @@
+// Drives the library's C ABI through every host path the GPU tests take —
+// plans of all test shapes and pencil grids, every stream count, every launch
+// shape the library accepts, real-to-complex plans with the Poisson
+// operations and caller workspaces, timing mode, and batches in all three
+// issue modes including graph caching, pointer changes and capture by the
+// caller — against the host-only HIP stand-in, so AddressSanitizer and the
+// stand-in's launch checks see all of it.  Prints "hostsim ok" and exits 0
+// when nothing was flagged.
+//
+// Usage: driver [nbatch nx ny nz ...]   (the batch shapes, x fastest)
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/fft3d.h"
+
+extern "C" int hostsim_violations();
+extern "C" long hostsim_launches();
+extern "C" size_t hostsim_live_allocations();
+
+namespace {
+
+int g_failures = 0;
+
+#define EXPECT(cond)                                                                              \
+    do {                                                                                          \
+        if (!(cond)) {                                                                            \
+            fprintf(stderr, "%s:%d: expectation failed: %s (%s)\n", __FILE__, __LINE__, #cond,    \
+                    fft3d_last_error());                                                          \
+            ++g_failures;                                                                         \
+        }                                                                                         \
+    } while (0)
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    explicit Buf(size_t b) : bytes(b) { EXPECT(hipMalloc(&p, b) == hipSuccess); }
+    ~Buf() { (void)hipFree(p); }
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+};
+
+size_t es_of(int dtype) { return dtype == FFT3D_C128 ? 16 : 8; }
+
+hipStream_t make_stream()
+{
+    hipStream_t s = nullptr;
+    EXPECT(hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess);
+    return s;
+}
+
+// (nx, ny, nz), p1, p2
+struct Case {
+    int64_t nx, ny, nz;
+    int p1, p2;
+};
+
+void c2c_cases(hipStream_t user)
+{
+    const Case cases[] = {{8, 8, 8, 1, 1},      {32, 32, 32, 2, 2},   {20, 12, 16, 2, 3},    {4, 6, 5, 2, 2},
+                          {1, 1, 1, 1, 1},      {8, 4, 1, 1, 1},      {16, 1, 3, 1, 1},      {100, 48, 64, 3, 3},
+                          {24, 30, 25, 4, 5},   {100, 120, 128, 4, 4}, {160, 160, 80, 2, 2}, {48, 48, 48, 1, 1},
+                          {512, 64, 64, 1, 1},  {16, 8, 512, 1, 1},   {8, 1024, 16, 2, 2},   {2, 2, 4096, 1, 1},
+                          {4096, 2, 2, 1, 1},   {32, 32, 32, 1, 1}};
+    for (const Case& c : cases) {
+        for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+            const size_t bytes = (size_t)c.nx * c.ny * c.nz * es_of(dtype);
+            Buf in(bytes), out(bytes);
+            fft3d_plan_t p = nullptr;
+            EXPECT(fft3d_plan(&p, c.nx, c.ny, c.nz, dtype, c.p1, c.p2, 0) == FFT3D_OK);
+            if (!p) continue;
+            for (int ns : {1, 2, 4, 16}) {
+                EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
+            }
+            EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
+            if (bytes >= 2 * es_of(dtype))  // partial overlap
+                EXPECT(fft3d_forward(p, in.p, (char*)in.p + es_of(dtype), user) == FFT3D_ERR_ALIAS);
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    fft3d_plan_t p = nullptr;
+    EXPECT(fft3d_plan(&p, 8, 8, 7, FFT3D_C64, 1, 1, 0) == FFT3D_ERR_UNSUPPORTED_SIZE);
+    EXPECT(fft3d_plan(&p, 8, 8, 8, FFT3D_C64, 9, 1, 0) == FFT3D_ERR_INVALID_ARG);
+    EXPECT(fft3d_plan(&p, 8, 8, 8, 5, 1, 1, 0) == FFT3D_ERR_INVALID_ARG);
+}
+
+// Every (axis, lw, tdiv, split, pad) the library accepts, one fresh plan each.
+void variant_cases(hipStream_t user)
+{
+    const Case shapes[] = {{512, 64, 64, 1, 1}, {64, 16, 512, 1, 1}, {32, 512, 16, 1, 1}, {256, 256, 8, 1, 1},
+                           {8, 1024, 32, 1, 1}};
+    int accepted = 0;
+    for (const Case& c : shapes) {
+        for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+            const size_t bytes = (size_t)c.nx * c.ny * c.nz * es_of(dtype);
+            Buf in(bytes), out(bytes);
+            for (int axis = 0; axis < 3; ++axis)
+                for (int lw = 1; lw <= 64; lw *= 2)
+                    for (int tdiv : {1, 2, 4})
+                        for (int split = 0; split < 2; ++split)
+                            for (int pad = 0; pad < (axis == 0 ? 2 : 1); ++pad) {
+                                fft3d_plan_t p = nullptr;
+                                EXPECT(fft3d_plan(&p, c.nx, c.ny, c.nz, dtype, 1, 1, 0) == FFT3D_OK);
+                                if (!p) continue;
+                                if (fft3d_set_stage_config(p, axis, lw, tdiv, split, pad) == FFT3D_OK) {
+                                    ++accepted;
+                                    EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                                    EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+                                }
+                                EXPECT(fft3d_destroy(p) == FFT3D_OK);
+                            }
+        }
+    }
+    EXPECT(accepted > 100);
+}
+
+void r2c_cases(hipStream_t user)
+{
+    const Case cases[] = {{8, 8, 8, 1, 1},     {10, 6, 8, 2, 2},    {12, 10, 15, 3, 2},  {64, 32, 16, 1, 1},
+                          {20, 12, 16, 2, 3},  {40, 24, 32, 2, 2},  {2, 1, 1, 1, 1},     {512, 16, 8, 1, 1},
+                          {256, 64, 64, 4, 4}, {100, 30, 24, 2, 5}, {4096, 2, 2, 1, 1}};
+    for (const Case& c : cases) {
+        for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+            const size_t es = es_of(dtype);
+            const size_t real_bytes = (size_t)c.nx * c.ny * c.nz * es / 2;
+            const size_t half_bytes = (size_t)(c.nx / 2 + 1) * c.ny * c.nz * es;
+            Buf r(real_bytes), r2(real_bytes), h(half_bytes);
+            fft3d_plan_t p = nullptr;
+            EXPECT(fft3d_plan(&p, c.nx, c.ny, c.nz, dtype, c.p1, c.p2, 1) == FFT3D_OK);
+            if (!p) continue;
+            for (int ns : {1, 3, 4}) {
+                EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, h.p, r2.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, h.p, r2.p, nullptr) == FFT3D_OK);
+                EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+                EXPECT(fft3d_poisson(p, r.p, r.p, user) == FFT3D_OK);
+                EXPECT(fft3d_poisson_adjoint(p, r2.p, r.p, user) == FFT3D_OK);
+            }
+            EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
+            // caller workspace, then back to a plan-owned one
+            const size_t wsb = fft3d_workspace_bytes(p);
+            EXPECT(wsb == half_bytes);
+            {
+                Buf ws(wsb);
+                EXPECT(fft3d_set_workspace(p, ws.p, wsb - 1) == FFT3D_ERR_WORKSPACE);
+                EXPECT(fft3d_set_workspace(p, ws.p, wsb) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+                EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, ws.p, r2.p, user) == FFT3D_ERR_ALIAS);
+                EXPECT(fft3d_set_workspace(p, nullptr, 0) == FFT3D_OK);
+            }
+            EXPECT(fft3d_poisson_adjoint(p, r.p, r2.p, user) == FFT3D_OK);
+            // timing mode
+            EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+            float ms[8];
+            EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) >= 3);
+            EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) >= 3);
+            EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    fft3d_plan_t p = nullptr;
+    EXPECT(fft3d_plan(&p, 9, 8, 8, FFT3D_C64, 1, 1, 1) == FFT3D_ERR_UNSUPPORTED_SIZE);
+}
+
+// A multi-stream plan launched inside a capture the caller began.
+void caller_capture_plan(hipStream_t user)
+{
+    fft3d_plan_t p = nullptr;
+    EXPECT(fft3d_plan(&p, 32, 24, 20, FFT3D_C64, 2, 3, 0) == FFT3D_OK);
+    if (!p) return;
+    Buf in(32 * 24 * 20 * 8), out(32 * 24 * 20 * 8);
+    EXPECT(fft3d_set_streams(p, 4) == FFT3D_OK);
+    EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
+    EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+    EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+    hipGraph_t g = nullptr;
+    EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
+    if (g) (void)hipGraphDestroy(g);
+    EXPECT(fft3d_destroy(p) == FFT3D_OK);
+}
+
+void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
+{
+    const int n = (int)dims.size() / 3;
+    for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+        std::vector<Buf*> bufs, bufs2;
+        std::vector<const void*> in;
+        std::vector<void*> out, in2;
+        for (int f = 0; f < n; ++f) {
+            const size_t b = (size_t)dims[3 * f] * dims[3 * f + 1] * dims[3 * f + 2] * es_of(dtype);
+            bufs.push_back(new Buf(b));
+            bufs2.push_back(new Buf(b));
+            in.push_back(bufs.back()->p);
+            out.push_back(bufs2.back()->p);
+            in2.push_back(bufs.back()->p);
+        }
+        fft3d_batch_t b = nullptr;
+        EXPECT(fft3d_plan_batch(&b, n, dims.data(), dtype) == FFT3D_OK);
+        if (!b) continue;
+        for (int mode : {2, 1, 0}) {
+            EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
+            for (int rep = 0; rep < 3; ++rep) {
+                EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+                EXPECT(fft3d_batch_inverse(b, out.data(), out.data(), user) == FFT3D_OK);
+                EXPECT(fft3d_batch_forward(b, in.data(), out.data(), nullptr) == FFT3D_OK);
+            }
+        }
+        // more pointer sets than cached graphs (mode 0 on a stream: one graph each)
+        EXPECT(fft3d_batch_set_mode(b, 0) == FFT3D_OK);
+        for (int rep = 0; rep < 12; ++rep) {
+            std::vector<Buf*> fresh;
+            std::vector<void*> o2;
+            for (int f = 0; f < n; ++f) {
+                fresh.push_back(new Buf(bufs2[f]->bytes));
+                o2.push_back(fresh.back()->p);
+            }
+            EXPECT(fft3d_batch_forward(b, in.data(), o2.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_batch_forward(b, in.data(), in2.data(), user) == FFT3D_OK);  // in place
+            EXPECT(hipStreamSynchronize(user) == hipSuccess);
+            for (Buf* x : fresh) delete x;
+        }
+        // stage configs of each distinct shape drop the cached graphs
+        for (int f = 0; f < n; ++f) {
+            EXPECT(fft3d_batch_set_stage_config(b, dims[3 * f], dims[3 * f + 1], dims[3 * f + 2], 1, 4, 1, 0, 0) ==
+                   FFT3D_OK);
+        }
+        EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+        EXPECT(fft3d_batch_set_stage_config(b, 3, 3, 3, 0, 1, 1, 0, 0) == FFT3D_ERR_INVALID_ARG);
+        EXPECT(fft3d_batch_set_mode(b, 3) == FFT3D_ERR_INVALID_ARG);
+        // the caller captures the batch into its own graph
+        for (int mode : {0, 1}) {
+            EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
+            EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
+            EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+            hipGraph_t g = nullptr;
+            EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
+            if (g) (void)hipGraphDestroy(g);
+        }
+        // overlapping outputs of two transforms
+        if (n >= 2) {
+            std::vector<void*> bad(out.begin(), out.end());
+            bad[1] = bad[0];
+            EXPECT(fft3d_batch_forward(b, in.data(), bad.data(), user) == FFT3D_ERR_ALIAS);
+        }
+        EXPECT(fft3d_batch_destroy(b) == FFT3D_OK);
+        for (Buf* x : bufs) delete x;
+        for (Buf* x : bufs2) delete x;
+    }
+    fft3d_batch_t b = nullptr;
+    const int64_t bad[3] = {8, 8, 7};
+    EXPECT(fft3d_plan_batch(&b, 1, bad, FFT3D_C64) == FFT3D_ERR_UNSUPPORTED_SIZE);
+    EXPECT(b == nullptr);
+}
+
+}  // namespace
+
+int main(int argc, char** argv)
+{
+    std::vector<int64_t> dims;
+    if (argc > 1) {
+        const int n = atoi(argv[1]);
+        for (int i = 0; i < 3 * n && 2 + i < argc; ++i) dims.push_back(atoll(argv[2 + i]));
+    }
+    if (dims.empty()) dims = {48, 48, 48, 64, 64, 64, 100, 120, 128, 160, 160, 80};
+    hipStream_t user = make_stream();
+    const size_t live0 = hostsim_live_allocations();
+    c2c_cases(user);
+    variant_cases(user);
+    r2c_cases(user);
+    caller_capture_plan(user);
+    batch_cases(dims, user);
+    (void)hipStreamDestroy(user);
+    const size_t leaked = hostsim_live_allocations() - live0;
+    EXPECT(leaked == 0);
+    printf("launches %ld, violations %d, failures %d, leaked allocations %zu\n", hostsim_launches(),
+           hostsim_violations(), g_failures, leaked);
+    if (hostsim_violations() == 0 && g_failures == 0) {
+        printf("hostsim ok\n");
+        return 0;
+    }
+    return 1;
+}

@@ -1,0 +1,482 @@
+// Host-only stand-in for the HIP runtime, used to run the library's host code
+// (planner, executor, batch task graphs, C ABI) without a GPU, under
+// AddressSanitizer and UndefinedBehaviorSanitizer.
+//
+// Device memory is host memory from aligned_alloc; kernels are not executed.
+// Instead every stage-kernel launch is checked: thread count and LDS bytes
+// against the gfx950 limits, and the element range that the lines of the tile
+// read and write (from the launch arguments, following each kernel's
+// addressing) against the allocation it starts in.  Streams, events and graph
+// capture are modelled closely enough to reject what the real runtime rejects
+// or what would be wrong on it: work on a destroyed stream or event, a
+// synchronisation inside a capture, a capture that ends with a forked stream
+// not joined back, destroying a stream that is still capturing.
+//
+// Violations are counted; hostsim_violations() reports them to the driver.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <set>
+#include <vector>
+
+#include "../../paper_2601_12209_amd/csrc/fft_lengths.hpp"
+#include "../../paper_2601_12209_amd/csrc/kernels.hpp"
+#include "../../paper_2601_12209_amd/csrc/stage_args.hpp"
+
+namespace {
+
+constexpr unsigned kStreamMagic = 0x57524541u;
+constexpr unsigned kEventMagic = 0x45564e54u;
+constexpr unsigned kGraphMagic = 0x47524150u;
+constexpr unsigned kExecMagic = 0x45584543u;
+
+std::map<uintptr_t, size_t> g_allocs;  // base -> bytes
+int g_violations = 0;
+long g_launches = 0;
+int g_next_capture = 1;
+
+void violation(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    fprintf(stderr, "hostsim violation: ");
+    vfprintf(stderr, fmt, ap);
+    fprintf(stderr, "\n");
+    va_end(ap);
+    ++g_violations;
+}
+
+}  // namespace
+
+struct ihipStream_t {
+    unsigned magic = kStreamMagic;
+    int capture = 0;                 // id of the capture this stream takes part in
+    ihipStream_t* origin = nullptr;  // the stream the capture began on
+    long ops = 0;                    // work items enqueued so far
+};
+
+struct ihipEvent_t {
+    unsigned magic = kEventMagic;
+    ihipStream_t* stream = nullptr;
+    long ops = -1;
+    int capture = 0;
+};
+
+struct ihipGraph {
+    unsigned magic = kGraphMagic;
+};
+
+struct hipGraphExec {
+    unsigned magic = kExecMagic;
+};
+
+namespace {
+
+struct WaitEdge {
+    ihipStream_t* waiter;
+    ihipStream_t* target;
+    long target_ops;
+};
+std::map<int, std::vector<ihipStream_t*>> g_members;  // capture id -> streams in it
+std::map<int, std::vector<WaitEdge>> g_edges;         // capture id -> cross-stream waits
+
+bool stream_ok(hipStream_t s, const char* what)
+{
+    if (s == nullptr) return true;  // the null stream
+    if (s->magic != kStreamMagic) {
+        violation("%s: invalid or destroyed stream", what);
+        return false;
+    }
+    return true;
+}
+
+bool event_ok(hipEvent_t e, const char* what)
+{
+    if (!e || e->magic != kEventMagic) {
+        violation("%s: invalid or destroyed event", what);
+        return false;
+    }
+    return true;
+}
+
+// Allocation containing [p, p + bytes), or violation.
+bool in_alloc(const void* p, size_t bytes, const char* what)
+{
+    const uintptr_t a = (uintptr_t)p;
+    auto it = g_allocs.upper_bound(a);
+    if (it == g_allocs.begin()) {
+        violation("%s: %p is not in any allocation", what, p);
+        return false;
+    }
+    --it;
+    if (a + bytes > it->first + it->second) {
+        violation("%s: [%p, +%zu) runs past its allocation [%p, +%zu)", what, p, bytes, (void*)it->first,
+                  it->second);
+        return false;
+    }
+    return true;
+}
+
+void enqueue(hipStream_t s) { if (s) ++s->ops; }
+
+}  // namespace
+
+extern "C" int hostsim_violations() { return g_violations; }
+extern "C" long hostsim_launches() { return g_launches; }
+extern "C" size_t hostsim_live_allocations() { return g_allocs.size(); }
+
+// ------------------------------------------------------------------- runtime
+
+hipError_t hipGetDevice(int* d)
+{
+    *d = 0;
+    return hipSuccess;
+}
+
+hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidDevice; }
+
+const char* hipGetErrorString(hipError_t e)
+{
+    static char buf[64];
+    snprintf(buf, sizeof buf, "stub error %d", (int)e);
+    return buf;
+}
+
+hipError_t hipMalloc(void** p, size_t bytes)
+{
+    if (!p) return hipErrorInvalidValue;
+    if (bytes == 0) {
+        *p = nullptr;
+        return hipSuccess;
+    }
+    const size_t r = (bytes + 255) & ~(size_t)255;
+    void* m = aligned_alloc(256, r);
+    if (!m) return hipErrorOutOfMemory;
+    g_allocs[(uintptr_t)m] = bytes;
+    *p = m;
+    return hipSuccess;
+}
+
+hipError_t hipFree(void* p)
+{
+    if (!p) return hipSuccess;
+    auto it = g_allocs.find((uintptr_t)p);
+    if (it == g_allocs.end()) {
+        violation("hipFree of %p, not an allocation base", p);
+        return hipErrorInvalidValue;
+    }
+    g_allocs.erase(it);
+    free(p);
+    return hipSuccess;
+}
+
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+{
+    if (kind == hipMemcpyHostToDevice || kind == hipMemcpyDeviceToDevice) in_alloc(dst, bytes, "hipMemcpy dst");
+    if (kind == hipMemcpyDeviceToHost || kind == hipMemcpyDeviceToDevice) in_alloc(src, bytes, "hipMemcpy src");
+    memcpy(dst, src, bytes);
+    return hipSuccess;
+}
+
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned int)
+{
+    *s = new ihipStream_t();
+    return hipSuccess;
+}
+
+hipError_t hipStreamDestroy(hipStream_t s)
+{
+    if (!s) return hipErrorInvalidHandle;
+    if (!stream_ok(s, "hipStreamDestroy")) return hipErrorInvalidHandle;
+    if (s->capture) violation("hipStreamDestroy of a stream that is capturing");
+    s->magic = 0;
+    delete s;
+    return hipSuccess;
+}
+
+hipError_t hipStreamSynchronize(hipStream_t s)
+{
+    if (!stream_ok(s, "hipStreamSynchronize")) return hipErrorInvalidHandle;
+    if (s && s->capture) {
+        violation("hipStreamSynchronize inside a capture");
+        return hipErrorStreamCaptureUnsupported;
+    }
+    return hipSuccess;
+}
+
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned)
+{
+    *e = new ihipEvent_t();
+    return hipSuccess;
+}
+
+hipError_t hipEventCreate(hipEvent_t* e) { return hipEventCreateWithFlags(e, 0); }
+
+hipError_t hipEventDestroy(hipEvent_t e)
+{
+    if (!event_ok(e, "hipEventDestroy")) return hipErrorInvalidHandle;
+    e->magic = 0;
+    delete e;
+    return hipSuccess;
+}
+
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s)
+{
+    if (!event_ok(e, "hipEventRecord") || !stream_ok(s, "hipEventRecord")) return hipErrorInvalidHandle;
+    e->stream = s;
+    e->ops = s ? s->ops : 0;
+    e->capture = s ? s->capture : 0;
+    return hipSuccess;
+}
+
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int)
+{
+    if (!event_ok(e, "hipStreamWaitEvent") || !stream_ok(s, "hipStreamWaitEvent")) return hipErrorInvalidHandle;
+    if (e->capture) {
+        if (!s) {
+            violation("the null stream waits on an event recorded in a capture");
+            return hipErrorStreamCaptureIsolation;
+        }
+        if (s->capture && s->capture != e->capture) {
+            violation("stream of one capture waits on an event of another");
+            return hipErrorStreamCaptureIsolation;
+        }
+        if (!s->capture) {  // fork: s joins the capture
+            s->capture = e->capture;
+            s->origin = e->stream->origin;
+            g_members[s->capture].push_back(s);
+        }
+        if (e->stream && e->stream != s) g_edges[s->capture].push_back({s, e->stream, e->ops});
+    }
+    enqueue(s);
+    return hipSuccess;
+}
+
+hipError_t hipEventSynchronize(hipEvent_t e)
+{
+    if (!event_ok(e, "hipEventSynchronize")) return hipErrorInvalidHandle;
+    if (e->capture) violation("hipEventSynchronize on an event recorded in a capture");
+    return hipSuccess;
+}
+
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b)
+{
+    if (!event_ok(a, "hipEventElapsedTime") || !event_ok(b, "hipEventElapsedTime")) return hipErrorInvalidHandle;
+    if (a->ops < 0 || b->ops < 0) return hipErrorNotReady;
+    *ms = 0.001f;
+    return hipSuccess;
+}
+
+hipError_t hipStreamIsCapturing(hipStream_t s, hipStreamCaptureStatus* st)
+{
+    if (!stream_ok(s, "hipStreamIsCapturing")) return hipErrorInvalidHandle;
+    *st = (s && s->capture) ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
+    return hipSuccess;
+}
+
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode)
+{
+    if (!s) return hipErrorStreamCaptureUnsupported;
+    if (!stream_ok(s, "hipStreamBeginCapture")) return hipErrorInvalidHandle;
+    if (s->capture) return hipErrorIllegalState;
+    s->capture = g_next_capture++;
+    s->origin = s;
+    g_members[s->capture].push_back(s);
+    return hipSuccess;
+}
+
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g)
+{
+    if (!stream_ok(s, "hipStreamEndCapture") || !s) return hipErrorInvalidHandle;
+    if (!s->capture || s->origin != s) return hipErrorIllegalState;
+    // a forked stream is joined when a joined stream (first the origin) waited
+    // on an event recorded after its last work item
+    std::set<ihipStream_t*> joined{s};
+    for (bool grew = true; grew;) {
+        grew = false;
+        for (const WaitEdge& w : g_edges[s->capture])
+            if (joined.count(w.waiter) && !joined.count(w.target) && w.target_ops == w.target->ops) {
+                joined.insert(w.target);
+                grew = true;
+            }
+    }
+    hipError_t r = hipSuccess;
+    for (ihipStream_t* m : g_members[s->capture]) {
+        if (!joined.count(m)) {
+            violation("capture ends with a forked stream not joined back");
+            r = hipErrorStreamCaptureUnjoined;
+        }
+    }
+    g_edges.erase(s->capture);
+    for (ihipStream_t* m : g_members[s->capture]) {
+        m->capture = 0;
+        m->origin = nullptr;
+    }
+    g_members.erase(s->capture);
+    *g = r == hipSuccess ? new ihipGraph() : nullptr;
+    return r;
+}
+
+hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, hipGraphNode_t*, char*, size_t)
+{
+    if (!g || g->magic != kGraphMagic) {
+        violation("hipGraphInstantiate of an invalid graph");
+        return hipErrorInvalidValue;
+    }
+    *x = new hipGraphExec();
+    return hipSuccess;
+}
+
+hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s)
+{
+    if (!x || x->magic != kExecMagic) {
+        violation("hipGraphLaunch of an invalid or destroyed graph");
+        return hipErrorInvalidValue;
+    }
+    if (!stream_ok(s, "hipGraphLaunch")) return hipErrorInvalidHandle;
+    enqueue(s);
+    return hipSuccess;
+}
+
+hipError_t hipGraphExecDestroy(hipGraphExec_t x)
+{
+    if (!x || x->magic != kExecMagic) {
+        violation("hipGraphExecDestroy of an invalid graph");
+        return hipErrorInvalidValue;
+    }
+    x->magic = 0;
+    delete x;
+    return hipSuccess;
+}
+
+hipError_t hipGraphDestroy(hipGraph_t g)
+{
+    if (!g || g->magic != kGraphMagic) {
+        violation("hipGraphDestroy of an invalid graph");
+        return hipErrorInvalidValue;
+    }
+    g->magic = 0;
+    delete g;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ stage kernels
+
+namespace fft3d {
+
+namespace {
+
+constexpr int kMaxThreads = 1024;
+
+bool has_variants(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096; }
+
+size_t table_entries(int n) { return (size_t)pass_table_size(radix_plan(n)); }
+
+size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Element range [lo, hi] (in units of `es` bytes) of a lines x len tile:
+// line (a, b) covers off + a*sa + b*sb + e*se, e < len.
+void check_range(const void* base, size_t es, int64_t off, int64_t A, int64_t sa, int64_t B, int64_t sb, int64_t len,
+                 int64_t se, const char* what)
+{
+    const int64_t lo = off;
+    const int64_t hi = off + (A - 1) * sa + (B - 1) * sb + (len - 1) * se;
+    if (lo < 0) {
+        violation("%s: negative element offset %lld", what, (long long)lo);
+        return;
+    }
+    in_alloc((const char*)base + lo * es, (size_t)(hi - lo + 1) * es, what);
+}
+
+void check_tables(const StageArgs& a, int n, size_t es, const char* what)
+{
+    const size_t s = table_entries(n);
+    if (s) in_alloc(a.twp, s * es, what);
+}
+
+hipError_t launched(hipStream_t s)
+{
+    if (!stream_ok(s, "kernel launch")) return hipErrorInvalidHandle;
+    enqueue(s);
+    ++g_launches;
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool c2c_variant_available(int n, int tdiv, int split)
+{
+    if (tdiv == 1 && !split) return length_supported(n);
+    if (!has_variants(n)) return false;
+    const int tpl = radix_plan(n).tpl;
+    return tdiv == 1 || (tdiv == 2 && tpl % 2 == 0) || (tdiv == 4 && tpl % 4 == 0);
+}
+
+hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    if (!length_supported(n)) return hipErrorInvalidValue;
+    const int tdiv = a.tdiv < 1 ? 1 : a.tdiv;
+    if (!c2c_variant_available(n, tdiv, a.split)) return hipErrorInvalidValue;
+    const size_t es = dtype == DT_F64 ? 16 : 8;
+    const int threads = a.lw * (radix_plan(n).tpl / tdiv);
+    const size_t line = a.strided ? (size_t)n : (size_t)(n + a.pad * (n / 8));
+    const size_t lds = align16((size_t)a.lw * line * (a.split ? es / 2 : es)) + table_entries(n) * es;
+    const int64_t blocks = a.strided ? (a.A + a.lw - 1) / a.lw : (a.A * a.B + a.lw - 1) / a.lw;
+    if (blocks == 0 || (a.strided && a.B == 0)) return hipSuccess;
+    if (threads > kMaxThreads || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+    if (a.strided && (a.sa != 1 || a.B > 65535)) violation("c2c strided tile with sa != 1 or too many rows");
+    if (blocks > 0x7fffffff) violation("c2c grid too large");
+    if (a.strided) {
+        check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "c2c strided load");
+        check_range(a.out, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "c2c strided store");
+    } else {
+        check_range(a.in, es, a.off, a.A, a.sa, a.B, a.sb, n, 1, "c2c load");
+        check_range(a.out, es, a.off, a.A, a.sa, a.B, a.sb, n, 1, "c2c store");
+    }
+    check_tables(a, n, es, "c2c pass table");
+    return launched(s);
+}
+
+static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    if (n % 2 != 0 || !length_supported(n / 2)) return hipErrorInvalidValue;
+    const int h = n / 2;
+    const size_t es = dtype == DT_F64 ? 16 : 8;
+    const int threads = a.lw * radix_plan(h).tpl;
+    const size_t lds = align16((size_t)a.lw * (h + 1) * es) + table_entries(h) * es;
+    if ((a.A * a.B + a.lw - 1) / a.lw == 0) return hipSuccess;
+    if (threads > kMaxThreads || lds > kMaxLdsBytes) violation("real kernel shape over the limits");
+    // complex-pair side has h values per line, half-spectrum side h + 1
+    const int64_t lin = r2c ? h : h + 1, lout = r2c ? h + 1 : h;
+    check_range(a.in, es, a.off, a.A, a.sa, a.B, a.sb, lin, 1, r2c ? "r2c load" : "c2r load");
+    check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, lout, 1, r2c ? "r2c store" : "c2r store");
+    in_alloc(a.tw, (size_t)(h + 1) * es, "real kernel root table");
+    check_tables(a, h, es, "real kernel pass table");
+    return launched(s);
+}
+
+hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(true, n, dtype, a, s); }
+
+hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(false, n, dtype, a, s); }
+
+hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    if (!length_supported(n)) return hipErrorInvalidValue;
+    const size_t es = dtype == DT_F64 ? 16 : 8;
+    const int threads = a.lw * radix_plan(n).tpl;
+    const size_t lds = align16((size_t)a.lw * n * es) + table_entries(n) * es;
+    if ((a.A + a.lw - 1) / a.lw == 0 || a.B == 0) return hipSuccess;
+    if (threads > kMaxThreads || lds > kMaxLdsBytes) violation("poisson kernel shape over the limits");
+    if (a.sa != 1) violation("poisson tile with sa != 1");
+    check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson load");
+    check_range(a.out, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson store");
+    check_tables(a, n, es, "poisson pass table");
+    return launched(s);
+}
+
+}  // namespace fft3d

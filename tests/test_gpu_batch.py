@@ -1,10 +1,11 @@
-"""GPU parity of batched uneven-size transforms in one persistent launch.
+"""GPU parity of batched uneven-size transforms issued as one task graph.
 
 The 64-transform workload (sizes drawn from a seed among 48^3, 64^3, 96^3,
 100x120x128, 160x160x80, complex64): every output against its own FP64
 oracle transform; bitwise equality with the same transform run alone through
-a single-transform plan (same per-line arithmetic); graph replay, direct
-persistent launch and one-launch-per-stage agree bit for bit.
+a single-transform plan (the batch runs the same stage kernels); graph replay,
+direct multi-stream issue and serial issue agree bit for bit, also when the
+caller captures the batch into a graph of its own.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from _util import fp32_bound, rel, to_host
+from _util import FP64_BOUND, fp32_bound, rel, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -31,19 +32,16 @@ def test_config4_each_against_oracle_and_single_plan(gpu_lib, workload):
     bp = gpu_lib.BatchPlan(shapes)
     outs = bp.forward(xs)
     torch.cuda.synchronize()
-    bp.check()
     for i, (s, a) in enumerate(zip(shapes, host)):
         got = to_host(outs[i])
         assert rel(got, oracle.fftn(a.astype(np.complex128))) <= fp32_bound(a.size), (i, s)
-    # bitwise equal to the single-transform plan (same per-line arithmetic)
+    # bitwise equal to the single-transform plan (same stage kernels)
     for i, s in enumerate(shapes[:12]):
         single = gpu_lib.Plan(s, torch.complex64).forward(xs[i])
         torch.cuda.synchronize()
         assert torch.equal(single, outs[i]), (i, s)
-    # inverse brings every field back
     back = bp.inverse(outs)
     torch.cuda.synchronize()
-    bp.check()
     for i, a in enumerate(host):
         assert rel(to_host(back[i]), a.astype(np.complex128)) <= fp32_bound(a.size), i
     bp.close()
@@ -51,15 +49,19 @@ def test_config4_each_against_oracle_and_single_plan(gpu_lib, workload):
 
 def test_modes_and_graph_replays_agree(gpu_lib, workload):
     shapes, host, xs = workload
+    side = torch.cuda.Stream()
     ref = None
     for mode in (2, 1, 0):
+        print(f"case mode {mode}", flush=True)
         bp = gpu_lib.BatchPlan(shapes, mode=mode)
         outs = [torch.empty_like(x) for x in xs]
+        torch.cuda.synchronize()
         for rep in range(3):  # graph replays, with eager torch work in between
-            bp.forward(xs, outs)
-            junk = torch.randn(1 << 20, device="cuda").sum()
+            with torch.cuda.stream(side):
+                bp.forward(xs, outs)
+                junk = torch.randn(1 << 20, device="cuda").sum()
+            side.synchronize()
             torch.cuda.synchronize()
-            bp.check()
             if ref is None:
                 ref = [o.clone() for o in outs]
             for i in range(len(xs)):
@@ -68,38 +70,81 @@ def test_modes_and_graph_replays_agree(gpu_lib, workload):
         bp.close()
 
 
+def test_caller_captures_batch(gpu_lib, workload):
+    shapes, host, xs = workload
+    sub = list(range(10))
+    s10 = [shapes[i] for i in sub]
+    x10 = [xs[i] for i in sub]
+    bp = gpu_lib.BatchPlan(s10, mode=1)
+    ref = [o.clone() for o in bp.forward(x10)]
+    outs = [torch.empty_like(x) for x in x10]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bp.forward(x10, outs)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for r, o in zip(ref, outs):
+            assert torch.equal(r, o), rep
+    del g
+    bp.close()
+
+
+def test_complex128_batch(gpu_lib):
+    shapes = [(12, 20, 16), (8, 8, 8), (30, 6, 10), (16, 48, 5)]
+    host = synth.batch_inputs(shapes, 17)
+    xs = [torch.from_numpy(a.astype(np.complex128)).cuda() for a in host]
+    bp = gpu_lib.BatchPlan(shapes, torch.complex128)
+    outs = bp.forward(xs)
+    back = bp.inverse(outs)
+    torch.cuda.synchronize()
+    for i, a in enumerate(host):
+        a64 = a.astype(np.complex128)
+        assert rel(to_host(outs[i]), oracle.fftn(a64)) <= FP64_BOUND, i
+        assert rel(to_host(back[i]), a64) <= FP64_BOUND, i
+    bp.close()
+
+
 def test_pointer_changes_and_in_place(gpu_lib, workload):
     shapes, host, xs = workload
     sub = [0, 1, 2, 3, 4, 5]
     s6 = [shapes[i] for i in sub]
+    side = torch.cuda.Stream()
     bp = gpu_lib.BatchPlan(s6)
-    ref = bp.forward([xs[i] for i in sub])
-    torch.cuda.synchronize()
-    copies = [xs[i].clone() for i in sub]
-    bp.forward(copies, copies)  # new pointers, in place
-    torch.cuda.synchronize()
-    bp.check()
+    with torch.cuda.stream(side):
+        ref = bp.forward([xs[i] for i in sub])
+        for _ in range(10):  # more pointer sets than cached graphs
+            copies = [xs[i].clone() for i in sub]
+            bp.forward(copies, copies)  # new pointers, in place
+    side.synchronize()
     for r, c in zip(ref, copies):
         assert torch.equal(r, c)
     bp.close()
 
 
-def test_lines_per_item_do_not_change_bits(gpu_lib, workload):
+def test_stage_configs_do_not_change_bits(gpu_lib, workload):
     shapes, host, xs = workload
     uniq = sorted(set(shapes))
     xs1 = [xs[shapes.index(s)] for s in uniq]
     bp = gpu_lib.BatchPlan(uniq)
     ref = [o.clone() for o in bp.forward(xs1)]
-    for n in (48, 64, 96, 100, 120, 128, 160, 80):
-        for strided in (0, 1):
-            for lw in (1, 3, 8):
-                bp.set_lines(n, strided, lw)
+    for s in uniq:
+        for axis, cfgs in ((0, [(1, 1, 0, 0), (4, 1, 1, 1)]), (1, [(4, 1, 0, 0), (16, 2, 1, 0)]),
+                           (2, [(8, 1, 0, 0), (32, 1, 1, 0)])):
+            for cfg in cfgs:
+                try:
+                    bp.set_stage_config(s, axis, *cfg)
+                except RuntimeError:
+                    continue
                 outs = bp.forward(xs1)
                 torch.cuda.synchronize()
-                bp.check()
                 for r, o in zip(ref, outs):
-                    assert torch.equal(r, o), (n, strided, lw)
-            bp.set_lines(n, strided, 0)
+                    assert torch.equal(r, o), (s, axis, cfg)
+            bp.set_stage_config(s, axis, 0)
     bp.close()
 
 
@@ -107,10 +152,16 @@ def test_batch_errors(gpu_lib):
     from paper_2601_12209_amd._lib import Fft3dError
 
     with pytest.raises(Fft3dError):
-        gpu_lib.BatchPlan([(8, 8, 1024)])  # above 512
+        gpu_lib.BatchPlan([(8, 8, 7)])  # unsupported length
     bp = gpu_lib.BatchPlan([(8, 8, 8), (8, 8, 8)])
     buf = torch.zeros(1024, dtype=torch.complex64, device="cuda")
     a, b = buf[:512].view(8, 8, 8), buf[256:768].view(8, 8, 8)
     with pytest.raises(Fft3dError):  # two transforms writing overlapping memory
         bp.forward([a.clone(), a.clone()], [a, b])
+    with pytest.raises(Fft3dError):
+        bp.set_stage_config((4, 4, 4), 0, 1)  # no transform of that shape
+    with pytest.raises(Fft3dError):
+        bp.set_mode(3)
+    with pytest.raises(ValueError):
+        bp.forward([a.clone()])
     bp.close()

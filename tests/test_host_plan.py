@@ -291,42 +291,16 @@ def test_simulator_catches_a_missing_edge(fft3d, monkeypatch):
     assert max(e if np.isfinite(e) else np.inf for e in errs) > 1e-3
 
 
-# ------------------------------------------------------------------ batch queue
+# ------------------------------------------------------------------ batch placement
 
-def test_batch_queue_order_and_dependencies(fft3d):
+def test_batch_placement_least_loaded(fft3d):
     shapes = synth.batch_sizes()
-    for op in (0, 1):
-        q = fft3d.query_batch_queue(shapes, op)
-        assert len(q) == 3 * len(shapes)
-        # stage-major, contiguous item ranges, every (fft, stage) once
-        assert [s["stage"] for s in q] == sorted(s["stage"] for s in q)
-        pos = 0
-        seen = set()
-        for i, s in enumerate(q):
-            assert s["first"] == pos and s["items"] > 0 and s["done_idx"] == i
-            pos += s["items"]
-            seen.add((s["fft"], s["stage"]))
-            nz, ny, nx = shapes[s["fft"]]
-            axis_fwd = s["stage"] if op == 0 else 2 - s["stage"]
-            assert s["axis"] == axis_fwd
-            n = (nx, ny, nz)[s["axis"]]
-            assert s["n"] == n and s["strided"] == (s["axis"] != 0)
-            lines = nx * ny * nz // n
-            if s["strided"]:
-                a, b = nx, lines // nx
-                assert s["items"] == -(-a // s["lw"]) * b
-            else:
-                assert s["items"] == -(-lines // s["lw"])
-            _, tpl = fft3d.query_radix_plan(n)
-            assert 1 <= s["lw"] and s["lw"] * tpl <= 256
-            if s["stage"] == 0:
-                assert s["dep"] == -1
-            else:  # waits on the previous stage of the same transform, listed earlier
-                d = q[s["dep"]]
-                assert s["dep"] < i and d["fft"] == s["fft"] and d["stage"] == s["stage"] - 1
-                assert s["dep_count"] == d["items"]
-        assert len(seen) == len(q)
-        # within a stage, larger segments first
-        for st in range(3):
-            items = [s["items"] for s in q if s["stage"] == st]
-            assert items == sorted(items, reverse=True)
+    per = fft3d.query_batch_placement(shapes, 4)
+    assert len(per) == 4
+    assert sorted(i for p in per for i in p) == list(range(len(shapes)))
+    cost = [np.prod(s) * np.log2(np.prod(s)) for s in shapes]
+    loads = [sum(cost[i] for i in p) for p in per]
+    # greedy LPT: the spread is at most the largest single cost
+    assert max(loads) - min(loads) <= max(cost) + 1e-6
+    for p in per:  # within a stream, larger transforms first
+        assert [cost[i] for i in p] == sorted((cost[i] for i in p), reverse=True)
