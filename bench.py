@@ -2,8 +2,10 @@
 """Benchmark of the pencil 3D FFT on one MI355X.
 
 One step = forward + inverse 3D C2C FFT of a 512^3 complex64 field (the
-headline workload): x, y, z stages forward, z, y, x inverse, every stage a
-batch of 1D Stockham FFTs over its pencil tiles.  The input (i.i.d. N(0,1)
+headline workload): x, y, z stages in both directions (the library's default
+staging for this size: the y stage writes a y/z-swapped workspace that the z
+stage reads back), every stage a batch of 1D Stockham FFTs over its pencil
+tiles.  The input (i.i.d. N(0,1)
 real and imaginary parts, seed 0) is resident in HBM before timing starts.
 
 Reported (one JSON line):
@@ -57,6 +59,8 @@ def measured_traffic(n_edge):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 DEFAULT_GRID = (1, 1)
 DEFAULT_STREAMS = 1
+STAGINGS = {"in_place": 0, "swap_yz": 1}
+DEFAULT_STAGING = "swap_yz"
 
 
 def _timed_steps(step, steps, warmup, torch):
@@ -91,11 +95,11 @@ def _stage_profile(plan, x, X, Y, reps, torch):
     return [v / reps for v in fwd], [v / reps for v in inv]
 
 
-def _measure(dtype, shape, grid, streams, steps, warmup, a_host, torch, fft3d):
+def _measure(dtype, shape, grid, streams, steps, warmup, a_host, torch, fft3d, staging=0):
     x = torch.from_numpy(a_host).to(device="cuda", dtype=dtype)
     X = torch.empty_like(x)
     Y = torch.empty_like(x)
-    plan = fft3d.Plan(shape, dtype, grid, streams=streams)
+    plan = fft3d.Plan(shape, dtype, grid, streams=streams, staging=staging)
 
     def step():
         plan.forward(x, out=X)
@@ -229,6 +233,9 @@ def main():
     ap.add_argument("--size", type=int, default=512, help="grid edge (default 512)")
     ap.add_argument("--grid", type=int, nargs=2, default=list(DEFAULT_GRID), help="pencil grid P1 P2")
     ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS)
+    ap.add_argument("--staging", choices=sorted(STAGINGS), default=DEFAULT_STAGING,
+                    help="in_place: y and z stages in place on the output; swap_yz: the y stage "
+                         "writes a y/z-swapped workspace that the z stage reads back")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 run")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle on the host")
     ap.add_argument("--no-extras", action="store_true",
@@ -260,7 +267,8 @@ def main():
     print(f"# input: {shape} complex N(0,1), seed {synth.HEADLINE['seed']}", file=sys.stderr, flush=True)
     a = synth.complex_normal(shape, synth.HEADLINE["seed"], np.complex64)
 
-    r32 = _measure(torch.complex64, shape, grid, args.streams, args.steps, args.warmup, a, torch, fft3d)
+    staging = STAGINGS[args.staging]
+    r32 = _measure(torch.complex64, shape, grid, args.streams, args.steps, args.warmup, a, torch, fft3d, staging)
     print(f"# c64: {r32['ms']:.3f} ms/step", file=sys.stderr, flush=True)
     if args.copy_calibration:
         dst = torch.empty_like(r32["X"])
@@ -271,14 +279,16 @@ def main():
     r64 = None
     if not args.no_fp64:
         a64 = a.astype(np.complex128)
-        r64 = _measure(torch.complex128, shape, grid, args.streams, args.steps, args.warmup, a64, torch, fft3d)
+        r64 = _measure(torch.complex128, shape, grid, args.streams, args.steps, args.warmup, a64, torch, fft3d,
+                       staging)
         del a64
         print(f"# c128: {r64['ms']:.3f} ms/step", file=sys.stderr, flush=True)
 
     def stage_report(r, elem):
         names = ["x", "y", "z"]
         out = {}
-        for tag, st, order in (("fwd", r["fwd_stages"], names), ("inv", r["inv_stages"], names[::-1])):
+        inv_order = names if staging == STAGINGS["swap_yz"] else names[::-1]
+        for tag, st, order in (("fwd", r["fwd_stages"], names), ("inv", r["inv_stages"], inv_order)):
             for nm, ms in zip(order, st):
                 gbs = 2.0 * elem * N / (ms * 1e-3) / 1e9
                 out[f"{tag}_{nm}"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
@@ -312,7 +322,7 @@ def main():
         "data": "synthetic: complex N(0,1) field, seed 0, resident in HBM",
         "config": {"workload": f"c2c_{n_edge}cubed_forward_plus_inverse", "nx": n_edge, "ny": n_edge,
                    "nz": n_edge, "precision": "complex64", "pencil_grid": list(grid),
-                   "streams": args.streams},
+                   "streams": args.streams, "staging": args.staging},
         "hbm_frac_whole_step": round(whole_frac, 4),
         "stages_c64": st32,
         "roofline": roofline,

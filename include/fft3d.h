@@ -64,8 +64,9 @@ typedef enum {
  *          min(Nz, Ny), Nxc = Nx (C2C) or Nx/2+1 (R2C).
  *   r2c    0: complex-to-complex plan; 1: real-to-complex plan (Nx even).
  * Each of Nx, Ny, Nz must be a supported length (fft3d_length_supported).
- * Allocates the plan's twiddle tables, its streams and events, and for R2C
- * plans a half-spectrum workspace (replaceable by fft3d_set_workspace).
+ * Allocates the plan's twiddle tables, its streams and events, and a
+ * workspace for R2C plans (half spectrum) and for large C2C plans (see
+ * fft3d_set_staging); fft3d_set_workspace can replace it.
  */
 fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype,
                         int p1, int p2, int r2c);
@@ -85,7 +86,8 @@ fft3d_status fft3d_forward(fft3d_plan_t plan, const void* in, void* out, void* s
 
 /*
  * Inverse transform: exponent sign +1, scaled by 1/(Nx*Ny*Nz), stages z, y, x
- * (Sec. IV-A).  C2C: same buffer rules as forward.  R2C plan: in = half
+ * (Sec. IV-A; x, y, z with FFT3D_STAGING_SWAP_YZ).  C2C: same buffer rules as
+ * forward.  R2C plan: in = half
  * spectrum (left intact; the imaginary parts of its kx = 0 and kx = Nx/2 bins
  * are ignored), out = real array, no overlap; uses the plan workspace.
  */
@@ -117,7 +119,8 @@ fft3d_status fft3d_poisson(fft3d_plan_t plan, const void* f, void* phi, void* st
  */
 fft3d_status fft3d_poisson_adjoint(fft3d_plan_t plan, const void* gphi, void* gf, void* stream);
 
-/* Bytes of the plan's workspace (0 for C2C plans). */
+/* Bytes of the plan's workspace: R2C plans (Nx/2+1)*Ny*Nz complex values,
+ * C2C plans Nx*Ny*Nz complex values with FFT3D_STAGING_SWAP_YZ, else 0. */
 size_t fft3d_workspace_bytes(fft3d_plan_t plan);
 
 /*
@@ -127,6 +130,27 @@ size_t fft3d_workspace_bytes(fft3d_plan_t plan);
  * workspace.  Too small -> FFT3D_ERR_WORKSPACE.
  */
 fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
+
+/*
+ * How a C2C plan stages its three passes (Sec. III-A's redistributions
+ * between the stages, done on one device by where each stage writes).
+ *   FFT3D_STAGING_IN_PLACE: the x stage writes `out`, the y and z stages
+ *     work in place on it; no workspace.  Inverse stages run z, y, x.
+ *   FFT3D_STAGING_SWAP_YZ: the y stage writes a plan workspace of Nx*Ny*Nz
+ *     complex values with y and z swapped (x fastest, then z, then y) and the
+ *     z stage reads it back into `out`, so z-lines are read with the row
+ *     stride of y-lines instead of the plane stride; forward, inverse and
+ *     backward all run x, y, z (the same transform up to rounding order).
+ * Default: SWAP_YZ for C2C plans of at least 512 MiB with Ny, Nz > 1 (the
+ * workspace is allocated by fft3d_plan; if that fails the plan stages in
+ * place), IN_PLACE otherwise.  Switching frees or allocates the owned
+ * workspace (fft3d_set_workspace can then supply a caller buffer) and waits
+ * for the device.  R2C plans accept only FFT3D_STAGING_IN_PLACE (else
+ * FFT3D_ERR_WRONG_PLAN).
+ */
+#define FFT3D_STAGING_IN_PLACE 0
+#define FFT3D_STAGING_SWAP_YZ 1
+fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
 
 /*
  * Number of internal HIP streams the tiles are placed on (1..16; default 4).
@@ -226,20 +250,22 @@ fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out);
 
 /*
  * Task graph of an operation (0 forward, 1 inverse, 2 backward, 3 Poisson,
- * 4 Poisson adjoint) for the given plan parameters and stream count, written
+ * 4 Poisson adjoint) for the given plan parameters (staging as in
+ * fft3d_set_staging) and stream count, written
  * as int64 records:
  *   header: [ntasks, nstages]
- *   per stage: [kind, axis, n, conj, weight, src, dst, scale]
+ *   per stage: [kind, axis, n, conj, weight, src, dst, scale, lay_src, lay_dst]
  *     kind 0 C2C, 1 R2C along x, 2 C2R along x, 3 fused Poisson z stage;
  *     axis 0..2; n the line length; conj 1 for the sign +1 transform; weight 1
  *     for the adjoint bin weighting; src/dst 0 = in, 1 = out, 2 = workspace;
- *     scale the output factor as the bit pattern of an IEEE double
+ *     scale the output factor as the bit pattern of an IEEE double; lay_src,
+ *     lay_dst the element order read / written (0 natural, 1 y and z swapped)
  *   per task:  [stage, x0, x1, y0, y1, z0, z1, stream, ndeps, deps..., nwaits, waits...]
  * Boxes are half-open ranges over the complex array.  Returns the number of
  * int64 values needed; writes them only if cap is large enough.  Negative on
  * invalid arguments.
  */
-int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int op,
+int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int staging, int op,
                              int nstreams, int64_t* out, int64_t cap);
 
 #ifdef __cplusplus

@@ -26,6 +26,7 @@ _SIGS = {
     "fft3d_workspace_bytes": (SZ, [P]),
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
+    "fft3d_set_staging": (I32, [P, I32]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
     "fft3d_set_timing": (I32, [P, I32]),
     "fft3d_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), I32]),
@@ -41,7 +42,7 @@ _SIGS = {
     "fft3d_length_supported": (I32, [I64]),
     "fft3d_query_radix_plan": (I32, [I64, ctypes.POINTER(I32), I32]),
     "fft3d_query_twiddles": (I32, [I64, I32, P]),
-    "fft3d_query_pipeline": (I64, [I64, I64, I64, I32, I32, I32, I32, I32, ctypes.POINTER(I64), I64]),
+    "fft3d_query_pipeline": (I64, [I64, I64, I64, I32, I32, I32, I32, I32, I32, ctypes.POINTER(I64), I64]),
 }
 
 

@@ -232,6 +232,8 @@ fft3d_status fft3d_plan_batch(fft3d_batch_t* out, int count, const int64_t* dims
         fft3d_plan_t p = nullptr;
         fft3d_status st = fft3d_plan(&p, d.nx, d.ny, d.nz, dtype, 1, 1, 0);
         if (st == FFT3D_OK) st = fft3d_set_streams(p, 1);
+        // transforms of one shape share the plan across streams: no workspace
+        if (st == FFT3D_OK) st = fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE);
         if (st != FFT3D_OK) {
             if (p) fft3d_destroy(p);
             release(b);

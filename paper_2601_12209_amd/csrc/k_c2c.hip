@@ -28,7 +28,7 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     T* ldsr = reinterpret_cast<T*>(smem_raw);
     const int t = threadIdx.x;
     int tj;
-    int64_t base;
+    int64_t base, base_o;
     bool ok;
     LdsView<cpx<T>> L;
     LdsView<T> Ls;
@@ -37,9 +37,11 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     if (a.strided) {
         const int lw = t % a.lw;
         tj = t / a.lw;
-        const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
-        ok = aa < a.A;
-        base = a.off + (ok ? aa : a.A - 1) + (int64_t)blockIdx.y * a.sb;
+        const int64_t aa0 = (int64_t)blockIdx.x * a.lw + lw;
+        ok = aa0 < a.A;
+        const int64_t aa = ok ? aa0 : a.A - 1;
+        base = a.off + aa + (int64_t)blockIdx.y * a.sb;
+        base_o = a.off_o + aa + (int64_t)blockIdx.y * a.sb_o;
         L = LdsView<cpx<T>>{lds + lw, a.lw, 0};
         Ls = LdsView<T>{ldsr + lw, a.lw, 0};
     } else {
@@ -50,6 +52,7 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
         const int64_t l = ok ? l0 : a.A * a.B - 1;
         const int64_t aa = l % a.A, bb = l / a.A;
         base = a.off + aa * a.sa + bb * a.sb;
+        base_o = a.off_o + aa * a.sa_o + bb * a.sb_o;
         const int stride = N + a.pad * (N / 8);
         L = LdsView<cpx<T>>{lds + lw * stride, 1, a.pad};
         Ls = LdsView<T>{ldsr + lw * stride, 1, a.pad};
@@ -57,11 +60,11 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * line * (SPLIT ? sizeof(T) : sizeof(cpx<T>))));
     stage_pass_twiddles<T, N>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
-    const int64_t se = a.se;
+    const int64_t se = a.se, se_o = a.se_o;
     // element e of this thread's line sits (e - tj) * se past the thread base;
     // e - tj is a compile-time constant at every call site
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base + tj * se;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base + tj * se;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base_o + tj * se_o;
     const bool cj = a.conj != 0;
     const T scale = (T)a.scale;
     auto load = [&](int e) -> cpx<T> {
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     };
     auto store = [&](int e, cpx<T> v) {
         if (cj) v = conj(v);
-        if (ok) out[(e - tj) * se] = v * scale;
+        if (ok) out[(e - tj) * se_o] = v * scale;
     };
     fft_line<T, N, TPL, SPLIT>(L, Ls, tj, twl, load, store);
 }

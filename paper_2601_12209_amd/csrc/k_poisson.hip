@@ -31,10 +31,12 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     const int lw = t % a.lw, tj = t / a.lw;
     const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
     const bool ok = aa < a.A;
-    const int64_t base = a.off + (ok ? aa : a.A - 1) + (int64_t)blockIdx.y * a.sb;  // see k_c2c
-    const int64_t se = a.se;
+    const int64_t ac = ok ? aa : a.A - 1;  // see k_c2c
+    const int64_t base = a.off + ac + (int64_t)blockIdx.y * a.sb;
+    const int64_t base_o = a.off_o + ac + (int64_t)blockIdx.y * a.sb_o;
+    const int64_t se = a.se, se_o = a.se_o;
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base + tj * se;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base + tj * se;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base_o + tj * se_o;
     LdsView<cpx<T>> L{lds + lw, a.lw, 0};
     LdsView<T> Ls{nullptr, 0, 0};
     constexpr int TPL = radix_plan(N).tpl;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
         return conj(L[e] * m);
     };
     auto store = [&](int e, cpx<T> v) {
-        if (ok) out[(e - tj) * se] = conj(v);
+        if (ok) out[(e - tj) * se_o] = conj(v);
     };
     fft_line<T, N, TPL, false, true, false>(L, Ls, tj, twl, load_mul, store);
 }

@@ -60,6 +60,19 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op)
     const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
     const double inv_n = 1.0 / ((double)d.nx * (double)d.ny * (double)d.nz);
     std::vector<Stage> s;
+    if (!d.r2c && d.staging == STAGING_SWAP_YZ) {
+        // x, y, z in both directions; the y stage writes the workspace in
+        // SWAP_YZ order, the z stage reads it back into the output
+        const bool fwd = op == OP_FORWARD;
+        if (op != OP_FORWARD && op != OP_INVERSE && op != OP_BACKWARD) return s;
+        const int cj = fwd ? 0 : 1;
+        s.push_back(mk(K_C2C, 0, nx, cj, 0, 1.0, BUF_IN, BUF_OUT));
+        s.push_back(mk(K_C2C, 1, ny, cj, 0, 1.0, BUF_OUT, BUF_WS));
+        s.back().lay_dst = LAY_SWAP_YZ;
+        s.push_back(mk(K_C2C, 2, nz, cj, 0, op == OP_INVERSE ? inv_n : 1.0, BUF_WS, BUF_OUT));
+        s.back().lay_src = LAY_SWAP_YZ;
+        return s;
+    }
     if (!d.r2c) {
         switch (op) {
         case OP_FORWARD:  // x, y, z (Alg. 1)

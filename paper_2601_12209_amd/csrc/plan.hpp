@@ -19,11 +19,24 @@ enum Op : int {
 
 enum Buf : int { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
 
+// Element order of a buffer between stages.  NATURAL: x fastest, then y,
+// then z.  SWAP_YZ: x fastest, then z, then y (z-lines have the row stride
+// of y-lines in the natural order).
+enum Layout : int { LAY_NATURAL = 0, LAY_SWAP_YZ = 1 };
+
+// How a C2C plan stages its passes.  IN_PLACE: every stage after the first
+// works in place on the output (no workspace).  SWAP_YZ: the y stage writes a
+// workspace in SWAP_YZ order and the z stage reads it back into the output,
+// so no stage reads z-lines at the natural order's plane stride; the inverse
+// then also runs x, y, z.
+enum Staging : int { STAGING_IN_PLACE = 0, STAGING_SWAP_YZ = 1 };
+
 struct PlanDesc {
     int64_t nx, ny, nz;
     int dtype;  // DT_F32 / DT_F64
     int p1, p2;
     int r2c;
+    int staging = STAGING_IN_PLACE;  // C2C plans only
     int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent
 };
 
@@ -43,6 +56,7 @@ struct Stage {
     int weight;    // adjoint weighting of interior half-spectrum bins
     double scale;  // output scale
     int src, dst;  // Buf ids
+    int lay_src = LAY_NATURAL, lay_dst = LAY_NATURAL;
 };
 
 struct Task {

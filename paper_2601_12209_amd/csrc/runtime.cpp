@@ -38,6 +38,10 @@ fft3d_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr int kMaxStreams = 16;
+// C2C plans of at least this many bytes default to the swapped-y/z staging
+// (measured on MI355X: faster at 512^3, slower at 256^3, whose 128-256 MiB
+// field stays in the 256 MB Infinity Cache)
+constexpr size_t kSwapStagingMinBytes = (size_t)512 << 20;
 
 }  // namespace
 
@@ -150,11 +154,24 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
     return c;
 }
 
+// Element strides of the complex array in a layout: (x, y, z).
+void layout_strides(const PlanDesc& d, int lay, int64_t st[3])
+{
+    const int64_t nxc = d.nxc();
+    st[0] = 1;
+    if (lay == LAY_SWAP_YZ) {
+        st[1] = nxc * d.nz;
+        st[2] = nxc;
+    } else {
+        st[1] = nxc;
+        st[2] = nxc * d.ny;
+    }
+}
+
 StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* const bufs[3])
 {
     const PlanDesc& d = p->d;
     const int64_t nxc = d.nxc(), ny = d.ny;
-    const int64_t dx = b.hi[0] - b.lo[0], dy = b.hi[1] - b.lo[1], dz = b.hi[2] - b.lo[2];
     StageArgs a;
     memset(&a, 0, sizeof a);
     a.in = bufs[st.src];
@@ -164,39 +181,32 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.conj = st.conj;
     a.weight = st.weight;
     a.scale = st.scale;
-    a.se = 1;
-    if (st.axis == 0) {
-        a.A = dy;
-        a.B = dz;
+    // the tile's lines run along st.axis; they form an A x B grid over the
+    // other two axes (x first when it is one of them)
+    const int ax_a = st.axis == 0 ? 1 : 0;
+    const int ax_b = st.axis == 2 ? 1 : 2;
+    a.A = b.hi[ax_a] - b.lo[ax_a];
+    a.B = b.hi[ax_b] - b.lo[ax_b];
+    if (st.kind == K_R2C_X || st.kind == K_C2R_X) {
+        // real rows: nx reals = nx/2 complex pairs per row
+        const int64_t h = d.nx / 2;
         const int64_t row = b.lo[1] + ny * b.lo[2];
-        if (st.kind == K_R2C_X) {
-            const int64_t h = d.nx / 2;  // complex pairs per real row
-            a.off = row * h; a.sa = h; a.sb = h * ny;
-            a.off_o = row * nxc; a.sa_o = nxc; a.sb_o = nxc * ny;
-        } else if (st.kind == K_C2R_X) {
-            const int64_t h = d.nx / 2;
-            a.off = row * nxc; a.sa = nxc; a.sb = nxc * ny;
-            a.off_o = row * h; a.sa_o = h; a.sb_o = h * ny;
-        } else {
-            a.off = row * nxc; a.sa = nxc; a.sb = nxc * ny;
-        }
+        const int64_t ci = nxc, ri = h;  // complex / real-pair row lengths
+        const int64_t li = st.kind == K_R2C_X ? ri : ci, lo = st.kind == K_R2C_X ? ci : ri;
+        a.off = row * li; a.sa = li; a.sb = li * ny; a.se = 1;
+        a.off_o = row * lo; a.sa_o = lo; a.sb_o = lo * ny; a.se_o = 1;
         a.strided = 0;
-    } else if (st.axis == 1) {
-        a.A = dx;
-        a.B = dz;
-        a.off = b.lo[0] + b.lo[2] * nxc * ny;
-        a.sa = 1;
-        a.sb = nxc * ny;
-        a.se = nxc;
-        a.strided = 1;
     } else {
-        a.A = dx;
-        a.B = dy;
-        a.off = b.lo[0] + b.lo[1] * nxc;
-        a.sa = 1;
-        a.sb = nxc;
-        a.se = nxc * ny;
-        a.strided = 1;
+        int64_t si[3], so[3];
+        layout_strides(d, st.lay_src, si);
+        layout_strides(d, st.lay_dst, so);
+        a.off = b.lo[0] * si[0] + b.lo[1] * si[1] + b.lo[2] * si[2];
+        a.sa = si[ax_a]; a.sb = si[ax_b]; a.se = si[st.axis];
+        a.off_o = b.lo[0] * so[0] + b.lo[1] * so[1] + b.lo[2] * so[2];
+        a.sa_o = so[ax_a]; a.sb_o = so[ax_b]; a.se_o = so[st.axis];
+        a.strided = st.axis != 0 ? 1 : 0;
+    }
+    if (st.kind == K_POISSON_Z) {
         a.pnx = d.nx; a.pny = d.ny; a.pnz = d.nz;
         a.kx0 = b.lo[0];
         a.ky0 = b.lo[1];
@@ -468,6 +478,19 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         }
         p->ws_owned = true;
     }
+    // large C2C plans stage through a y/z-swapped workspace by default (see
+    // fft3d_set_staging); if it cannot be allocated they stage in place
+    if (!r2c && ny > 1 && nz > 1 && (size_t)nx * ny * nz * elem_bytes(dtype) >= kSwapStagingMinBytes) {
+        const size_t need = (size_t)nx * ny * nz * elem_bytes(dtype);
+        if (hipMalloc(&p->ws, need) == hipSuccess) {
+            p->d.staging = STAGING_SWAP_YZ;
+            p->ws_owned = true;
+            p->ws_bytes = need;
+        } else {
+            p->ws = nullptr;
+            (void)hipGetLastError();
+        }
+    }
     p->streams.assign(kMaxStreams, nullptr);
     if (forks(p)) {
         e = ensure_streams(p, p->nstreams);
@@ -512,6 +535,9 @@ static fft3d_status c2c_or_r2c(fft3d_plan_t p, int op, const void* in, void* out
     if (!d.r2c) {
         if (in != out && ranges_overlap(in, n * s, out, n * s))
             return fail(FFT3D_ERR_ALIAS, "in and out partially overlap");
+        if (d.staging == STAGING_SWAP_YZ &&
+            (ranges_overlap(p->ws, p->ws_bytes, in, n * s) || ranges_overlap(p->ws, p->ws_bytes, out, n * s)))
+            return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
     } else {
         const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.nxc() * d.ny * d.nz * s;
         const size_t in_bytes = op == OP_FORWARD ? real_bytes : half_bytes;
@@ -565,14 +591,16 @@ fft3d_status fft3d_poisson_adjoint(fft3d_plan_t p, const void* gphi, void* gf, v
 
 size_t fft3d_workspace_bytes(fft3d_plan_t p)
 {
-    if (!p || !p->d.r2c) return 0;
+    if (!p) return 0;
+    if (!p->d.r2c && p->d.staging != STAGING_SWAP_YZ) return 0;
     return (size_t)p->d.nxc() * p->d.ny * p->d.nz * elem_bytes(p->d.dtype);
 }
 
 fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    if (!p->d.r2c) return ws ? fail(FFT3D_ERR_WRONG_PLAN, "C2C plans use no workspace") : FFT3D_OK;
+    if (!p->d.r2c && p->d.staging != STAGING_SWAP_YZ)
+        return ws ? fail(FFT3D_ERR_WRONG_PLAN, "in-place C2C staging uses no workspace") : FFT3D_OK;
     const size_t need = fft3d_workspace_bytes(p);
     if (ws && bytes < need) return fail(FFT3D_ERR_WORKSPACE, "workspace smaller than fft3d_workspace_bytes");
     if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -593,6 +621,35 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
     p->ws = mine;
     p->ws_owned = true;
     p->ws_bytes = need;
+    return FFT3D_OK;
+}
+
+fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ)
+        return fail(FFT3D_ERR_INVALID_ARG, "staging must be 0 (in place) or 1 (swap y/z)");
+    if (p->d.r2c) return staging == STAGING_IN_PLACE ? FFT3D_OK
+                                                     : fail(FFT3D_ERR_WRONG_PLAN, "swap-y/z staging is for C2C plans");
+    if (staging == p->d.staging) return FFT3D_OK;
+    // enqueued work may still use the old workspace (hipFree waits for the device)
+    if (p->ws && p->ws_owned) hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_owned = false;
+    p->ws_bytes = 0;
+    p->d.staging = staging;
+    for (int op = 0; op < OP_COUNT; ++op) p->pipe_ok[op] = false;
+    if (staging == STAGING_SWAP_YZ) {
+        const size_t need = fft3d_workspace_bytes(p);
+        hipError_t e = hipMalloc(&p->ws, need);
+        if (e != hipSuccess) {
+            p->ws = nullptr;
+            p->d.staging = STAGING_IN_PLACE;
+            return hip_fail(e, "workspace allocation");
+        }
+        p->ws_owned = true;
+        p->ws_bytes = need;
+    }
     return FFT3D_OK;
 }
 
@@ -717,12 +774,15 @@ fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out)
     return FFT3D_OK;
 }
 
-int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int op,
+int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int staging, int op,
                              int nstreams, int64_t* out, int64_t cap)
 {
     PlanDesc d;
     d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = DT_F32; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
     if (validate_desc(d) != FFT3D_OK) return -1;
+    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ) return -1;
+    if (r2c && staging != STAGING_IN_PLACE) return -1;
+    d.staging = staging;
     if (op < 0 || op >= OP_COUNT || nstreams < 1 || nstreams > kMaxStreams) return -1;
     const Pipeline pl = build_pipeline(d, op, nstreams);
     std::vector<int64_t> v;
@@ -731,8 +791,8 @@ int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2,
     for (const Stage& s : pl.stages) {
         int64_t scale_bits;
         memcpy(&scale_bits, &s.scale, sizeof scale_bits);
-        int64_t rec[8] = {s.kind, s.axis, s.n, s.conj, s.weight, s.src, s.dst, scale_bits};
-        v.insert(v.end(), rec, rec + 8);
+        int64_t rec[10] = {s.kind, s.axis, s.n, s.conj, s.weight, s.src, s.dst, scale_bits, s.lay_src, s.lay_dst};
+        v.insert(v.end(), rec, rec + 10);
     }
     for (const Task& t : pl.tasks) {
         v.push_back(t.stage);

@@ -15,10 +15,11 @@ enum KernelKind : int {
 enum DType : int { DT_F32 = 0, DT_F64 = 1 };
 
 // The tile's lines form an A x B grid; line (a, b) starts at element
-// off + a*sa + b*sb of the input and its elements are se apart.  Elements are
+// off + a*sa + b*sb of the input and its elements are se apart; in the output
+// it starts at off_o + a*sa_o + b*sb_o with elements se_o apart.  Elements are
 // complex values of the kernel's precision (for R2C input and C2R output, a
 // complex value is a pair of consecutive reals).  R2C/C2R lines are contiguous
-// (se = 1) and their output line starts at off_o + a*sa_o + b*sb_o.
+// (se = se_o = 1).
 struct StageArgs {
     const void* in;
     void* out;
@@ -26,8 +27,8 @@ struct StageArgs {
     const void* twp;  // per-pass twiddle table of the kernel's FFT length
     int64_t A, B;
     int64_t off, sa, sb, se;
-    int64_t off_o, sa_o, sb_o;
-    int strided;  // 1: lanes of a wavefront walk neighbouring lines (requires sa == 1)
+    int64_t off_o, sa_o, sb_o, se_o;
+    int strided;  // 1: lanes of a wavefront walk neighbouring lines (requires sa == sa_o == 1)
     int lw;       // lines per workgroup
     int tdiv;     // threads per line = (default threads per line) / tdiv
     int split;    // 1: exchange real and imaginary parts through LDS separately

@@ -41,10 +41,14 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+STAGING_IN_PLACE = 0
+STAGING_SWAP_YZ = 1
+
+
 class Plan:
     """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind."""
 
-    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None):
+    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None):
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
         self.code = _dtype_code(dtype)
@@ -58,6 +62,8 @@ class Plan:
         self._ws = None
         if streams is not None:
             self.set_streams(streams)
+        if staging is not None:
+            self.set_staging(staging)
 
     # ------------------------------------------------------------ helpers
     @property
@@ -137,6 +143,12 @@ class Plan:
     # ------------------------------------------------------------ tuning
     def set_streams(self, n: int):
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
+
+    def set_staging(self, staging: int):
+        """STAGING_IN_PLACE (no workspace) or STAGING_SWAP_YZ (C2C: y stage writes a
+        y/z-swapped workspace that the z stage reads back)."""
+        check(_lib.lib().fft3d_set_staging(self._h, int(staging)), "fft3d_set_staging")
+        self._ws = None
 
     def set_stage_config(self, axis: int, lw: int, tdiv: int = 1, split: int = 0, pad: int = 0):
         """Launch shape of the stage kernels along one axis (lw = 0: default)."""
@@ -344,25 +356,25 @@ def query_twiddles(n: int, dtype) -> np.ndarray:
     return out
 
 
-def query_pipeline(shape, grid, r2c=False, op=0, nstreams=4):
+def query_pipeline(shape, grid, r2c=False, op=0, nstreams=4, staging=0):
     """Decoded task graph: (stages, tasks) with boxes over the complex (x, y, z) index space."""
     nz, ny, nx = shape
     L = _lib.lib()
-    need = L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), op, nstreams, None, 0)
+    need = L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), int(staging), op, nstreams, None, 0)
     if need < 0:
         raise ValueError("invalid pipeline arguments")
     buf = (ctypes.c_int64 * need)()
-    L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), op, nstreams, buf, need)
+    L.fft3d_query_pipeline(nx, ny, nz, grid[0], grid[1], int(r2c), int(staging), op, nstreams, buf, need)
     v = list(buf)
     ntasks, nstages = v[0], v[1]
     pos = 2
     stages = []
     for _ in range(nstages):
-        kind, axis, n, conj, weight, src, dst, sbits = v[pos:pos + 8]
+        kind, axis, n, conj, weight, src, dst, sbits, lay_src, lay_dst = v[pos:pos + 10]
         scale = float(np.array([sbits], dtype=np.int64).view(np.float64)[0])
         stages.append(dict(kind=kind, axis=axis, n=n, conj=conj, weight=weight, src=src, dst=dst,
-                           scale=scale))
-        pos += 8
+                           scale=scale, lay_src=lay_src, lay_dst=lay_dst))
+        pos += 10
     tasks = []
     for _ in range(ntasks):
         stage = v[pos]

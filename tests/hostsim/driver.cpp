@@ -83,8 +83,41 @@ void c2c_cases(hipStream_t user)
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
             if (bytes >= 2 * es_of(dtype))  // partial overlap
                 EXPECT(fft3d_forward(p, in.p, (char*)in.p + es_of(dtype), user) == FFT3D_ERR_ALIAS);
+            // swapped-y/z staging: owned workspace, then a caller one
+            EXPECT(fft3d_workspace_bytes(p) == 0);
+            EXPECT(fft3d_set_workspace(p, in.p, bytes) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
+            EXPECT(fft3d_workspace_bytes(p) == bytes);
+            for (int ns : {1, 4}) {
+                EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
+            }
+            {
+                Buf ws(bytes);
+                EXPECT(fft3d_set_workspace(p, ws.p, bytes) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, ws.p, out.p, user) == FFT3D_ERR_ALIAS);
+                EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
+            }
+            EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+            EXPECT(fft3d_set_staging(p, 2) == FFT3D_ERR_INVALID_ARG);
             EXPECT(fft3d_destroy(p) == FFT3D_OK);
         }
+    }
+    {  // large plans default to the swapped staging with an owned workspace
+        const size_t bytes = (size_t)512 * 256 * 256 * 16;
+        Buf in(bytes), out(bytes);
+        fft3d_plan_t p = nullptr;
+        EXPECT(fft3d_plan(&p, 512, 256, 256, FFT3D_C128, 2, 2, 0) == FFT3D_OK);
+        EXPECT(fft3d_workspace_bytes(p) == bytes);
+        EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+        EXPECT(fft3d_inverse(p, out.p, in.p, user) == FFT3D_OK);
+        EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        EXPECT(fft3d_plan(&p, 256, 256, 256, FFT3D_C128, 1, 1, 0) == FFT3D_OK);  // 256 MiB: in place
+        EXPECT(fft3d_workspace_bytes(p) == 0);
+        EXPECT(fft3d_destroy(p) == FFT3D_OK);
     }
     fft3d_plan_t p = nullptr;
     EXPECT(fft3d_plan(&p, 8, 8, 7, FFT3D_C64, 1, 1, 0) == FFT3D_ERR_UNSUPPORTED_SIZE);
@@ -112,6 +145,9 @@ void variant_cases(hipStream_t user)
                                 if (!p) continue;
                                 if (fft3d_set_stage_config(p, axis, lw, tdiv, split, pad) == FFT3D_OK) {
                                     ++accepted;
+                                    EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                                    EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+                                    EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
                                     EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
                                     EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
                                 }
@@ -146,6 +182,8 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_poisson_adjoint(p, r2.p, r.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             // caller workspace, then back to a plan-owned one
             const size_t wsb = fft3d_workspace_bytes(p);
             EXPECT(wsb == half_bytes);

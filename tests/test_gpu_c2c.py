@@ -162,3 +162,46 @@ def test_kernel_shape_variants_bitwise(gpu_lib, shape, dtype):
         plan.set_stage_config(axis, 0)
     plan.close()
     assert tried > 10
+
+
+STAGING_CASES = [((32, 32, 32), (1, 1)), ((16, 12, 20), (2, 3)), ((64, 48, 100), (3, 3)), ((64, 64, 512), (1, 1)),
+                 ((512, 8, 16), (1, 1)), ((1, 4, 8), (1, 1)), ((5, 6, 4), (2, 2))]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid", STAGING_CASES, ids=[f"{s}-{g}" for s, g in STAGING_CASES])
+def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
+    """The y stage writes a y/z-swapped workspace and the z stage reads it back:
+    forward bitwise equal to in-place staging (same line arithmetic), inverse and
+    backward (run x, y, z) against the oracle; in place and a caller workspace."""
+    print(f"case staging swap_yz shape={shape} grid={grid} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 31)
+    x = to_dev(a, dtype)
+    ref_in = promoted(a, dtype)
+    tol = bound(dtype, a.size)
+    base = gpu_lib.Plan(shape, dtype, grid)
+    want_fwd = base.forward(x)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=3, staging=gpu_lib.STAGING_SWAP_YZ)
+    assert plan.workspace_bytes() == x.numel() * x.element_size()
+    X = plan.forward(x)
+    xi = plan.inverse(x)
+    xb = plan.backward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(X, want_fwd)
+    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
+    assert rel(to_host(xi), oracle.ifftn(ref_in)) <= tol
+    assert rel(to_host(xb), oracle.bfftn(ref_in)) <= tol
+    # in place, then with a caller workspace
+    y = x.clone()
+    plan.forward(y, out=y)
+    ws = torch.empty_like(x)
+    plan.set_workspace(ws)
+    z = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, want_fwd) and torch.equal(z, want_fwd)
+    from paper_2601_12209_amd._lib import Fft3dError
+
+    with pytest.raises(Fft3dError):
+        plan.forward(ws, out=X)  # the workspace overlaps the input
+    plan.close()
+    base.close()

@@ -203,14 +203,14 @@ def _apply_stage(st, box, bufs, shape):
         raise AssertionError(kind)
 
 
-def _simulate(fft3d, shape, grid, op, ns, inp, rng):
+def _simulate(fft3d, shape, grid, op, ns, inp, rng, staging=0):
     r2c = op >= 3 or np.isrealobj(inp) or inp.shape[2] != shape[2]
-    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=ns)
+    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=ns, staging=staging)
     nz, ny, nx = shape
     nxc = nx // 2 + 1
     if not r2c:
         out = np.full(shape, np.nan + 0j)
-        ws = None
+        ws = np.full(shape, np.nan + 0j) if staging else None
     else:
         out_real = op in (1, 2, 3, 4)
         out = np.full(shape, np.nan) if out_real else np.full((nz, ny, nxc), np.nan + 0j)
@@ -240,14 +240,28 @@ def _simulate(fft3d, shape, grid, op, ns, inp, rng):
 SIM_CASES = [((6, 4, 8), (2, 2), 2), ((5, 6, 10), (3, 2), 4), ((8, 6, 4), (1, 3), 1), ((4, 4, 6), (2, 1), 3)]
 
 
+@pytest.mark.parametrize("staging", [0, 1], ids=["in_place", "swap_yz"])
 @pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
-def test_simulated_c2c(fft3d, shape, grid, ns):
+def test_simulated_c2c(fft3d, shape, grid, ns, staging):
     rng = np.random.default_rng(0)
     a = synth.complex_normal(shape, 1)
     for trial in range(3):
-        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 0, ns, a, rng), oracle.fftn(a)) < 1e-14
-        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 1, ns, a, rng), oracle.ifftn(a)) < 1e-14
-        assert oracle.rel_l2(_simulate(fft3d, shape, grid, 2, ns, a, rng), oracle.bfftn(a)) < 1e-14
+        for op, want in ((0, oracle.fftn(a)), (1, oracle.ifftn(a)), (2, oracle.bfftn(a))):
+            got = _simulate(fft3d, shape, grid, op, ns, a, rng, staging)
+            assert oracle.rel_l2(got, want) < 1e-14, op
+
+
+def test_swap_yz_staging_layouts(fft3d):
+    """y writes the workspace with y/z swapped, z reads it back; x, y, z in every direction."""
+    for op in (0, 1, 2):
+        stages, _ = fft3d.query_pipeline((8, 6, 4), (2, 2), op=op, nstreams=2, staging=1)
+        assert [st["axis"] for st in stages] == [0, 1, 2]
+        assert [(st["src"], st["dst"]) for st in stages] == [(0, 1), (1, 2), (2, 1)]
+        assert [(st["lay_src"], st["lay_dst"]) for st in stages] == [(0, 0), (0, 1), (1, 0)]
+        assert [st["conj"] for st in stages] == [int(op != 0)] * 3
+        assert stages[2]["scale"] == (1.0 / (8 * 6 * 4) if op == 1 else 1.0)
+    with pytest.raises(ValueError):  # R2C plans stage in place only
+        fft3d.query_pipeline((8, 6, 4), (1, 1), r2c=True, staging=1)
 
 
 @pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
