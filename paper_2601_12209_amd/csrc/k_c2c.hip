@@ -37,9 +37,12 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     if (a.strided) {
         const int lw = t % a.lw;
         tj = t / a.lw;
-        const int64_t aa0 = (int64_t)blockIdx.x * a.lw + lw;
-        ok = aa0 < a.A;
-        const int64_t aa = ok ? aa0 : a.A - 1;
+        // with a.align, the tiles of this row start `shift` lines early so that
+        // every output segment covers whole cache lines
+        const int64_t shift = a.align > 1 ? (a.off_o + (int64_t)blockIdx.y * a.sb_o) % a.align : 0;
+        const int64_t aa0 = (int64_t)blockIdx.x * a.lw + lw - shift;
+        ok = aa0 >= 0 && aa0 < a.A;
+        const int64_t aa = aa0 < 0 ? 0 : (aa0 < a.A ? aa0 : a.A - 1);
         base = a.off + aa + (int64_t)blockIdx.y * a.sb;
         base_o = a.off_o + aa + (int64_t)blockIdx.y * a.sb_o;
         L = LdsView<cpx<T>>{lds + lw, a.lw, 0};
@@ -87,7 +90,7 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
     const size_t lds = align16((size_t)a.lw * line * elem) + pass_table_bytes<T, N>();
     dim3 grid;
-    if (a.strided) grid = dim3((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
+    if (a.strided) grid = dim3((unsigned)((a.A + (a.align > 1 ? a.align - 1 : 0) + a.lw - 1) / a.lw), (unsigned)a.B, 1);
     else grid = dim3((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;

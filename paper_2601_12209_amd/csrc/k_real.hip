@@ -18,6 +18,15 @@
 
 namespace fft3d {
 
+// LDS bytes of a real-kernel launch: lw lines of H + 1 values and the pass
+// table of the length-H FFT.
+template <typename T, int N>
+constexpr size_t real_lds_bytes(int lw)
+{
+    constexpr int H = N / 2;
+    return align16((size_t)lw * (H + 1) * sizeof(cpx<T>)) + pass_table_bytes<T, H>();
+}
+
 template <typename T, int N>
 __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
 {
@@ -34,7 +43,8 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table (pre/post-processing)
+    // W_N^k for the split step: a few KiB read by every workgroup, served by the caches
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
     LdsView<cpx<T>> L{lds + lw * H, 1, 0};
     LdsView<T> Ls{nullptr, 0, 0};
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * H * sizeof(cpx<T>)));
@@ -46,7 +56,8 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     const T half = (T)0.5;
     const T wgt = a.weight ? (T)2 : (T)1;
     const T scale = (T)a.scale;
-    for (int k = tj; k <= H; k += TPL) {
+    // bins k = tj + i*TPL (i < H/TPL) on every thread, bin H on thread 0
+    auto bin = [&](int k) {
         const cpx<T> zk = L[k == H ? 0 : k];
         const cpx<T> zr = conj(L[k == 0 ? 0 : H - k]);
         const cpx<T> e = (zk + zr) * half;
@@ -54,7 +65,10 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
         cpx<T> x = e + cmul(tw[k], o);
         if (k > 0 && k < H) x = x * wgt;
         if (ok) out[k] = x * scale;
-    }
+    };
+#pragma unroll
+    for (int i = 0; i < H / TPL; ++i) bin(tj + i * TPL);
+    if (tj == 0) bin(H);
 }
 
 template <typename T, int N>
@@ -73,17 +87,29 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     const cpx<T>* __restrict__ in =
         reinterpret_cast<const cpx<T>*>(a.in) + a.off + aa * a.sa + bb * a.sb;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);  // W_N table (pre/post-processing)
+    // W_N^k for the merge step: a few KiB read by every workgroup, served by the caches
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
     LdsView<cpx<T>> L{lds + lw * (H + 1), 1, 0};
     LdsView<T> Ls{nullptr, 0, 0};
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * (H + 1) * sizeof(cpx<T>)));
     stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const T wgt = a.weight ? (T)0.5 : (T)1;
-    for (int k = tj; k <= H; k += TPL) {
-        cpx<T> v = in[k];
-        if (k == 0 || k == H) v.im = (T)0;
+    // every load first (bins tj + i*TPL, and bin H on thread 0), then the LDS writes
+    cpx<T> pre[H / TPL];
+#pragma unroll
+    for (int i = 0; i < H / TPL; ++i) pre[i] = in[tj + i * TPL];
+    cpx<T> top = in[H];
+#pragma unroll
+    for (int i = 0; i < H / TPL; ++i) {
+        const int k = tj + i * TPL;
+        cpx<T> v = pre[i];
+        if (k == 0) v.im = (T)0;
         else v = v * wgt;
         L[k] = v;
+    }
+    if (tj == 0) {
+        top.im = (T)0;
+        L[H] = top;
     }
     __syncthreads();
     // conjugate-sign DFT as conj(F(conj Z'))
@@ -109,7 +135,7 @@ static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
         constexpr int H = N / 2;
         constexpr int TPL = radix_plan(H).tpl;
         const int threads = a.lw * TPL;
-        const size_t lds = align16((size_t)a.lw * (H + 1) * sizeof(cpx<T>)) + pass_table_bytes<T, H>();
+        const size_t lds = real_lds_bytes<T, N>(a.lw);
         const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
         if (grid.x == 0) return hipSuccess;
         if (r2c) {

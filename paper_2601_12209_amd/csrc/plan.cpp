@@ -93,9 +93,10 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op)
     }
     switch (op) {
     case OP_FORWARD:
-        s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_OUT));
-        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_OUT, BUF_OUT));
-        s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+        // x and y in the workspace (rows on cache-line bounds), z writes the output
+        s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_WS));
+        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+        s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_WS, BUF_OUT));
         break;
     case OP_INVERSE:
     case OP_BACKWARD:

@@ -38,6 +38,13 @@ struct PlanDesc {
     int r2c;
     int staging = STAGING_IN_PLACE;  // C2C plans only
     int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent
+    // row pitch (complex elements) of the workspace: the complex x extent
+    // rounded up to 128 bytes, so workspace rows start on cache-line bounds
+    int64_t wpitch() const
+    {
+        const int64_t per_line = dtype == 1 ? 8 : 16;  // complex values per 128 bytes
+        return (nxc() + per_line - 1) / per_line * per_line;
+    }
 };
 
 // Half-open index box over the complex array (x, y, z).

@@ -154,24 +154,28 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
     return c;
 }
 
-// Element strides of the complex array in a layout: (x, y, z).
-void layout_strides(const PlanDesc& d, int lay, int64_t st[3])
+// Row pitch (complex elements) of a complex buffer: the workspace rows are
+// padded to 128 bytes, caller buffers are dense.
+int64_t row_pitch(const PlanDesc& d, int buf) { return buf == BUF_WS ? d.wpitch() : d.nxc(); }
+
+// Element strides (x, y, z) of a complex buffer in a layout.
+void layout_strides(const PlanDesc& d, int buf, int lay, int64_t st[3])
 {
-    const int64_t nxc = d.nxc();
+    const int64_t pitch = row_pitch(d, buf);
     st[0] = 1;
     if (lay == LAY_SWAP_YZ) {
-        st[1] = nxc * d.nz;
-        st[2] = nxc;
+        st[1] = pitch * d.nz;
+        st[2] = pitch;
     } else {
-        st[1] = nxc;
-        st[2] = nxc * d.ny;
+        st[1] = pitch;
+        st[2] = pitch * d.ny;
     }
 }
 
 StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* const bufs[3])
 {
     const PlanDesc& d = p->d;
-    const int64_t nxc = d.nxc(), ny = d.ny;
+    const int64_t ny = d.ny;
     StageArgs a;
     memset(&a, 0, sizeof a);
     a.in = bufs[st.src];
@@ -188,18 +192,19 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.A = b.hi[ax_a] - b.lo[ax_a];
     a.B = b.hi[ax_b] - b.lo[ax_b];
     if (st.kind == K_R2C_X || st.kind == K_C2R_X) {
-        // real rows: nx reals = nx/2 complex pairs per row
+        // real rows: nx reals = nx/2 complex pairs per row (dense); complex
+        // rows: the buffer's row pitch
         const int64_t h = d.nx / 2;
         const int64_t row = b.lo[1] + ny * b.lo[2];
-        const int64_t ci = nxc, ri = h;  // complex / real-pair row lengths
-        const int64_t li = st.kind == K_R2C_X ? ri : ci, lo = st.kind == K_R2C_X ? ci : ri;
+        const int64_t li = st.kind == K_R2C_X ? h : row_pitch(d, st.src);
+        const int64_t lo = st.kind == K_R2C_X ? row_pitch(d, st.dst) : h;
         a.off = row * li; a.sa = li; a.sb = li * ny; a.se = 1;
         a.off_o = row * lo; a.sa_o = lo; a.sb_o = lo * ny; a.se_o = 1;
         a.strided = 0;
     } else {
         int64_t si[3], so[3];
-        layout_strides(d, st.lay_src, si);
-        layout_strides(d, st.lay_dst, so);
+        layout_strides(d, st.src, st.lay_src, si);
+        layout_strides(d, st.dst, st.lay_dst, so);
         a.off = b.lo[0] * si[0] + b.lo[1] * si[1] + b.lo[2] * si[2];
         a.sa = si[ax_a]; a.sb = si[ax_b]; a.se = si[st.axis];
         a.off_o = b.lo[0] * so[0] + b.lo[1] * so[1] + b.lo[2] * so[2];
@@ -221,6 +226,12 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.tdiv = c.tdiv;
     a.split = c.split;
     a.pad = c.pad;
+    // strided C2C tiles writing rows that do not start on cache lines: shift
+    // each row's tiles so the stores cover whole lines (partial-line stores
+    // cost about as much again on MI355X)
+    const int64_t per_line = 128 / (int64_t)elem_bytes(d.dtype);
+    if (st.kind == K_C2C && a.strided && c.lw % per_line == 0 && a.sb_o % per_line != 0 && a.se_o % per_line == 0)
+        a.align = (int)per_line;
     return a;
 }
 
@@ -469,7 +480,7 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         }
     }
     if (r2c) {
-        p->ws_bytes = (size_t)d.nxc() * ny * nz * elem_bytes(dtype);
+        p->ws_bytes = (size_t)d.wpitch() * ny * nz * elem_bytes(dtype);
         e = hipMalloc(&p->ws, p->ws_bytes);
         if (e != hipSuccess) {
             p->ws = nullptr;
@@ -481,7 +492,7 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
     // large C2C plans stage through a y/z-swapped workspace by default (see
     // fft3d_set_staging); if it cannot be allocated they stage in place
     if (!r2c && ny > 1 && nz > 1 && (size_t)nx * ny * nz * elem_bytes(dtype) >= kSwapStagingMinBytes) {
-        const size_t need = (size_t)nx * ny * nz * elem_bytes(dtype);
+        const size_t need = (size_t)d.wpitch() * ny * nz * elem_bytes(dtype);
         if (hipMalloc(&p->ws, need) == hipSuccess) {
             p->d.staging = STAGING_SWAP_YZ;
             p->ws_owned = true;
@@ -544,8 +555,7 @@ static fft3d_status c2c_or_r2c(fft3d_plan_t p, int op, const void* in, void* out
         const size_t out_bytes = op == OP_FORWARD ? half_bytes : real_bytes;
         if (ranges_overlap(in, in_bytes, out, out_bytes))
             return fail(FFT3D_ERR_ALIAS, "real-to-complex transforms cannot run in place");
-        if (op != OP_FORWARD &&
-            (ranges_overlap(p->ws, p->ws_bytes, in, in_bytes) || ranges_overlap(p->ws, p->ws_bytes, out, out_bytes)))
+        if (ranges_overlap(p->ws, p->ws_bytes, in, in_bytes) || ranges_overlap(p->ws, p->ws_bytes, out, out_bytes))
             return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
     }
     return run(p, op, in, out, stream);
@@ -593,7 +603,7 @@ size_t fft3d_workspace_bytes(fft3d_plan_t p)
 {
     if (!p) return 0;
     if (!p->d.r2c && p->d.staging != STAGING_SWAP_YZ) return 0;
-    return (size_t)p->d.nxc() * p->d.ny * p->d.nz * elem_bytes(p->d.dtype);
+    return (size_t)p->d.wpitch() * p->d.ny * p->d.nz * elem_bytes(p->d.dtype);
 }
 
 fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)

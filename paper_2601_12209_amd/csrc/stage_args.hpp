@@ -29,6 +29,8 @@ struct StageArgs {
     int64_t off, sa, sb, se;
     int64_t off_o, sa_o, sb_o, se_o;
     int strided;  // 1: lanes of a wavefront walk neighbouring lines (requires sa == sa_o == 1)
+    int align;    // strided: > 1 shifts each row's line tiles so that output row segments
+                  // start on multiples of `align` elements (a cache line); lw % align == 0
     int lw;       // lines per workgroup
     int tdiv;     // threads per line = (default threads per line) / tdiv
     int split;    // 1: exchange real and imaginary parts through LDS separately

@@ -47,6 +47,13 @@ struct Buf {
 
 size_t es_of(int dtype) { return dtype == FFT3D_C128 ? 16 : 8; }
 
+// Workspace rows are padded to 128 bytes.
+size_t padded(int64_t n, int dtype)
+{
+    const int64_t per = 128 / (int64_t)es_of(dtype);
+    return (size_t)((n + per - 1) / per * per);
+}
+
 hipStream_t make_stream()
 {
     hipStream_t s = nullptr;
@@ -87,7 +94,8 @@ void c2c_cases(hipStream_t user)
             EXPECT(fft3d_workspace_bytes(p) == 0);
             EXPECT(fft3d_set_workspace(p, in.p, bytes) == FFT3D_ERR_WRONG_PLAN);
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
-            EXPECT(fft3d_workspace_bytes(p) == bytes);
+            const size_t wsb = padded(c.nx, dtype) * c.ny * c.nz * es_of(dtype);
+            EXPECT(fft3d_workspace_bytes(p) == wsb);
             for (int ns : {1, 4}) {
                 EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
                 EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
@@ -95,8 +103,9 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
             }
             {
-                Buf ws(bytes);
-                EXPECT(fft3d_set_workspace(p, ws.p, bytes) == FFT3D_OK);
+                Buf ws(wsb);
+                EXPECT(fft3d_set_workspace(p, ws.p, wsb - 1) == FFT3D_ERR_WORKSPACE);
+                EXPECT(fft3d_set_workspace(p, ws.p, wsb) == FFT3D_OK);
                 EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
                 EXPECT(fft3d_forward(p, ws.p, out.p, user) == FFT3D_ERR_ALIAS);
                 EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
@@ -186,7 +195,7 @@ void r2c_cases(hipStream_t user)
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             // caller workspace, then back to a plan-owned one
             const size_t wsb = fft3d_workspace_bytes(p);
-            EXPECT(wsb == half_bytes);
+            EXPECT(wsb == padded(c.nx / 2 + 1, dtype) * c.ny * c.nz * es);
             {
                 Buf ws(wsb);
                 EXPECT(fft3d_set_workspace(p, ws.p, wsb - 1) == FFT3D_ERR_WORKSPACE);

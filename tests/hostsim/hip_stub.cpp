@@ -428,17 +428,21 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
     const int threads = a.lw * (radix_plan(n).tpl / tdiv);
     const size_t line = a.strided ? (size_t)n : (size_t)(n + a.pad * (n / 8));
     const size_t lds = align16((size_t)a.lw * line * (a.split ? es / 2 : es)) + table_entries(n) * es;
-    const int64_t blocks = a.strided ? (a.A + a.lw - 1) / a.lw : (a.A * a.B + a.lw - 1) / a.lw;
+    const int64_t blocks = a.strided ? (a.A + (a.align > 1 ? a.align - 1 : 0) + a.lw - 1) / a.lw
+                                     : (a.A * a.B + a.lw - 1) / a.lw;
+    if (a.align > 1 && (!a.strided || a.lw % a.align != 0)) violation("c2c align without a strided tile of whole lines");
     if (blocks == 0 || (a.strided && a.B == 0)) return hipSuccess;
     if (threads > kMaxThreads || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
     if (a.strided && (a.sa != 1 || a.B > 65535)) violation("c2c strided tile with sa != 1 or too many rows");
     if (blocks > 0x7fffffff) violation("c2c grid too large");
     if (a.strided) {
+        if (a.sa_o != 1) violation("c2c strided tile with sa_o != 1");
         check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "c2c strided load");
-        check_range(a.out, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "c2c strided store");
+        check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "c2c strided store");
     } else {
+        if (a.se != 1 || a.se_o != 1) violation("c2c contiguous tile with element stride != 1");
         check_range(a.in, es, a.off, a.A, a.sa, a.B, a.sb, n, 1, "c2c load");
-        check_range(a.out, es, a.off, a.A, a.sa, a.B, a.sb, n, 1, "c2c store");
+        check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, n, 1, "c2c store");
     }
     check_tables(a, n, es, "c2c pass table");
     return launched(s);
@@ -474,9 +478,9 @@ hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     const size_t lds = align16((size_t)a.lw * n * es) + table_entries(n) * es;
     if ((a.A + a.lw - 1) / a.lw == 0 || a.B == 0) return hipSuccess;
     if (threads > kMaxThreads || lds > kMaxLdsBytes) violation("poisson kernel shape over the limits");
-    if (a.sa != 1) violation("poisson tile with sa != 1");
+    if (a.sa != 1 || a.sa_o != 1) violation("poisson tile with sa != 1");
     check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson load");
-    check_range(a.out, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson store");
+    check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "poisson store");
     check_tables(a, n, es, "poisson pass table");
     return launched(s);
 }

@@ -182,7 +182,9 @@ def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
     base = gpu_lib.Plan(shape, dtype, grid)
     want_fwd = base.forward(x)
     plan = gpu_lib.Plan(shape, dtype, grid, streams=3, staging=gpu_lib.STAGING_SWAP_YZ)
-    assert plan.workspace_bytes() == x.numel() * x.element_size()
+    per_line = 128 // x.element_size()  # workspace rows are padded to 128 bytes
+    pitch = -(-shape[2] // per_line) * per_line
+    assert plan.workspace_bytes() == pitch * shape[0] * shape[1] * x.element_size()
     X = plan.forward(x)
     xi = plan.inverse(x)
     xb = plan.backward(x)
@@ -194,7 +196,7 @@ def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
     # in place, then with a caller workspace
     y = x.clone()
     plan.forward(y, out=y)
-    ws = torch.empty_like(x)
+    ws = torch.empty(plan.workspace_bytes() // x.element_size(), dtype=x.dtype, device="cuda")
     plan.set_workspace(ws)
     z = plan.forward(x)
     torch.cuda.synchronize()
@@ -202,6 +204,6 @@ def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
     from paper_2601_12209_amd._lib import Fft3dError
 
     with pytest.raises(Fft3dError):
-        plan.forward(ws, out=X)  # the workspace overlaps the input
+        plan.forward(ws[: x.numel()].view(shape), out=X)  # the workspace overlaps the input
     plan.close()
     base.close()
