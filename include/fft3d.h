@@ -161,6 +161,16 @@ fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
 /*
+ * Graph replay of forked pipelines: capture the whole task graph of a call
+ * that forks onto the plan's streams (fork, every tile launch, the event
+ * edges, join) into a hipGraph once per operation and buffer set, and replay
+ * it.  Currently switched off: enable = 1 returns FFT3D_ERR_INVALID_ARG and
+ * every call is issued directly (a caller capturing its stream still records
+ * the launches into its own graph).  enable = 0 is accepted.
+ */
+fft3d_status fft3d_set_graphs(fft3d_plan_t plan, int enable);
+
+/*
  * Override the launch shape of the stage kernels along one axis (0 = x,
  * 1 = y, 2 = z) of this plan: lw lines per workgroup (a power of two; 0
  * restores the default shape), tdiv divides the threads that cooperate on one

@@ -27,6 +27,7 @@ _SIGS = {
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
     "fft3d_set_staging": (I32, [P, I32]),
+    "fft3d_set_graphs": (I32, [P, I32]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
     "fft3d_set_timing": (I32, [P, I32]),
     "fft3d_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), I32]),

@@ -38,6 +38,7 @@ fft3d_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr int kMaxStreams = 16;
+constexpr size_t kMaxGraphs = 8;  // cached pipeline graphs per plan
 // C2C plans of at least this many bytes default to the swapped-y/z staging
 // (measured on MI355X: faster at 512^3, slower at 256^3, whose 128-256 MiB
 // field stays in the 256 MB Infinity Cache)
@@ -80,6 +81,18 @@ struct fft3d_plan_s {
     bool pipe_ok[OP_COUNT] = {};
     std::vector<char> needs_event[OP_COUNT];
     KConf conf_override[3];  // per axis; lw == 0: default
+    // forked pipelines issued on a non-default stream are captured once per
+    // (operation, buffers) into a hipGraph and replayed
+    struct CachedGraph {
+        int op;
+        const void* in;
+        void* out;
+        void* ws;
+        hipGraphExec_t exec;
+    };
+    bool use_graphs = false;  // replay is switched off (see fft3d_set_graphs)
+    std::vector<CachedGraph> graphs;
+    hipStream_t graph_stream = nullptr;  // stream of the last graph launch
     // per-stage timing (tracing): events around every stage of the last call
     bool timing = false;
     std::vector<hipEvent_t> tev;  // 6 timing events (up to 5 stages)
@@ -352,6 +365,48 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
     return FFT3D_OK;
 }
 
+// Destroy the cached graphs (after the last replay has finished).
+void drop_graphs(fft3d_plan_s* p)
+{
+    if (p->graphs.empty()) return;
+    hipStreamSynchronize(p->graph_stream);
+    for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+}
+
+fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user);
+
+// Replay (capturing on first use) the forked pipeline of this operation and
+// these buffers on a non-default stream that is not being captured.
+fft3d_status run_graph(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user)
+{
+    fft3d_plan_s::CachedGraph* hit = nullptr;
+    for (auto& g : p->graphs)
+        if (g.op == op && g.in == bufs[0] && g.out == bufs[1] && g.ws == bufs[2]) hit = &g;
+    if (!hit) {
+        if (p->graphs.size() >= kMaxGraphs) drop_graphs(p);
+        hipError_t e = hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        fft3d_status st = issue_forked(p, op, pl, bufs, user);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(user, &graph);
+        if (st != FFT3D_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        p->graphs.push_back({op, bufs[0], bufs[1], bufs[2], exec});
+        hit = &p->graphs.back();
+    }
+    p->graph_stream = user;
+    hipError_t e = hipGraphLaunch(hit->exec, user);
+    return e == hipSuccess ? FFT3D_OK : hip_fail(e, "hipGraphLaunch");
+}
+
 fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* stream)
 {
     const Pipeline& pl = get_pipeline(p, op);
@@ -369,8 +424,23 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
         }
         return FFT3D_OK;
     }
+    if (p->use_graphs && user != nullptr) {
+        // the legacy default stream cannot be captured; a stream the caller is
+        // capturing takes the launches into the caller's graph
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        e = hipStreamIsCapturing(user, &cap);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+        if (cap == hipStreamCaptureStatusNone) return run_graph(p, op, pl, bufs, user);
+    }
+    return issue_forked(p, op, pl, bufs, user);
+}
+
+// Fork onto the plan's streams, one event edge per cross-stream dependency,
+// join back onto the caller's stream.
+fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user)
+{
     const std::vector<char>& need = p->needs_event[op];
-    e = hipEventRecord(p->fork, user);
+    hipError_t e = hipEventRecord(p->fork, user);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
     std::vector<char> started(p->nstreams, 0);
     std::vector<int> last(p->nstreams, -1);
@@ -405,6 +475,7 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
 
 void release(fft3d_plan_s* p)
 {
+    drop_graphs(p);
     for (hipStream_t s : p->streams)
         if (s) {
             hipStreamSynchronize(s);
@@ -615,6 +686,7 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
     if (ws && bytes < need) return fail(FFT3D_ERR_WORKSPACE, "workspace smaller than fft3d_workspace_bytes");
     if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     // the old workspace may still be in use by enqueued work
+    drop_graphs(p);
     for (hipStream_t s : p->streams)
         if (s) hipStreamSynchronize(s);
     if (ws) {
@@ -642,6 +714,7 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     if (p->d.r2c) return staging == STAGING_IN_PLACE ? FFT3D_OK
                                                      : fail(FFT3D_ERR_WRONG_PLAN, "swap-y/z staging is for C2C plans");
     if (staging == p->d.staging) return FFT3D_OK;
+    drop_graphs(p);
     // enqueued work may still use the old workspace (hipFree waits for the device)
     if (p->ws && p->ws_owned) hipFree(p->ws);
     p->ws = nullptr;
@@ -663,10 +736,21 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     return FFT3D_OK;
 }
 
+fft3d_status fft3d_set_graphs(fft3d_plan_t p, int enable)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (enable)  // the first replay test of this path ended in a host segfault on MI355X, cause not found
+        return fail(FFT3D_ERR_INVALID_ARG, "graph replay of forked pipelines is switched off");
+    drop_graphs(p);
+    p->use_graphs = false;
+    return FFT3D_OK;
+}
+
 fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
     if (nstreams < 1 || nstreams > kMaxStreams) return fail(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
+    drop_graphs(p);
     p->nstreams = nstreams;
     if (forks(p)) {
         hipError_t e = ensure_streams(p, nstreams);
@@ -680,6 +764,7 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
     if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
     if (lw == 0) {
+        drop_graphs(p);
         p->conf_override[axis] = KConf();
         return FFT3D_OK;
     }
@@ -698,6 +783,7 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
                                                    "(threads, LDS, or no such kernel variant)");
         }
     }
+    drop_graphs(p);
     p->conf_override[axis] = c;
     return FFT3D_OK;
 }

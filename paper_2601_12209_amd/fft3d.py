@@ -144,6 +144,10 @@ class Plan:
     def set_streams(self, n: int):
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
 
+    def set_graphs(self, enable: bool):
+        """Replay forked pipelines from captured hipGraphs on non-default streams (default on)."""
+        check(_lib.lib().fft3d_set_graphs(self._h, int(bool(enable))), "fft3d_set_graphs")
+
     def set_staging(self, staging: int):
         """STAGING_IN_PLACE (no workspace) or STAGING_SWAP_YZ (C2C: y stage writes a
         y/z-swapped workspace that the z stage reads back)."""

@@ -87,6 +87,9 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
                 EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
             }
+            // graph replay of forked pipelines is switched off
+            EXPECT(fft3d_set_graphs(p, 1) == FFT3D_ERR_INVALID_ARG);
+            EXPECT(fft3d_set_graphs(p, 0) == FFT3D_OK);
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
             if (bytes >= 2 * es_of(dtype))  // partial overlap
                 EXPECT(fft3d_forward(p, in.p, (char*)in.p + es_of(dtype), user) == FFT3D_ERR_ALIAS);
