@@ -61,31 +61,37 @@ def _wavenumbers(n: int) -> np.ndarray:
     return np.where(2 * k <= n, k, k - n)
 
 
-def turbulence_field(shape, seed: int, dtype=np.float32, workers: int | None = None) -> np.ndarray:
-    """Random-phase Fourier modes with amplitude |k|^(-11/6) (energy ~ k^(-5/3)).
+def turbulence_spectrum(shape, seed: int, cdtype=np.complex64) -> np.ndarray:
+    """Half spectrum (nz, ny, nx//2+1) of random-phase modes: amplitude
+    |k|^(-11/6) for k != 0 (energy ~ k^(-5/3)), 0 at k = 0, phases uniform on
+    [0, 2*pi) from the seed, one (ny, nx//2+1) plane of draws per kz."""
+    nz, ny, nx = shape
+    rdt = np.float32 if cdtype == np.complex64 else np.float64
+    rng = np.random.default_rng(seed)
+    kx = _wavenumbers(nx)[: nx // 2 + 1].astype(rdt)
+    ky = _wavenumbers(ny).astype(rdt)
+    kz = _wavenumbers(nz).astype(rdt)
+    spec = np.empty((nz, ny, nx // 2 + 1), dtype=cdtype)
+    for z in range(nz):  # plane by plane keeps the temporaries small
+        k2 = kz[z] ** 2 + ky[:, None] ** 2 + kx[None, :] ** 2
+        with np.errstate(divide="ignore"):
+            amp = np.where(k2 > 0, k2 ** rdt(-11.0 / 12.0), rdt(0.0))
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(ny, nx // 2 + 1)).astype(rdt)
+        spec[z] = amp * (np.cos(ph) + 1j * np.sin(ph))
+    return spec
 
-    The half spectrum (nz, ny, nx//2+1) gets amplitude |k|^(-11/6) for k != 0
-    and 0 at k = 0, and phases uniform on [0, 2*pi) from the seed.  A library
-    inverse real FFT (``scipy.fft.irfftn``) turns it into a real field, which is
-    normalised to unit variance.  The spectrum is built in complex64 to bound
-    host memory at 1024^3.
-    """
+
+def turbulence_field(shape, seed: int, dtype=np.float32, workers: int | None = None) -> np.ndarray:
+    """Real field of the turbulence spectrum, normalised to zero mean and unit
+    variance.  A library inverse real FFT (``scipy.fft.irfftn``) turns the half
+    spectrum into the field; for float32 output the spectrum is built in
+    complex64 to bound host memory at 1024^3, for float64 in complex128."""
     import os
 
     import scipy.fft
 
     nz, ny, nx = shape
-    rng = np.random.default_rng(seed)
-    kx = _wavenumbers(nx)[: nx // 2 + 1].astype(np.float32)
-    ky = _wavenumbers(ny).astype(np.float32)
-    kz = _wavenumbers(nz).astype(np.float32)
-    spec = np.empty((nz, ny, nx // 2 + 1), dtype=np.complex64)
-    for z in range(nz):  # plane by plane keeps the temporaries small
-        k2 = kz[z] ** 2 + ky[:, None] ** 2 + kx[None, :] ** 2
-        with np.errstate(divide="ignore"):
-            amp = np.where(k2 > 0, k2 ** np.float32(-11.0 / 12.0), np.float32(0.0))
-        ph = rng.uniform(0.0, 2.0 * np.pi, size=(ny, nx // 2 + 1)).astype(np.float32)
-        spec[z] = amp * (np.cos(ph) + 1j * np.sin(ph))
+    spec = turbulence_spectrum(shape, seed, np.complex64 if dtype == np.float32 else np.complex128)
     if workers is None:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
     u = scipy.fft.irfftn(spec, s=(nz, ny, nx), axes=(0, 1, 2), workers=workers)

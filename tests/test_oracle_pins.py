@@ -228,3 +228,33 @@ def test_poisson_self_adjoint_and_gradient():
     eps = 1e-3
     fd = (np.sum(oracle.poisson(f + eps * d) * w) - np.sum(oracle.poisson(f - eps * d) * w)) / (2 * eps)
     assert abs(fd - np.sum(g * d)) < 1e-10 * abs(fd)
+
+
+# ------------------------------------------------------------------ input recipes
+
+def test_turbulence_field_recovers_projected_spectrum():
+    """The FP64 R2C of the turbulence field is its half spectrum made Hermitian
+    (the kx = 0 and kx = nx/2 planes averaged with their mirrored conjugates)
+    and scaled by the normalisation: pins the recipe of the 1024^3 workload on
+    a small grid."""
+    shape = (12, 10, 16)
+    nz, ny, nx = shape
+    u = synth.turbulence_field(shape, 3, np.float64)
+    assert abs(u.mean()) < 1e-12 and abs(u.std() - 1.0) < 1e-12
+    S = synth.turbulence_spectrum(shape, 3, np.complex128)
+    P = S.copy()
+    for kx in (0, nx // 2):
+        plane = S[:, :, kx]
+        mirror = np.conj(plane[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny])
+        P[:, :, kx] = 0.5 * (plane + mirror)
+    P[0, 0, 0] = 0.0
+    H = oracle.rfftn(u)
+    # u = (irfftn(S) - mean) / std and irfftn carries 1/N: H = P * N_scale
+    scale = H.ravel()[np.argmax(np.abs(P.ravel()))] / P.ravel()[np.argmax(np.abs(P.ravel()))]
+    assert abs(scale.imag) < 1e-12 * abs(scale) and scale.real > 0
+    assert oracle.rel_l2(H, P * scale.real) < 1e-12
+    # spectrum amplitudes follow |k|^(-11/6) off the projected planes
+    k = np.sqrt(synth._wavenumbers(nz)[:, None, None] ** 2 + synth._wavenumbers(ny)[None, :, None] ** 2
+                + np.arange(nx // 2 + 1)[None, None, :] ** 2)
+    inner = np.abs(S[:, :, 1:nx // 2])
+    assert np.allclose(inner, k[:, :, 1:nx // 2] ** (-11.0 / 6.0), rtol=1e-12)
