@@ -179,6 +179,22 @@ def _extras(reps, torch, fft3d, synth, np):
             p.close()
         del x
         torch.cuda.empty_cache()
+    # 840^3 complex64: the largest grid of the paper's GPU runs (lengths with a
+    # factor 7), whole on one GPU; parity is covered by the GPU tests
+    n8 = 840
+    m8 = n8 ** 3
+    x = torch.randn((n8, n8, n8), dtype=torch.complex64, device="cuda")
+    p = fft3d.Plan((n8, n8, n8), torch.complex64)
+    X = p.forward(x)
+    Y = torch.empty_like(X)
+    with torch.cuda.stream(side):
+        ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), max(3, reps // 2), torch)
+    rep["c2c_840cubed_c64_grid1x1"] = {
+        "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m8 * math.log2(m8) / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(12 * 8 * m8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    p.close()
+    del x, X, Y
+    torch.cuda.empty_cache()
     # 64 uneven transforms issued as one task graph, on a non-default stream
     shapes = synth.batch_sizes()
     host = synth.batch_inputs(shapes, synth.CFG4["seed"])

@@ -53,6 +53,12 @@ template <typename T> FD cpx<T> mul_negi(cpx<T> a) { return {a.im, -a.re}; }  //
 #define K_COS_4PI_5 (-0.809016994374947424102293417182819059L)
 #define K_SIN_2PI_5 0.951056516295153572116439333379382143L
 #define K_SIN_4PI_5 0.587785252292473129168705954639072769L
+#define K_COS_2PI_7 0.623489801858733530525004884004239811L
+#define K_COS_4PI_7 (-0.222520933956314404288902564496794759L)
+#define K_COS_6PI_7 (-0.900968867902419126236102319507445051L)
+#define K_SIN_2PI_7 0.781831482468029808708444526674057750L
+#define K_SIN_4PI_7 0.974927912181823607018131682993931217L
+#define K_SIN_6PI_7 0.433883739117558120475768332848358755L
 #define K_COS_PI_8 0.923879532511286756128183189396788933L
 #define K_SIN_PI_8 0.382683432365089771728459984030398866L
 
@@ -102,6 +108,31 @@ template <typename T> FD void dft5(cpx<T>* v)
     v[4] = a1 + mul_i(b1);
     v[2] = a2 + mul_negi(b2);
     v[3] = a2 + mul_i(b2);
+}
+
+// radix 7 from the mirrored pairs t_j = x_j + x_{7-j}, d_j = x_j - x_{7-j}:
+// X_k = x_0 + sum_j t_j cos(2 pi jk/7) - i sum_j d_j sin(2 pi jk/7), and
+// X_{7-k} the same with +i, for k = 1..3 (jk reduced mod 7 by symmetry).
+template <typename T> FD void dft7(cpx<T>* v)
+{
+    const T c1 = (T)K_COS_2PI_7, c2 = (T)K_COS_4PI_7, c3 = (T)K_COS_6PI_7;
+    const T s1 = (T)K_SIN_2PI_7, s2 = (T)K_SIN_4PI_7, s3 = (T)K_SIN_6PI_7;
+    const cpx<T> t1 = v[1] + v[6], t2 = v[2] + v[5], t3 = v[3] + v[4];
+    const cpx<T> d1 = v[1] - v[6], d2 = v[2] - v[5], d3 = v[3] - v[4];
+    const cpx<T> x0 = v[0];
+    const cpx<T> a1 = x0 + t1 * c1 + t2 * c2 + t3 * c3;
+    const cpx<T> a2 = x0 + t1 * c2 + t2 * c3 + t3 * c1;
+    const cpx<T> a3 = x0 + t1 * c3 + t2 * c1 + t3 * c2;
+    const cpx<T> b1 = d1 * s1 + d2 * s2 + d3 * s3;
+    const cpx<T> b2 = d1 * s2 - d2 * s3 - d3 * s1;
+    const cpx<T> b3 = d1 * s3 - d2 * s1 + d3 * s2;
+    v[0] = x0 + t1 + t2 + t3;
+    v[1] = a1 + mul_negi(b1);
+    v[6] = a1 + mul_i(b1);
+    v[2] = a2 + mul_negi(b2);
+    v[5] = a2 + mul_i(b2);
+    v[3] = a3 + mul_negi(b3);
+    v[4] = a3 + mul_i(b3);
 }
 
 // radix 8 as 2 x 4: u_j = x_j + x_{j+4}, v_j = (x_j - x_{j+4}) W8^j, then DFT4
@@ -155,6 +186,7 @@ template <int R, typename T> FD void dft_radix(cpx<T>* v)
     else if constexpr (R == 3) dft3(v);
     else if constexpr (R == 4) dft4(v);
     else if constexpr (R == 5) dft5(v);
+    else if constexpr (R == 7) dft7(v);
     else if constexpr (R == 8) dft8(v);
     else if constexpr (R == 16) dft16(v);
     else static_assert(R == 2, "unsupported radix");

@@ -100,7 +100,9 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
                            args, lds, s);
 }
 
-// Lengths that also get the TDIV = 2, 4 and SPLIT variants.
+// Lengths that also get the TDIV = 2, 4 and SPLIT variants.  (A TDIV 3
+// variant for 840's odd 105 threads per line spilled and ran slower than
+// 8-line tiles at 840^3, as did the split exchange there.)
 template <int N>
 constexpr bool has_variants()
 {

@@ -148,10 +148,22 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         while (lw * tpl < 256 && lw < 64) lw *= 2;
         const int64_t a = b.hi[0] - b.lo[0];
         lw = (int)std::min<int64_t>(lw, next_pow2(a));
+        // too many threads for lw lines: fewer threads per line (2 or 4) where
+        // the kernel has the variant
         int tdiv = 1;
-        while (c2c && lw * (tpl / tdiv) > 1024 && tdiv < 4 && tpl % (2 * tdiv) == 0 &&
-               c2c_variant_available(nk, 2 * tdiv, 1))
-            tdiv *= 2;
+        if (c2c && lw * tpl > 1024) {
+            for (int td : {2, 4})
+                if (tpl % td == 0 && c2c_variant_available(nk, td, 1) && lw * (tpl / td) <= 1024) {
+                    tdiv = td;
+                    break;
+                }
+            if (tdiv == 1)  // none fits 1024 threads: the largest divisor, lw shrinks below
+                for (int td : {4, 2})
+                    if (tpl % td == 0 && c2c_variant_available(nk, td, 1)) {
+                        tdiv = td;
+                        break;
+                    }
+        }
         c.lw = lw;
         c.tdiv = tdiv;
         c.split = c2c && c2c_variant_available(nk, tdiv, 1) ? 1 : 0;

@@ -36,6 +36,14 @@ CASES = [
     ((16, 1024, 8), (2, 2)),
     ((4096, 2, 2), (1, 1)),
     ((2, 2, 4096), (1, 1)),
+    # radix-7 lengths (7, 14, 21, 28, 35, 42, 56, 840) and 720 = 16*9*5
+    ((14, 21, 28), (2, 2)),
+    ((35, 42, 56), (3, 2)),
+    ((7, 7, 7), (1, 1)),
+    ((840, 3, 4), (1, 1)),
+    ((2, 5, 840), (1, 1)),
+    ((6, 720, 4), (2, 2)),
+    ((105, 70, 112), (1, 1)),
 ]
 
 
@@ -117,7 +125,7 @@ def test_alias_and_argument_errors(gpu_lib):
     from paper_2601_12209_amd._lib import Fft3dError
 
     with pytest.raises(Fft3dError):
-        gpu_lib.Plan((8, 8, 7), torch.complex64)  # 7 has no kernel
+        gpu_lib.Plan((8, 8, 11), torch.complex64)  # 11 has no kernel
     with pytest.raises(Fft3dError):
         gpu_lib.Plan((8, 8, 8), torch.complex64, (9, 1))  # p1 > ny
     plan = gpu_lib.Plan((8, 8, 8), torch.complex64)
@@ -128,7 +136,8 @@ def test_alias_and_argument_errors(gpu_lib):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
-@pytest.mark.parametrize("shape", [(64, 64, 512), (512, 16, 64), (16, 512, 32), (8, 256, 256), (32, 1024, 8)])
+@pytest.mark.parametrize("shape", [(64, 64, 512), (512, 16, 64), (16, 512, 32), (8, 256, 256), (32, 1024, 8),
+                                   (840, 8, 32)])
 def test_kernel_shape_variants_bitwise(gpu_lib, shape, dtype):
     """Launch shapes (lines per block, threads per line, split exchange, padding) reorder
     no arithmetic: every accepted shape gives the default shape's bits."""

@@ -31,6 +31,11 @@ CASES = [
     ((8, 16, 512), (1, 1)),
     ((4, 4, 1024), (1, 1)),
     ((2, 3, 2048), (1, 1)),
+    # radix-7 lengths: 14 = 2*7, 42, 70, 840 = 8*3*5*7, half length 420
+    ((14, 21, 28), (2, 2)),
+    ((7, 35, 84), (1, 3)),
+    ((4, 3, 840), (1, 1)),
+    ((840, 2, 6), (1, 1)),
 ]
 
 

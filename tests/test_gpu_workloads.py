@@ -5,6 +5,8 @@ benchmark times.
   inverse against the FP64 oracle on every output.
 * 256^3 complex64 and complex128, pencil grid 4x4: forward and inverse against
   the oracle on every output.
+* 840^3 complex64 (radix-7 lengths, the largest grid of the paper's GPU
+  runs) by 32 sampled outputs and the round trip.
 * 1024^3 real float32 turbulence field, pencil grid 8x8, R2C then C2R: the
   FP64 oracle cannot take the whole transform in test time, so (i) 82 outputs
   (18 low and Nyquist modes plus 64 seeded random ones) against
@@ -122,6 +124,40 @@ def test_config3_1024cubed_r2c_turbulence(gpu_lib):
     torch.cuda.synchronize()
     del H
     err = rel(to_host(back), u.astype(np.float64))
+    print(f"round trip rel-L2 {err:.3e}", flush=True)
+    assert err <= fp32_bound(n)
+    plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_840cubed_radix7_sampled(gpu_lib):
+    """The largest grid of the paper's GPU runs, 840^3 = (8*3*5*7)^3 complex64, on
+    one GPU: 32 seeded outputs against per-point oracle sums (error measured
+    against the spectral RMS from Parseval) and the round trip on every point."""
+    shape = (840, 840, 840)
+    n = 840 ** 3
+    print("case 840^3 c64: building the field", flush=True)
+    a = synth.complex_normal(shape, 8, np.complex64)
+    x = torch.from_numpy(a).cuda()
+    plan = gpu_lib.Plan(shape, torch.complex64)
+    X = plan.forward(x)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    pts = np.stack([rng.integers(840, size=32) for _ in range(3)], axis=1)
+    pts[0] = (0, 0, 0)
+    pts[1] = (0, 0, 1)
+    a128 = a.astype(np.complex128)
+    want = oracle.dft3d_points(a128, pts)
+    got = X[pts[:, 0], pts[:, 1], pts[:, 2]].cpu().numpy().astype(np.complex128)
+    rms_all = math.sqrt(n * float(np.vdot(a128.ravel(), a128.ravel()).real) / n)
+    err = float(np.sqrt(np.mean(np.abs(got - want) ** 2)) / rms_all)
+    print(f"sampled error / spectral RMS: {err:.3e}", flush=True)
+    assert err <= fp32_bound(n)
+    del a128
+    Y = plan.inverse(X)
+    torch.cuda.synchronize()
+    del X
+    err = rel(to_host(Y), a.astype(np.complex128))
     print(f"round trip rel-L2 {err:.3e}", flush=True)
     assert err <= fp32_bound(n)
     plan.close()

@@ -43,9 +43,10 @@ def test_header_symbols_exported(fft3d):
         assert hasattr(lib, n), f"{n} declared in fft3d.h but not exported"
 
 
-SUPPORTED = [1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 16, 20, 24, 25, 30, 32, 40, 48, 50, 60, 64, 75, 80, 96,
-             100, 120, 125, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 384, 400, 480, 500, 512,
-             600, 640, 750, 768, 800, 960, 1000, 1024, 2048, 4096]
+SUPPORTED = [1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 15, 16, 20, 21, 24, 25, 28, 30, 32, 35, 40, 42, 48, 50,
+             56, 60, 64, 70, 75, 80, 84, 96, 100, 105, 112, 120, 125, 128, 140, 150, 160, 168, 192, 200, 210,
+             240, 250, 256, 280, 300, 320, 384, 400, 420, 480, 500, 512, 600, 640, 720, 750, 768, 800, 840,
+             960, 1000, 1024, 2048, 4096]
 
 
 def test_supported_lengths_and_radix_plans(fft3d):
@@ -54,11 +55,11 @@ def test_supported_lengths_and_radix_plans(fft3d):
     for n in SUPPORTED:
         radices, tpl = fft3d.query_radix_plan(n)
         assert int(np.prod(radices)) == n
-        assert set(radices) <= {2, 3, 4, 5, 8, 16}
+        assert set(radices) <= {2, 3, 4, 5, 7, 8, 16}
         assert tpl == (n // max(radices) if radices else 1)
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 8, 12, 100, 120, 512, 1000, 1024, 4096])
+@pytest.mark.parametrize("n", [2, 3, 5, 7, 8, 12, 100, 120, 512, 840, 1000, 1024, 4096])
 def test_twiddles(fft3d, n):
     w64 = fft3d.query_twiddles(n, "c128")
     m = np.arange(n, dtype=np.longdouble)
