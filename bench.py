@@ -202,14 +202,27 @@ def _extras(reps, torch, fft3d, synth, np):
     outs = [torch.empty_like(t) for t in xs]
     pts = sum(int(np.prod(sh)) for sh in shapes)
     flops = sum(5 * np.prod(sh) * math.log2(np.prod(sh)) for sh in shapes)
-    brep = {"transforms": len(shapes), "points": pts}
+    # shapes whose planes fit the fused x-y kernel take two passes over HBM
+    # (the batch's default there), the others three
+    probe = fft3d.BatchPlan(shapes)
+    fused = set()
+    for sh in set(shapes):
+        try:
+            probe.set_staging(sh, fft3d.STAGING_FUSED_XY)
+            fused.add(sh)
+        except RuntimeError:
+            pass
+    probe.close()
+    bbytes = sum((2 if sh in fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
+    brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
+            "hbm_bytes_per_call": bbytes}
     side = torch.cuda.Stream()
     for mode, name in ((0, "graph_4_streams"), (1, "direct_4_streams"), (2, "serial_one_stream")):
         bp = fft3d.BatchPlan(shapes, mode=mode)
         with torch.cuda.stream(side):
             ms = _time(lambda: bp.forward(xs, outs), reps, torch)
         brep[name] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
-                      "hbm_frac": round(3 * 2 * 8 * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                      "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bp.close()
     bp = fft3d.BatchPlan(shapes)
     with torch.cuda.stream(side):

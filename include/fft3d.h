@@ -141,15 +141,24 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
  *     z stage reads it back into `out`, so z-lines are read with the row
  *     stride of y-lines instead of the plane stride; forward, inverse and
  *     backward all run x, y, z (the same transform up to rounding order).
+ *   FFT3D_STAGING_FUSED_XY: one kernel loads each z-plane (Nx x Ny) into LDS
+ *     and runs its x and y FFTs there, then the z stage works in place on
+ *     `out`: two passes over memory instead of three, no workspace (the slab
+ *     form of Sec. III-A: two local transforms, then the third).  Only for
+ *     the planes with a compiled kernel that fit in 160 KiB of LDS (complex64:
+ *     squares 8, 16, 24, 32, 48, 64, 96, 128 and 100 x 120, 80 x 160;
+ *     complex128: the squares up to 96) and p1 == 1 (else
+ *     FFT3D_ERR_UNSUPPORTED_SIZE).  Inverse stages run z, then planes.
  * Default: SWAP_YZ for C2C plans of at least 512 MiB with Ny, Nz > 1 (the
  * workspace is allocated by fft3d_plan; if that fails the plan stages in
- * place), IN_PLACE otherwise.  Switching frees or allocates the owned
+ * place), else FUSED_XY where available, else IN_PLACE.  Switching frees or allocates the owned
  * workspace (fft3d_set_workspace can then supply a caller buffer) and waits
  * for the device.  R2C plans accept only FFT3D_STAGING_IN_PLACE (else
  * FFT3D_ERR_WRONG_PLAN).
  */
 #define FFT3D_STAGING_IN_PLACE 0
 #define FFT3D_STAGING_SWAP_YZ 1
+#define FFT3D_STAGING_FUSED_XY 2
 fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
 
 /*
@@ -228,6 +237,13 @@ fft3d_status fft3d_batch_inverse(fft3d_batch_t plan, const void* const* in, void
 fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
                                           int lw, int tdiv, int split, int pad);
 
+/* Staging of the transforms of one shape: FFT3D_STAGING_IN_PLACE or
+ * FFT3D_STAGING_FUSED_XY (UNSUPPORTED_SIZE where no fused kernel fits that
+ * plane); a workspace staging is FFT3D_ERR_INVALID_ARG, since transforms of
+ * one shape share their plan across streams.  Drops the captured graphs;
+ * results agree to rounding, not bit for bit, between stagings. */
+fft3d_status fft3d_batch_set_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int staging);
+
 /* 0: graph replay on non-default streams (default); 1: direct launches on the
  * internal streams; 2: all transforms one after another on the caller's
  * stream (for comparison). */
@@ -269,7 +285,8 @@ fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out);
  *     axis 0..2; n the line length; conj 1 for the sign +1 transform; weight 1
  *     for the adjoint bin weighting; src/dst 0 = in, 1 = out, 2 = workspace;
  *     scale the output factor as the bit pattern of an IEEE double; lay_src,
- *     lay_dst the element order read / written (0 natural, 1 y and z swapped)
+ *     lay_dst the element order read / written (0 natural, 1 y and z swapped);
+ *     kind 4 is the fused x-y plane stage (x and y FFTs of whole planes)
  *   per task:  [stage, x0, x1, y0, y1, z0, z1, stream, ndeps, deps..., nwaits, waits...]
  * Boxes are half-open ranges over the complex array.  Returns the number of
  * int64 values needed; writes them only if cap is large enough.  Negative on

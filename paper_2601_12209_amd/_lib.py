@@ -35,6 +35,7 @@ _SIGS = {
     "fft3d_batch_forward": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
     "fft3d_batch_inverse": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
     "fft3d_batch_set_stage_config": (I32, [P, I64, I64, I64, I32, I32, I32, I32, I32]),
+    "fft3d_batch_set_staging": (I32, [P, I64, I64, I64, I32]),
     "fft3d_batch_set_mode": (I32, [P, I32]),
     "fft3d_batch_destroy": (I32, [P]),
     "fft3d_query_batch_placement": (I64, [I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I64), I64]),

@@ -233,7 +233,9 @@ fft3d_status fft3d_plan_batch(fft3d_batch_t* out, int count, const int64_t* dims
         fft3d_status st = fft3d_plan(&p, d.nx, d.ny, d.nz, dtype, 1, 1, 0);
         if (st == FFT3D_OK) st = fft3d_set_streams(p, 1);
         // transforms of one shape share the plan across streams: no workspace
-        if (st == FFT3D_OK) st = fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE);
+        // (fused x-y planes where the plane fits in LDS, else in place)
+        if (st == FFT3D_OK && fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) != FFT3D_OK)
+            st = fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE);
         if (st != FFT3D_OK) {
             if (p) fft3d_destroy(p);
             release(b);
@@ -286,6 +288,18 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
     if (b->used) hipStreamSynchronize(b->last_stream);
     drop_graphs(b);  // launch shapes are baked into the captured graphs
     return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
+}
+
+fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int staging)
+{
+    if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    auto it = b->plans.find(Shape(nx, ny, nz));
+    if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
+    if (staging != FFT3D_STAGING_IN_PLACE && staging != FFT3D_STAGING_FUSED_XY)
+        return set_error(FFT3D_ERR_INVALID_ARG, "a batch stages in place or in fused x-y planes (no workspace)");
+    if (b->used) hipStreamSynchronize(b->last_stream);
+    drop_graphs(b);  // the stage lists are baked into the captured graphs
+    return fft3d_set_staging(it->second, staging);
 }
 
 fft3d_status fft3d_batch_set_mode(fft3d_batch_t b, int mode)

@@ -60,6 +60,22 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op)
     const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
     const double inv_n = 1.0 / ((double)d.nx * (double)d.ny * (double)d.nz);
     std::vector<Stage> s;
+    if (!d.r2c && d.staging == STAGING_FUSED_XY) {
+        switch (op) {
+        case OP_FORWARD:  // the planes (x and y), then z in place
+            s.push_back(mk(K_C2C_XY, 0, nx, 0, 0, 1.0, BUF_IN, BUF_OUT));
+            s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_OUT, BUF_OUT));
+            break;
+        case OP_INVERSE:  // mirrored: z, then the planes
+        case OP_BACKWARD:
+            s.push_back(mk(K_C2C, 2, nz, 1, 0, 1.0, BUF_IN, BUF_OUT));
+            s.push_back(mk(K_C2C_XY, 0, nx, 1, 0, op == OP_INVERSE ? inv_n : 1.0, BUF_OUT, BUF_OUT));
+            break;
+        default:
+            break;
+        }
+        return s;
+    }
     if (!d.r2c && d.staging == STAGING_SWAP_YZ) {
         // x, y, z in both directions; the y stage writes the workspace in
         // SWAP_YZ order, the z stage reads it back into the output

@@ -28,8 +28,10 @@ enum Layout : int { LAY_NATURAL = 0, LAY_SWAP_YZ = 1 };
 // works in place on the output (no workspace).  SWAP_YZ: the y stage writes a
 // workspace in SWAP_YZ order and the z stage reads it back into the output,
 // so no stage reads z-lines at the natural order's plane stride; the inverse
-// then also runs x, y, z.
-enum Staging : int { STAGING_IN_PLACE = 0, STAGING_SWAP_YZ = 1 };
+// then also runs x, y, z.  FUSED_XY (small planes, p1 == 1): one kernel does
+// the x and y FFTs of whole planes in LDS, then the z stage works in place:
+// two passes; the inverse runs z, then the planes.
+enum Staging : int { STAGING_IN_PLACE = 0, STAGING_SWAP_YZ = 1, STAGING_FUSED_XY = 2 };
 
 struct PlanDesc {
     int64_t nx, ny, nz;

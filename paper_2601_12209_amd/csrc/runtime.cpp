@@ -14,6 +14,7 @@
 #include "fft_lengths.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "plane_list.hpp"
 #include "stage_args.hpp"
 
 using namespace fft3d;
@@ -119,6 +120,7 @@ int kernel_length(const Stage& st)
 // Threads and LDS bytes a configuration needs, or false if it cannot run.
 bool conf_fits(const Stage& st, int dtype, const KConf& c, bool strided)
 {
+    if (st.kind == K_C2C_XY) return true;  // fixed launch shape
     const int nk = kernel_length(st);
     const RadixPlan rp = radix_plan(nk);
     if (c.lw < 1 || c.tdiv < 1 || rp.tpl % c.tdiv != 0) return false;
@@ -217,6 +219,7 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.out = bufs[st.dst];
     a.tw = p->tw[st.axis];
     a.twp = p->twp[st.axis];
+    a.twp2 = p->twp[1];
     a.conj = st.conj;
     a.weight = st.weight;
     a.scale = st.scale;
@@ -245,6 +248,17 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
         a.off_o = b.lo[0] * so[0] + b.lo[1] * so[1] + b.lo[2] * so[2];
         a.sa_o = so[ax_a]; a.sb_o = so[ax_b]; a.se_o = so[st.axis];
         a.strided = st.axis != 0 ? 1 : 0;
+    }
+    if (st.kind == K_C2C_XY) {
+        // whole planes: rows of nx values (pitch sa), planes sb apart, B planes
+        a.A = 1;
+        a.B = b.hi[2] - b.lo[2];
+        int64_t si[3], so[3];
+        layout_strides(d, st.src, st.lay_src, si);
+        layout_strides(d, st.dst, st.lay_dst, so);
+        a.sa = si[1]; a.sb = si[2]; a.sa_o = so[1]; a.sb_o = so[2];
+        a.strided = 0;
+        return a;
     }
     if (st.kind == K_POISSON_Z) {
         a.pnx = d.nx; a.pny = d.ny; a.pnz = d.nz;
@@ -277,6 +291,7 @@ hipError_t launch_task(const fft3d_plan_s* p, const Stage& st, const StageArgs& 
     case K_R2C_X: return launch_r2c_x(st.n, p->d.dtype, a, s);
     case K_C2R_X: return launch_c2r_x(st.n, p->d.dtype, a, s);
     case K_POISSON_Z: return launch_poisson_z(st.n, p->d.dtype, a, s);
+    case K_C2C_XY: return launch_c2c_xy((int)p->d.nx, (int)p->d.ny, p->d.dtype, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -595,6 +610,10 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
             (void)hipGetLastError();
         }
     }
+    // small planes: the fused x-y kernel (two passes instead of three)
+    if (!r2c && p->d.staging == STAGING_IN_PLACE && p1 == 1 && ny > 1 &&
+        plane_available(nx, ny, elem_bytes(dtype)))
+        p->d.staging = STAGING_FUSED_XY;
     p->streams.assign(kMaxStreams, nullptr);
     if (forks(p)) {
         e = ensure_streams(p, p->nstreams);
@@ -731,10 +750,12 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
 fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ)
-        return fail(FFT3D_ERR_INVALID_ARG, "staging must be 0 (in place) or 1 (swap y/z)");
+    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ && staging != STAGING_FUSED_XY)
+        return fail(FFT3D_ERR_INVALID_ARG, "staging must be 0 (in place), 1 (swap y/z) or 2 (fused x-y planes)");
     if (p->d.r2c) return staging == STAGING_IN_PLACE ? FFT3D_OK
-                                                     : fail(FFT3D_ERR_WRONG_PLAN, "swap-y/z staging is for C2C plans");
+                                                     : fail(FFT3D_ERR_WRONG_PLAN, "this staging is for C2C plans");
+    if (staging == STAGING_FUSED_XY && (p->d.p1 != 1 || !plane_available(p->d.nx, p->d.ny, elem_bytes(p->d.dtype))))
+        return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "no fused x-y kernel for this plane (or p1 > 1)");
     if (staging == p->d.staging) return FFT3D_OK;
     drop_graphs(p);
     // enqueued work may still use the old workspace (hipFree waits for the device)
@@ -898,8 +919,9 @@ int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2,
     PlanDesc d;
     d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = DT_F32; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
     if (validate_desc(d) != FFT3D_OK) return -1;
-    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ) return -1;
+    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ && staging != STAGING_FUSED_XY) return -1;
     if (r2c && staging != STAGING_IN_PLACE) return -1;
+    if (staging == STAGING_FUSED_XY && (p1 != 1 || !plane_listed(nx, ny))) return -1;
     d.staging = staging;
     if (op < 0 || op >= OP_COUNT || nstreams < 1 || nstreams > kMaxStreams) return -1;
     const Pipeline pl = build_pipeline(d, op, nstreams);

@@ -10,6 +10,7 @@ enum KernelKind : int {
     K_R2C_X = 1,      // real x-lines -> half-spectrum x-lines
     K_C2R_X = 2,      // half-spectrum x-lines -> real x-lines
     K_POISSON_Z = 3,  // z-lines: forward FFT, spectral multiplier, inverse FFT
+    K_C2C_XY = 4,     // whole x-y planes in LDS: x FFTs then y FFTs (small planes)
 };
 
 enum DType : int { DT_F32 = 0, DT_F64 = 1 };
@@ -25,6 +26,7 @@ struct StageArgs {
     void* out;
     const void* tw;   // forward roots W_n^m = exp(-2 pi i m/n), m < n, n = axis length
     const void* twp;  // per-pass twiddle table of the kernel's FFT length
+    const void* twp2; // K_C2C_XY: per-pass table of the y length (twp: the x length)
     int64_t A, B;
     int64_t off, sa, sb, se;
     int64_t off_o, sa_o, sb_o, se_o;

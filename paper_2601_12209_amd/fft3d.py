@@ -43,6 +43,7 @@ def _stream_handle(stream=None) -> int:
 
 STAGING_IN_PLACE = 0
 STAGING_SWAP_YZ = 1
+STAGING_FUSED_XY = 2
 
 
 class Plan:
@@ -149,8 +150,9 @@ class Plan:
         check(_lib.lib().fft3d_set_graphs(self._h, int(bool(enable))), "fft3d_set_graphs")
 
     def set_staging(self, staging: int):
-        """STAGING_IN_PLACE (no workspace) or STAGING_SWAP_YZ (C2C: y stage writes a
-        y/z-swapped workspace that the z stage reads back)."""
+        """STAGING_IN_PLACE (no workspace), STAGING_SWAP_YZ (C2C: y stage writes a
+        y/z-swapped workspace that the z stage reads back) or STAGING_FUSED_XY
+        (C2C small planes: x and y FFTs of whole planes in LDS, then z)."""
         check(_lib.lib().fft3d_set_staging(self._h, int(staging)), "fft3d_set_staging")
         self._ws = None
 
@@ -215,6 +217,11 @@ class BatchPlan:
         nz, ny, nx = shape
         check(_lib.lib().fft3d_batch_set_stage_config(self._h, nx, ny, nz, int(axis), int(lw), int(tdiv),
                                                       int(split), int(pad)), "fft3d_batch_set_stage_config")
+
+    def set_staging(self, shape, staging: int):
+        """STAGING_IN_PLACE or STAGING_FUSED_XY for the transforms of one (nz, ny, nx) shape."""
+        nz, ny, nx = shape
+        check(_lib.lib().fft3d_batch_set_staging(self._h, nx, ny, nz, int(staging)), "fft3d_batch_set_staging")
 
     def _run(self, fn, xs, outs, stream):
         dt = _COMPLEX[self.code]

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/fft3d.h"
+#include "../../paper_2601_12209_amd/csrc/plane_list.hpp"
 
 extern "C" int hostsim_violations();
 extern "C" long hostsim_launches();
@@ -73,7 +74,8 @@ void c2c_cases(hipStream_t user)
                           {1, 1, 1, 1, 1},      {8, 4, 1, 1, 1},      {16, 1, 3, 1, 1},      {100, 48, 64, 3, 3},
                           {24, 30, 25, 4, 5},   {100, 120, 128, 4, 4}, {160, 160, 80, 2, 2}, {48, 48, 48, 1, 1},
                           {512, 64, 64, 1, 1},  {16, 8, 512, 1, 1},   {8, 1024, 16, 2, 2},   {2, 2, 4096, 1, 1},
-                          {4096, 2, 2, 1, 1},   {32, 32, 32, 1, 1}};
+                          {4096, 2, 2, 1, 1},   {32, 32, 32, 1, 1},   {64, 64, 40, 1, 4},    {100, 120, 12, 1, 2},
+                          {80, 160, 8, 1, 1},   {128, 128, 16, 1, 1}, {24, 24, 7, 1, 1}};
     for (const Case& c : cases) {
         for (int dtype : {FFT3D_C64, FFT3D_C128}) {
             const size_t bytes = (size_t)c.nx * c.ny * c.nz * es_of(dtype);
@@ -114,7 +116,20 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
-            EXPECT(fft3d_set_staging(p, 2) == FFT3D_ERR_INVALID_ARG);
+            EXPECT(fft3d_set_staging(p, 3) == FFT3D_ERR_INVALID_ARG);
+            // fused x-y planes where a kernel exists (and p1 == 1)
+            const bool planes = c.p1 == 1 && c.ny > 1 && fft3d::plane_available(c.nx, c.ny, es_of(dtype));
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) ==
+                   (planes ? FFT3D_OK : FFT3D_ERR_UNSUPPORTED_SIZE));
+            if (planes) {
+                EXPECT(fft3d_workspace_bytes(p) == 0);
+                for (int ns : {1, 3}) {
+                    EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                    EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
+                }
+            }
             EXPECT(fft3d_destroy(p) == FFT3D_OK);
         }
     }
@@ -288,6 +303,18 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         }
         EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_stage_config(b, 3, 3, 3, 0, 1, 1, 0, 0) == FFT3D_ERR_INVALID_ARG);
+        // staging per shape: in place always, fused planes where a kernel fits
+        for (int f = 0; f < n; ++f) {
+            const int64_t *d = &dims[3 * f];
+            const bool planes = d[1] > 1 && fft3d::plane_available(d[0], d[1], es_of(dtype));
+            EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_FUSED_XY) ==
+                   (planes ? FFT3D_OK : FFT3D_ERR_UNSUPPORTED_SIZE));
+            EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
+            EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_INVALID_ARG);
+        }
+        EXPECT(fft3d_batch_inverse(b, out.data(), out.data(), user) == FFT3D_OK);
+        EXPECT(fft3d_batch_set_staging(b, 3, 3, 3, FFT3D_STAGING_IN_PLACE) == FFT3D_ERR_INVALID_ARG);
         EXPECT(fft3d_batch_set_mode(b, 3) == FFT3D_ERR_INVALID_ARG);
         // the caller captures the batch into its own graph
         for (int mode : {0, 1}) {

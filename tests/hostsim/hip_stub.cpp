@@ -26,6 +26,7 @@
 
 #include "../../paper_2601_12209_amd/csrc/fft_lengths.hpp"
 #include "../../paper_2601_12209_amd/csrc/kernels.hpp"
+#include "../../paper_2601_12209_amd/csrc/plane_list.hpp"
 #include "../../paper_2601_12209_amd/csrc/stage_args.hpp"
 
 namespace {
@@ -469,6 +470,21 @@ static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hi
 hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(true, n, dtype, a, s); }
 
 hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(false, n, dtype, a, s); }
+
+hipError_t launch_c2c_xy(int nx, int ny, int dtype, const StageArgs& a, hipStream_t s)
+{
+    const size_t es = dtype == DT_F64 ? 16 : 8;
+    if (!plane_available(nx, ny, es)) return hipErrorInvalidValue;
+    if (a.B == 0) return hipSuccess;
+    if (plane_threads(nx, ny) > kMaxThreads || plane_threads(nx, ny) % 64) violation("plane kernel threads");
+    // plane b: rows of nx values sa apart, planes sb apart
+    check_range(a.in, es, a.off, ny, a.sa, a.B, a.sb, nx, 1, "plane load");
+    check_range(a.out, es, a.off_o, ny, a.sa_o, a.B, a.sb_o, nx, 1, "plane store");
+    if (a.twp) check_tables(a, nx, es, "plane x pass table");
+    const size_t sy = table_entries(ny);
+    if (sy) in_alloc(a.twp2, sy * es, "plane y pass table");
+    return launched(s);
+}
 
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
 {

@@ -268,3 +268,43 @@ def test_graph_replay_of_forked_pipelines(gpu_lib, dtype):
         assert torch.equal(out, ref_f), rep
     del g
     plan.close()
+
+
+FUSED_CASES = [((40, 64, 64), (1, 4)), ((12, 120, 100), (1, 2)), ((8, 160, 80), (1, 1)), ((16, 128, 128), (1, 1)),
+               ((7, 24, 24), (1, 1)), ((5, 8, 8), (1, 1)), ((3, 48, 48), (1, 3)), ((20, 96, 96), (1, 1))]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid", FUSED_CASES, ids=[f"{s}-{g}" for s, g in FUSED_CASES])
+def test_fused_xy_planes(gpu_lib, shape, grid, dtype):
+    """Whole x-y planes in LDS (x then y FFTs), then z: forward bitwise equal to the
+    in-place staging (same line arithmetic), inverse and backward against the oracle."""
+    from paper_2601_12209_amd._lib import Fft3dError
+
+    print(f"case fused planes shape={shape} grid={grid} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 51)
+    x = to_dev(a, dtype)
+    ref_in = promoted(a, dtype)
+    tol = bound(dtype, a.size)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=2)
+    if shape[1:] in ((128, 128), (120, 100), (160, 80)) and dtype == torch.complex128:  # plane > LDS
+        with pytest.raises(Fft3dError):
+            plan.set_staging(gpu_lib.STAGING_FUSED_XY)
+        return
+    plan.set_staging(gpu_lib.STAGING_FUSED_XY)
+    assert plan.workspace_bytes() == 0
+    base = gpu_lib.Plan(shape, dtype, grid, streams=2, staging=gpu_lib.STAGING_IN_PLACE)
+    X = plan.forward(x)
+    want = base.forward(x)
+    xi = plan.inverse(x)
+    xb = plan.backward(x)
+    y = x.clone()
+    plan.forward(y, out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(X, want)
+    assert torch.equal(y, want)
+    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
+    assert rel(to_host(xi), oracle.ifftn(ref_in)) <= tol
+    assert rel(to_host(xb), oracle.bfftn(ref_in)) <= tol
+    plan.close()
+    base.close()

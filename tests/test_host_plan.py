@@ -191,6 +191,11 @@ def _apply_stage(st, box, bufs, shape):
             return oracle.dft1d(full, +1).real
 
         dst[z0:z1, y0:y1, :] = np.apply_along_axis(c2r, 2, rows) * scale
+    elif kind == 4:  # whole x-y planes: x FFTs, then y FFTs
+        sub = src[z0:z1, y0:y1, x0:x1]
+        res = np.apply_along_axis(lambda v: oracle.dft1d(v, sign), 2, sub)
+        res = np.apply_along_axis(lambda v: oracle.dft1d(v, sign), 1, res) * scale
+        dst[z0:z1, y0:y1, x0:x1] = res
     elif kind == 3:  # Poisson z stage
         sub = src[z0:z1, y0:y1, x0:x1]
         kz = _wavenumber(np.arange(nz), nz)[:, None, None]
@@ -250,6 +255,24 @@ def test_simulated_c2c(fft3d, shape, grid, ns, staging):
         for op, want in ((0, oracle.fftn(a)), (1, oracle.ifftn(a)), (2, oracle.bfftn(a))):
             got = _simulate(fft3d, shape, grid, op, ns, a, rng, staging)
             assert oracle.rel_l2(got, want) < 1e-14, op
+
+
+FUSED_CASES = [((6, 8, 8), (1, 2), 2), ((5, 16, 16), (1, 1), 1), ((12, 24, 24), (1, 3), 4)]
+
+
+@pytest.mark.parametrize("shape,grid,ns", FUSED_CASES)
+def test_simulated_fused_xy(fft3d, shape, grid, ns):
+    rng = np.random.default_rng(5)
+    a = synth.complex_normal(shape, 2)
+    for op, want in ((0, oracle.fftn(a)), (1, oracle.ifftn(a)), (2, oracle.bfftn(a))):
+        stages, _ = fft3d.query_pipeline(shape, grid, op=op, nstreams=ns, staging=2)
+        assert [st["kind"] for st in stages] == ([4, 0] if op == 0 else [0, 4])
+        got = _simulate(fft3d, shape, grid, op, ns, a, rng, 2)
+        assert oracle.rel_l2(got, want) < 1e-14, op
+    with pytest.raises(ValueError):  # planes need p1 == 1
+        fft3d.query_pipeline(shape, (2, 1), staging=2)
+    with pytest.raises(ValueError):  # no kernel for a 6 x 8 plane
+        fft3d.query_pipeline((4, 8, 6), (1, 1), staging=2)
 
 
 def test_swap_yz_staging_layouts(fft3d):
