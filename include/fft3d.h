@@ -153,8 +153,13 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
  * workspace is allocated by fft3d_plan; if that fails the plan stages in
  * place), else FUSED_XY where available, else IN_PLACE.  Switching frees or allocates the owned
  * workspace (fft3d_set_workspace can then supply a caller buffer) and waits
- * for the device.  R2C plans accept only FFT3D_STAGING_IN_PLACE (else
- * FFT3D_ERR_WRONG_PLAN).
+ * for the device.  R2C plans always hold their workspace and accept
+ * IN_PLACE (the x and y stages of the forward run in the workspace, z writes
+ * `out`) and SWAP_YZ (forward only: x writes `out`, y writes the workspace
+ * with y and z swapped, z reads it back into `out`; bitwise the same result);
+ * their inverse, backward and Poisson stages do not change.  Default for R2C:
+ * SWAP_YZ when the half spectrum takes at least 512 MiB, else IN_PLACE.
+ * FUSED_XY on an R2C plan -> FFT3D_ERR_WRONG_PLAN.
  */
 #define FFT3D_STAGING_IN_PLACE 0
 #define FFT3D_STAGING_SWAP_YZ 1

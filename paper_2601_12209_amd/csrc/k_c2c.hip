@@ -37,14 +37,21 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     if (a.strided) {
         const int lw = t % a.lw;
         tj = t / a.lw;
+        int64_t bx = blockIdx.x, by = blockIdx.y;
+        if (a.xcd) {  // host guarantees gridDim.x * gridDim.y % 8 == 0
+            const int64_t lin = bx + by * gridDim.x, per = (int64_t)gridDim.x * gridDim.y / 8;
+            const int64_t tile = (lin % 8) * per + lin / 8;
+            bx = tile % gridDim.x;
+            by = tile / gridDim.x;
+        }
         // with a.align, the tiles of this row start `shift` lines early so that
         // every output segment covers whole cache lines
-        const int64_t shift = a.align > 1 ? (a.off_o + (int64_t)blockIdx.y * a.sb_o) % a.align : 0;
-        const int64_t aa0 = (int64_t)blockIdx.x * a.lw + lw - shift;
+        const int64_t shift = a.align > 1 ? (a.off_o + by * a.sb_o) % a.align : 0;
+        const int64_t aa0 = bx * a.lw + lw - shift;
         ok = aa0 >= 0 && aa0 < a.A;
         const int64_t aa = aa0 < 0 ? 0 : (aa0 < a.A ? aa0 : a.A - 1);
-        base = a.off + aa + (int64_t)blockIdx.y * a.sb;
-        base_o = a.off_o + aa + (int64_t)blockIdx.y * a.sb_o;
+        base = a.off + aa + by * a.sb;
+        base_o = a.off_o + aa + by * a.sb_o;
         L = LdsView<cpx<T>>{lds + lw, a.lw, 0};
         Ls = LdsView<T>{ldsr + lw, a.lw, 0};
     } else {
@@ -95,6 +102,8 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
     if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
     StageArgs arg = a;
+    // the XCD-grouped tile order needs whole groups of 8 workgroups
+    if (!a.strided || ((uint64_t)grid.x * grid.y) % 8 != 0) arg.xcd = 0;
     void* args[] = {&arg};
     return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT>), grid, dim3(threads),
                            args, lds, s);

@@ -18,13 +18,23 @@
 
 namespace fft3d {
 
-// LDS bytes of a real-kernel launch: lw lines of H + 1 values and the pass
-// table of the length-H FFT.
+// LDS slots of one line: H + 1 values, plus one slot per eight with `pad`
+// (element e at e + (e / 8) * pad; without it the first pass's outputs, R
+// consecutive values per thread, put the lanes of a line R slots apart, all
+// on the same banks for R = 16).
+template <int N>
+__host__ __device__ constexpr int real_line_slots(int pad)
+{
+    return N / 2 + 1 + (pad ? N / 16 : 0);
+}
+
+// LDS bytes of a real-kernel launch: lw lines and the pass table of the
+// length-H FFT.
 template <typename T, int N>
-constexpr size_t real_lds_bytes(int lw)
+constexpr size_t real_lds_bytes(int lw, int pad)
 {
     constexpr int H = N / 2;
-    return align16((size_t)lw * (H + 1) * sizeof(cpx<T>)) + pass_table_bytes<T, H>();
+    return align16((size_t)lw * real_line_slots<N>(pad) * sizeof(cpx<T>)) + pass_table_bytes<T, H>();
 }
 
 template <typename T, int N>
@@ -45,9 +55,10 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
     // W_N^k for the split step: a few KiB read by every workgroup, served by the caches
     const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
-    LdsView<cpx<T>> L{lds + lw * H, 1, 0};
+    const int slots = real_line_slots<N>(a.pad);
+    LdsView<cpx<T>> L{lds + lw * slots, 1, a.pad};
     LdsView<T> Ls{nullptr, 0, 0};
-    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * H * sizeof(cpx<T>)));
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * slots * sizeof(cpx<T>)));
     stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     auto load = [&](int e) -> cpx<T> { return in[e]; };
     auto store_lds = [&](int e, cpx<T> v) { L[e] = v; };
@@ -89,9 +100,10 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + aa * a.sa_o + bb * a.sb_o;
     // W_N^k for the merge step: a few KiB read by every workgroup, served by the caches
     const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.tw);
-    LdsView<cpx<T>> L{lds + lw * (H + 1), 1, 0};
+    const int slots = real_line_slots<N>(a.pad);
+    LdsView<cpx<T>> L{lds + lw * slots, 1, a.pad};
     LdsView<T> Ls{nullptr, 0, 0};
-    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * (H + 1) * sizeof(cpx<T>)));
+    cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * slots * sizeof(cpx<T>)));
     stage_pass_twiddles<T, H>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const T wgt = a.weight ? (T)0.5 : (T)1;
     // every load first (bins tj + i*TPL, and bin H on thread 0), then the LDS writes
@@ -135,9 +147,10 @@ static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
         constexpr int H = N / 2;
         constexpr int TPL = radix_plan(H).tpl;
         const int threads = a.lw * TPL;
-        const size_t lds = real_lds_bytes<T, N>(a.lw);
+        const size_t lds = real_lds_bytes<T, N>(a.lw, a.pad);
         const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
         if (grid.x == 0) return hipSuccess;
+        if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
         if (r2c) {
             StageArgs arg = a;
             void* args[] = {&arg};

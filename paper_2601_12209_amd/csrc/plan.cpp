@@ -107,6 +107,17 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op)
         }
         return s;
     }
+    if (d.staging == STAGING_SWAP_YZ && op == OP_FORWARD) {
+        // x writes the output, y moves it into the workspace with y and z
+        // swapped, z reads the workspace rows back into the output: no stage
+        // reads lines at the plane stride
+        s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_OUT));
+        s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_OUT, BUF_WS));
+        s.back().lay_dst = LAY_SWAP_YZ;
+        s.push_back(mk(K_C2C, 2, nz, 0, 0, 1.0, BUF_WS, BUF_OUT));
+        s.back().lay_src = LAY_SWAP_YZ;
+        return s;
+    }
     switch (op) {
     case OP_FORWARD:
         // x and y in the workspace (rows on cache-line bounds), z writes the output

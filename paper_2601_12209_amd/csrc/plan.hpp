@@ -38,7 +38,7 @@ struct PlanDesc {
     int dtype;  // DT_F32 / DT_F64
     int p1, p2;
     int r2c;
-    int staging = STAGING_IN_PLACE;  // C2C plans only
+    int staging = STAGING_IN_PLACE;  // R2C: IN_PLACE or SWAP_YZ (forward only)
     int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent
     // row pitch (complex elements) of the workspace: the complex x extent
     // rounded up to 128 bytes, so workspace rows start on cache-line bounds

@@ -33,6 +33,9 @@ struct StageArgs {
     int strided;  // 1: lanes of a wavefront walk neighbouring lines (requires sa == sa_o == 1)
     int align;    // strided: > 1 shifts each row's line tiles so that output row segments
                   // start on multiples of `align` elements (a cache line); lw % align == 0
+    int xcd;      // strided: 1 gives each of the 8 XCDs a contiguous run of tiles
+                  // (workgroups go to XCDs round-robin by linear id), so tiles that
+                  // share cache lines meet in one L2
     int lw;       // lines per workgroup
     int tdiv;     // threads per line = (default threads per line) / tdiv
     int split;    // 1: exchange real and imaginary parts through LDS separately

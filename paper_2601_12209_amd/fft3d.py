@@ -150,11 +150,13 @@ class Plan:
         check(_lib.lib().fft3d_set_graphs(self._h, int(bool(enable))), "fft3d_set_graphs")
 
     def set_staging(self, staging: int):
-        """STAGING_IN_PLACE (no workspace), STAGING_SWAP_YZ (C2C: y stage writes a
-        y/z-swapped workspace that the z stage reads back) or STAGING_FUSED_XY
-        (C2C small planes: x and y FFTs of whole planes in LDS, then z)."""
+        """STAGING_IN_PLACE (C2C: no workspace), STAGING_SWAP_YZ (y stage writes a
+        y/z-swapped workspace that the z stage reads back; R2C: forward only) or
+        STAGING_FUSED_XY (C2C small planes: x and y FFTs of whole planes in LDS,
+        then z)."""
         check(_lib.lib().fft3d_set_staging(self._h, int(staging)), "fft3d_set_staging")
-        self._ws = None
+        if not self.r2c:  # a C2C switch replaces the workspace; R2C plans keep theirs
+            self._ws = None
 
     def set_stage_config(self, axis: int, lw: int, tdiv: int = 1, split: int = 0, pad: int = 0):
         """Launch shape of the stage kernels along one axis (lw = 0: default)."""

@@ -209,7 +209,14 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_poisson_adjoint(p, r2.p, r.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
-            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
+            for (int ns : {1, 3}) {
+                EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, h.p, r2.p, user) == FFT3D_OK);
+                EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+            }
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             // caller workspace, then back to a plan-owned one
             const size_t wsb = fft3d_workspace_bytes(p);

@@ -284,8 +284,25 @@ def test_swap_yz_staging_layouts(fft3d):
         assert [(st["lay_src"], st["lay_dst"]) for st in stages] == [(0, 0), (0, 1), (1, 0)]
         assert [st["conj"] for st in stages] == [int(op != 0)] * 3
         assert stages[2]["scale"] == (1.0 / (8 * 6 * 4) if op == 1 else 1.0)
-    with pytest.raises(ValueError):  # R2C plans stage in place only
-        fft3d.query_pipeline((8, 6, 4), (1, 1), r2c=True, staging=1)
+    # R2C: only the forward changes (x writes the output, y the swapped workspace)
+    stages, _ = fft3d.query_pipeline((8, 6, 4), (2, 2), r2c=True, op=0, nstreams=2, staging=1)
+    assert [st["kind"] for st in stages] == [1, 0, 0]
+    assert [(st["src"], st["dst"]) for st in stages] == [(0, 1), (1, 2), (2, 1)]
+    assert [(st["lay_src"], st["lay_dst"]) for st in stages] == [(0, 0), (0, 1), (1, 0)]
+    for op in (1, 2, 3, 4):
+        assert (fft3d.query_pipeline((8, 6, 4), (2, 2), r2c=True, op=op, nstreams=2, staging=1)[0]
+                == fft3d.query_pipeline((8, 6, 4), (2, 2), r2c=True, op=op, nstreams=2, staging=0)[0])
+    with pytest.raises(ValueError):  # fused planes are C2C only
+        fft3d.query_pipeline((8, 8, 8), (1, 1), r2c=True, staging=2)
+
+
+@pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
+def test_simulated_r2c_swap_yz(fft3d, shape, grid, ns):
+    rng = np.random.default_rng(2)
+    f = synth.real_normal(shape, 5)
+    for _ in range(3):
+        got = _simulate(fft3d, shape, grid, 0, ns, f, rng, staging=1)
+        assert oracle.rel_l2(got, oracle.rfftn(f)) < 1e-14
 
 
 @pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
