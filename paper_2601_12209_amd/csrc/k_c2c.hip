@@ -12,14 +12,33 @@
 //
 // Variants: TDIV divides the threads per line (more butterflies per thread, so
 // more lines per workgroup and longer row segments); SPLIT halves the LDS tile
-// by exchanging real and imaginary parts one after the other.
+// by exchanging real and imaginary parts one after the other; NT marks the
+// global stores (NT >= 1) and loads (NT == 2) non-temporal, so the streamed
+// tile does not displace reusable lines from the caches (every element is read
+// and written once per stage).
 #include "device_fft.hpp"
 #include "kernels.hpp"
 #include "stage_args.hpp"
 
 namespace fft3d {
 
-template <typename T, int N, int TDIV, bool SPLIT>
+template <typename T>
+__device__ __forceinline__ void store_nt(cpx<T>* p, cpx<T> v)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> load_nt(const cpx<T>* p)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return cpx<T>{w.x, w.y};
+}
+
+template <typename T, int N, int TDIV, bool SPLIT, int NT>
 __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
 {
     constexpr int TPL = radix_plan(N).tpl / TDIV;
@@ -78,17 +97,22 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     const bool cj = a.conj != 0;
     const T scale = (T)a.scale;
     auto load = [&](int e) -> cpx<T> {
-        const cpx<T> v = in[(e - tj) * se];
+        cpx<T> v;
+        if constexpr (NT == 2) v = load_nt(&in[(e - tj) * se]);
+        else v = in[(e - tj) * se];
         return cj ? conj(v) : v;
     };
     auto store = [&](int e, cpx<T> v) {
         if (cj) v = conj(v);
-        if (ok) out[(e - tj) * se_o] = v * scale;
+        if (ok) {
+            if constexpr (NT >= 1) store_nt(&out[(e - tj) * se_o], v * scale);
+            else out[(e - tj) * se_o] = v * scale;
+        }
     };
     fft_line<T, N, TPL, SPLIT>(L, Ls, tj, twl, load, store);
 }
 
-template <typename T, int N, int TDIV, bool SPLIT>
+template <typename T, int N, int TDIV, bool SPLIT, int NT = 0>
 static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
 {
     constexpr int TPL = radix_plan(N).tpl / TDIV;
@@ -105,7 +129,7 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     // the XCD-grouped tile order needs whole groups of 8 workgroups
     if (!a.strided || ((uint64_t)grid.x * grid.y) % 8 != 0) arg.xcd = 0;
     void* args[] = {&arg};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT>), grid, dim3(threads),
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT, NT>), grid, dim3(threads),
                            args, lds, s);
 }
 
@@ -122,6 +146,13 @@ template <typename T, int N>
 static hipError_t launch_c2c_n(const StageArgs& a, hipStream_t s)
 {
     const int tdiv = a.tdiv < 1 ? 1 : a.tdiv;
+    if constexpr (has_variants<N>()) {
+        // non-temporal variants: one thread per butterfly only
+        if (tdiv == 1 && a.nt == 1)
+            return a.split ? launch_c2c_v<T, N, 1, true, 1>(a, s) : launch_c2c_v<T, N, 1, false, 1>(a, s);
+        if (tdiv == 1 && a.nt == 2)
+            return a.split ? launch_c2c_v<T, N, 1, true, 2>(a, s) : launch_c2c_v<T, N, 1, false, 2>(a, s);
+    }
     if (tdiv == 1 && !a.split) return launch_c2c_v<T, N, 1, false>(a, s);
     if constexpr (has_variants<N>()) {
         constexpr int tpl = radix_plan(N).tpl;

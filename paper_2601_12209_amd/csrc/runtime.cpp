@@ -211,6 +211,32 @@ void layout_strides(const PlanDesc& d, int buf, int lay, int64_t st[3])
     }
 }
 
+// Cache policy of a C2C launch (StageArgs::nt), from measurements at 512^3 on
+// MI355X.  Non-temporal stores: complex128 C2C stages 2-3 % faster, in-place
+// R2C y stages 11-19 %; complex64 stages writing another buffer along y or z
+// ran 1-2 % slower with them and keep plain stores.  Non-temporal loads as
+// well where the tile reads whole cache lines of another buffer (complex128
+// stages a further 1-3 %, the complex64 x stage 3-4 %); where neighbouring
+// tiles share lines (misaligned rows) or the stage works in place, plain
+// loads (non-temporal ones there measured 4-25 % slower).  Fields that fit
+// the 256 MB Infinity Cache next to their workspace keep plain accesses, so
+// one stage's output stays cached for the next.
+int c2c_cache_policy(const PlanDesc& d, const Stage& st, const StageArgs& a, int64_t per_line)
+{
+    if (st.kind != K_C2C) return 0;
+    if ((size_t)d.nxc() * d.ny * d.nz * elem_bytes(d.dtype) < kSwapStagingMinBytes) return 0;
+    const bool in_place = st.src == st.dst;
+    if (d.dtype == DT_F32 && a.strided && !in_place) return 0;
+    bool whole_lines;
+    if (a.strided)  // row segments of lw lines at off + b*sb + e*se
+        whole_lines = a.align <= 1 && a.lw % per_line == 0 && a.A % per_line == 0 && a.off % per_line == 0 &&
+                      a.sb % per_line == 0 && a.se % per_line == 0;
+    else  // lanes along each line: lines of st.n contiguous values at off + a*sa + b*sb
+        whole_lines = a.se == 1 && st.n % per_line == 0 && a.off % per_line == 0 && a.sa % per_line == 0 &&
+                      a.sb % per_line == 0;
+    return !in_place && whole_lines ? 2 : 1;
+}
+
 StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* const bufs[3])
 {
     const PlanDesc& d = p->d;
@@ -287,6 +313,7 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     // stage at 512^3 on MI355X (C2C and R2C); complex64 stages ran 3-5 % slower
     // with it, so they keep the plain order
     if (a.strided && d.dtype == DT_F64) a.xcd = 1;
+    a.nt = c2c_cache_policy(d, st, a, per_line);
     return a;
 }
 

@@ -36,6 +36,9 @@ struct StageArgs {
     int xcd;      // strided: 1 gives each of the 8 XCDs a contiguous run of tiles
                   // (workgroups go to XCDs round-robin by linear id), so tiles that
                   // share cache lines meet in one L2
+    int nt;       // cache policy of the tile's global accesses: 0 plain, 1 non-temporal
+                  // stores, 2 non-temporal loads and stores (C2C kernels of the lengths
+                  // with launch-shape variants, one thread per butterfly; ignored elsewhere)
     int lw;       // lines per workgroup
     int tdiv;     // threads per line = (default threads per line) / tdiv
     int split;    // 1: exchange real and imaginary parts through LDS separately
