@@ -45,6 +45,21 @@ template <typename T> FD cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
 template <typename T> FD cpx<T> mul_i(cpx<T> a) { return {-a.im, a.re}; }     // i * a
 template <typename T> FD cpx<T> mul_negi(cpx<T> a) { return {a.im, -a.re}; }  // -i * a
 
+// Global accesses marked non-temporal (streamed data that should not displace
+// reusable lines from the caches); one 8- or 16-byte access per value.
+template <typename T> FD void store_nt(cpx<T>* p, cpx<T> v)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+template <typename T> FD cpx<T> load_nt(const cpx<T>* p)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return cpx<T>{w.x, w.y};
+}
+
 // cos/sin constants of the small DFTs, in long double so each precision gets
 // its correctly rounded value.
 #define K_SQRT1_2 0.707106781186547524400844362104849039L

@@ -22,22 +22,6 @@
 
 namespace fft3d {
 
-template <typename T>
-__device__ __forceinline__ void store_nt(cpx<T>* p, cpx<T> v)
-{
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    const v2 w = {v.re, v.im};
-    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
-}
-
-template <typename T>
-__device__ __forceinline__ cpx<T> load_nt(const cpx<T>* p)
-{
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-    return cpx<T>{w.x, w.y};
-}
-
 template <typename T, int N, int TDIV, bool SPLIT, int NT>
 __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
 {
