@@ -455,7 +455,7 @@ static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hi
     const int h = n / 2;
     const size_t es = dtype == DT_F64 ? 16 : 8;
     const int threads = a.lw * radix_plan(h).tpl;
-    const size_t lds = align16((size_t)a.lw * (h + 1) * es) + table_entries(h) * es;
+    const size_t lds = align16((size_t)a.lw * (h + 1 + (a.pad ? h / 8 : 0)) * es) + table_entries(h) * es;
     if ((a.A * a.B + a.lw - 1) / a.lw == 0) return hipSuccess;
     if (threads > kMaxThreads || lds > kMaxLdsBytes) violation("real kernel shape over the limits");
     // complex-pair side has h values per line, half-spectrum side h + 1
