@@ -300,6 +300,23 @@ fft3d_status fft3d_query_twiddles(int64_t n, int dtype, void* out);
 int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2, int r2c, int staging, int op,
                              int nstreams, int64_t* out, int64_t cap);
 
+/*
+ * Default launch configuration of every task of the same task graph (plan
+ * precision dtype, one stream, no stage overrides), in task order, as int64
+ * records after a header [ntasks]:
+ *   [lw, tdiv, split, pad, strided, align, xcd, nt]
+ * lw lines per workgroup; tdiv threads-per-line divisor; split re/im LDS
+ * exchange; pad padded contiguous LDS lines; strided 1 when the lanes of a
+ * wavefront walk neighbouring lines; align > 1: row tiles shifted so stored
+ * segments start on multiples of align elements; xcd 1: XCD-grouped tile
+ * order; nt cache policy (0 plain, 1 non-temporal stores, 2 non-temporal
+ * loads and stores).  Host-side only (no device work).  Returns the number of
+ * int64 values needed, writes them only if cap is large enough, negative on
+ * invalid arguments.
+ */
+int64_t fft3d_query_launches(int64_t nx, int64_t ny, int64_t nz, int dtype, int p1, int p2, int r2c, int staging,
+                             int op, int64_t* out, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,6 +45,7 @@ _SIGS = {
     "fft3d_query_radix_plan": (I32, [I64, ctypes.POINTER(I32), I32]),
     "fft3d_query_twiddles": (I32, [I64, I32, P]),
     "fft3d_query_pipeline": (I64, [I64, I64, I64, I32, I32, I32, I32, I32, I32, ctypes.POINTER(I64), I64]),
+    "fft3d_query_launches": (I64, [I64, I64, I64, I32, I32, I32, I32, I32, I32, ctypes.POINTER(I64), I64]),
 }
 
 

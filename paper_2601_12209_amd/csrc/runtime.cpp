@@ -994,4 +994,31 @@ int64_t fft3d_query_pipeline(int64_t nx, int64_t ny, int64_t nz, int p1, int p2,
     return (int64_t)v.size();
 }
 
+int64_t fft3d_query_launches(int64_t nx, int64_t ny, int64_t nz, int dtype, int p1, int p2, int r2c, int staging,
+                             int op, int64_t* out, int64_t cap)
+{
+    PlanDesc d;
+    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = dtype; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
+    if (validate_desc(d) != FFT3D_OK) return -1;
+    if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ && staging != STAGING_FUSED_XY) return -1;
+    if (r2c && staging == STAGING_FUSED_XY) return -1;
+    if (staging == STAGING_FUSED_XY && (p1 != 1 || !plane_listed(nx, ny))) return -1;
+    if (op < 0 || op >= OP_COUNT) return -1;
+    d.staging = staging;
+    // the launch shapes depend only on the plan description (no device state)
+    fft3d_plan_s tmp;
+    tmp.d = d;
+    const Pipeline pl = build_pipeline(d, op, 1);
+    void* const bufs[3] = {nullptr, nullptr, nullptr};
+    std::vector<int64_t> v;
+    v.push_back((int64_t)pl.tasks.size());
+    for (const Task& t : pl.tasks) {
+        const StageArgs a = make_args(&tmp, pl.stages[t.stage], t.box, bufs);
+        const int64_t rec[8] = {a.lw, a.tdiv, a.split, a.pad, a.strided, a.align, a.xcd, a.nt};
+        v.insert(v.end(), rec, rec + 8);
+    }
+    if (out && cap >= (int64_t)v.size()) memcpy(out, v.data(), v.size() * sizeof(int64_t));
+    return (int64_t)v.size();
+}
+
 }  // extern "C"

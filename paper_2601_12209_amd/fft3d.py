@@ -369,6 +369,25 @@ def query_twiddles(n: int, dtype) -> np.ndarray:
     return out
 
 
+LAUNCH_FIELDS = ("lw", "tdiv", "split", "pad", "strided", "align", "xcd", "nt")
+
+
+def query_launches(shape, dtype, grid=(1, 1), r2c=False, op=0, staging=0):
+    """Default launch configuration of every task (task order of a one-stream
+    plan): dicts with the keys of LAUNCH_FIELDS.  dtype: the plan precision."""
+    nz, ny, nx = shape
+    L = _lib.lib()
+    args = (nx, ny, nz, _dtype_code(dtype), grid[0], grid[1], int(r2c), int(staging), int(op))
+    need = L.fft3d_query_launches(*args, None, 0)
+    if need < 0:
+        raise ValueError("invalid launch query arguments")
+    buf = (ctypes.c_int64 * need)()
+    L.fft3d_query_launches(*args, buf, need)
+    v = list(buf)
+    k = len(LAUNCH_FIELDS)
+    return [dict(zip(LAUNCH_FIELDS, v[1 + i * k:1 + (i + 1) * k])) for i in range(v[0])]
+
+
 def query_pipeline(shape, grid, r2c=False, op=0, nstreams=4, staging=0):
     """Decoded task graph: (stages, tasks) with boxes over the complex (x, y, z) index space."""
     nz, ny, nx = shape

@@ -359,3 +359,74 @@ def test_batch_placement_least_loaded(fft3d):
     assert max(loads) - min(loads) <= max(cost) + 1e-6
     for p in per:  # within a stream, larger transforms first
         assert [cost[i] for i in p] == sorted((cost[i] for i in p), reverse=True)
+
+
+# ------------------------------------------------------------------ launch configuration
+
+def _by_stage(fft3d, shape, dtype, r2c=False, op=0, staging=0, grid=(1, 1)):
+    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=1, staging=staging)
+    launches = fft3d.query_launches(shape, dtype, grid, r2c=r2c, op=op, staging=staging)
+    assert len(launches) == len(tasks)
+    return [(stages[t["stage"]], L) for t, L in zip(tasks, launches)]
+
+
+def test_cache_policy_large_c2c(fft3d):
+    """512^3 swapped staging: complex128 stages stream with non-temporal loads and
+    stores (whole cache lines of another buffer) and XCD-grouped strided tiles;
+    complex64 x stages the same, complex64 y/z stages plain accesses, plain order."""
+    for dtype in ("c64", "c128"):
+        for op in (0, 1):
+            got = _by_stage(fft3d, (512, 512, 512), dtype, op=op, staging=1)
+            assert [st["axis"] for st, _ in got] == [0, 1, 2]
+            for st, L in got:
+                assert L["strided"] == int(st["axis"] != 0)
+                assert L["xcd"] == int(dtype == "c128" and st["axis"] != 0)
+                assert L["align"] <= 1
+                want = 0 if (dtype == "c64" and st["axis"] != 0) else 2
+                assert L["nt"] == want, (dtype, op, st, L)
+    # the complex64 strided stages take 32 lines, two threads per line fewer, full LDS tile
+    _, L = _by_stage(fft3d, (512, 512, 512), "c64", staging=1)[1]
+    assert (L["lw"], L["tdiv"], L["split"]) == (32, 2, 0)
+
+
+def test_cache_policy_in_place_and_cache_resident(fft3d):
+    # in place at 512^3 (complex128): non-temporal stores only (the line just read is rewritten)
+    for st, L in _by_stage(fft3d, (512, 512, 512), "c128", staging=0)[1:]:
+        assert st["src"] == st["dst"] and L["nt"] == 1
+    # fields that fit the Infinity Cache keep plain accesses
+    for dtype in ("c64", "c128"):
+        for staging in (0, 1):
+            assert all(L["nt"] == 0 for _, L in _by_stage(fft3d, (256, 256, 256), dtype, staging=staging))
+
+
+def test_r2c_launches(fft3d):
+    """512^3 R2C: padded LDS lines in the real x kernels; output rows of 257 values
+    get shifted (cache-line aligned) tiles; non-temporal loads only where whole
+    lines of another buffer are read."""
+    for dtype in ("f32", "f64"):
+        fwd = _by_stage(fft3d, (512, 512, 512), dtype, r2c=True, op=0, staging=1)
+        (x, Lx), (y, Ly), (z, Lz) = fwd
+        assert x["kind"] == 1 and Lx["pad"] == 1 and Lx["nt"] == 0 and Lx["strided"] == 0
+        per_line = 16 if dtype == "f32" else 8
+        assert Lz["align"] == per_line and Ly["align"] <= 1  # z writes the 257-value rows of the output
+        if dtype == "f32":
+            assert Ly["nt"] == 0 and Lz["nt"] == 0
+        else:  # rows of 257 values are read misaligned: stores only
+            assert Ly["nt"] == 1 and Lz["nt"] == 1 and Ly["xcd"] == 1 and Lz["xcd"] == 1
+        inv = _by_stage(fft3d, (512, 512, 512), dtype, r2c=True, op=1)
+        (z, Lz), (y, Ly), (x, Lx) = inv
+        assert x["kind"] == 2 and Lx["pad"] == 1 and Lx["nt"] == 0
+        assert y["src"] == y["dst"] == 2 and Ly["nt"] == 1  # in place in the workspace
+        assert Lz["nt"] == (0 if dtype == "f32" else 1)
+    # small R2C plans: plain accesses, padded real kernels
+    for st, L in _by_stage(fft3d, (32, 32, 32), "f32", r2c=True, op=3):
+        assert L["nt"] == 0
+        if st["kind"] in (1, 2):
+            assert L["pad"] == 1
+
+
+def test_launch_query_rejects_bad_arguments(fft3d):
+    with pytest.raises(ValueError):
+        fft3d.query_launches((8, 8, 8), "c64", r2c=True, staging=2)
+    with pytest.raises(ValueError):
+        fft3d.query_launches((8, 8, 11), "c64")
