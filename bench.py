@@ -171,7 +171,9 @@ def _extras(reps, torch, fft3d, synth, np):
             name = f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}"
             rep[name] = {
                 "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                # plans with >= 16 tiles replay their task graph (one hipGraph node per tile)
+                "issue": "task graph" if grid[0] * grid[1] >= 16 else "direct"}
             if grid != (1, 1):
                 torch.cuda.synchronize()
                 checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),

@@ -175,12 +175,18 @@ fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
 /*
- * Graph replay of forked pipelines: capture the whole task graph of a call
- * that forks onto the plan's streams (fork, every tile launch, the event
- * edges, join) into a hipGraph once per operation and buffer set, and replay
- * it.  Currently switched off: enable = 1 returns FFT3D_ERR_INVALID_ARG and
- * every call is issued directly (a caller capturing its stream still records
- * the launches into its own graph).  enable = 0 is accepted.
+ * Graph replay of tiled pipelines (Sec. IV's task graph as one launch).  With
+ * enable = 1, a call of a plan with more than one tile per stage builds, once
+ * per operation and (in, out, workspace) triple, a hipGraph with one kernel
+ * node per tile whose dependencies are exactly the tile's producers, and
+ * launches it on the caller's stream (the plan's streams and events are not
+ * used; at most 8 graphs are cached, the oldest set is dropped when full).
+ * Results are bitwise identical to direct issue.  A call on a stream the
+ * caller is capturing is issued directly (into the caller's graph).  Cached
+ * graphs are dropped (after the device finishes them) by every setter that
+ * changes launches.  Default: 1 for plans with at least 16 tiles per stage
+ * (p1 * p2 >= 16), where the graph measured 10-22 % faster than direct issue
+ * on MI355X; 0 below (fewer, larger tiles issue faster directly).
  */
 fft3d_status fft3d_set_graphs(fft3d_plan_t plan, int enable);
 

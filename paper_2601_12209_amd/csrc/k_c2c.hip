@@ -112,9 +112,8 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     StageArgs arg = a;
     // the XCD-grouped tile order needs whole groups of 8 workgroups
     if (!a.strided || ((uint64_t)grid.x * grid.y) % 8 != 0) arg.xcd = 0;
-    void* args[] = {&arg};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT, NT>), grid, dim3(threads),
-                           args, lds, s);
+    return launch_stage_kernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT, NT>), grid, dim3(threads),
+                               arg, lds, s);
 }
 
 // Lengths that also get the TDIV = 2, 4 and SPLIT variants.  (A TDIV 3

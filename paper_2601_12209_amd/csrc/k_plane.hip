@@ -97,10 +97,8 @@ static hipError_t launch_plane(const StageArgs& a, hipStream_t s)
     } else {
         if (a.B == 0) return hipSuccess;
         constexpr int NT = plane_threads(NX, NY);
-        StageArgs arg = a;
-        void* args[] = {&arg};
-        return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2c_xy<T, NX, NY, NT>), dim3((unsigned)a.B),
-                               dim3(NT), args, lds, s);
+        return launch_stage_kernel(reinterpret_cast<const void*>(&k_c2c_xy<T, NX, NY, NT>), dim3((unsigned)a.B),
+                                   dim3(NT), a, lds, s);
     }
 }
 

@@ -74,10 +74,8 @@ static hipError_t launch_poisson_n(const StageArgs& a, hipStream_t s)
     const size_t lds = align16((size_t)a.lw * N * sizeof(cpx<T>)) + pass_table_bytes<T, N>();
     const dim3 grid((unsigned)((a.A + a.lw - 1) / a.lw), (unsigned)a.B, 1);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    StageArgs arg = a;
-    void* args[] = {&arg};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_poisson_z<T, N>), grid, dim3(threads), args, lds,
-                           s);
+    return launch_stage_kernel(reinterpret_cast<const void*>(&k_poisson_z<T, N>), grid, dim3(threads), a, lds,
+                               s);
 }
 
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)

@@ -151,17 +151,9 @@ static hipError_t launch_real_n(bool r2c, const StageArgs& a, hipStream_t s)
         const dim3 grid((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
         if (grid.x == 0) return hipSuccess;
         if (threads > 1024 || lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
-        if (r2c) {
-            StageArgs arg = a;
-            void* args[] = {&arg};
-            return hipLaunchKernel(reinterpret_cast<const void*>(&k_r2c_x<T, N>), grid, dim3(threads), args,
-                                   lds, s);
-        } else {
-            StageArgs arg = a;
-            void* args[] = {&arg};
-            return hipLaunchKernel(reinterpret_cast<const void*>(&k_c2r_x<T, N>), grid, dim3(threads), args,
-                                   lds, s);
-        }
+        const void* f = r2c ? reinterpret_cast<const void*>(&k_r2c_x<T, N>)
+                            : reinterpret_cast<const void*>(&k_c2r_x<T, N>);
+        return launch_stage_kernel(f, grid, dim3(threads), a, lds, s);
     }
 }
 

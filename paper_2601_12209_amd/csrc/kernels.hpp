@@ -24,4 +24,22 @@ hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
 // planes a.sb / a.sb_o apart.
 hipError_t launch_c2c_xy(int nx, int ny, int dtype, const StageArgs& a, hipStream_t s);
 
+// One stage-kernel launch as data: what a hipGraph kernel node needs (every
+// stage kernel takes a single StageArgs by value).
+struct KernelLaunch {
+    const void* func = nullptr;
+    dim3 grid;
+    dim3 block;
+    size_t lds = 0;
+    StageArgs args{};
+};
+
+// Every launcher above ends in launch_stage_kernel: it launches on `s`, or,
+// while a recorder is installed on the calling host thread, writes the launch
+// into it (and sets *recorded) instead.  Launchers that have nothing to do
+// (an empty grid) return hipSuccess without calling it.
+void set_launch_recorder(KernelLaunch* rec, bool* recorded);
+hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const StageArgs& a, size_t lds,
+                               hipStream_t s);
+
 }  // namespace fft3d

@@ -40,6 +40,12 @@ fft3d_status hip_fail(hipError_t e, const char* what)
 
 constexpr int kMaxStreams = 16;
 constexpr size_t kMaxGraphs = 8;  // cached pipeline graphs per plan
+// Plans with at least this many tiles per stage replay their task graphs by
+// default.  Measured on MI355X, fwd+inv complex64: 256^3 on 4x4 tiles 0.83 ms
+// direct on 4 streams (0.71 on one) -> 0.65 ms as a graph, 8x8 2.14 -> 1.86,
+// 512^3 on 4x4 3.35 -> 2.99; with 2x2 tiles one stream is faster (256^3
+// 0.34 ms against 0.37 as a graph, 32^3 0.08 against 0.24).
+constexpr int64_t kGraphMinTiles = 16;
 // C2C plans of at least this many bytes, and R2C plans whose half spectrum is
 // at least this large, default to the swapped-y/z staging (measured on MI355X:
 // faster at 512^3, slower at 256^3, whose 128-256 MiB field stays in the
@@ -49,6 +55,34 @@ constexpr size_t kSwapStagingMinBytes = (size_t)512 << 20;
 }  // namespace
 
 namespace fft3d {
+namespace {
+thread_local KernelLaunch* t_recorder = nullptr;
+thread_local bool* t_recorded = nullptr;
+}  // namespace
+
+void set_launch_recorder(KernelLaunch* rec, bool* recorded)
+{
+    t_recorder = rec;
+    t_recorded = recorded;
+}
+
+hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const StageArgs& a, size_t lds,
+                               hipStream_t s)
+{
+    if (t_recorder) {
+        t_recorder->func = func;
+        t_recorder->grid = grid;
+        t_recorder->block = block;
+        t_recorder->lds = lds;
+        t_recorder->args = a;
+        *t_recorded = true;
+        return hipSuccess;
+    }
+    StageArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchKernel(func, grid, block, args, lds, s);
+}
+
 // error reporting shared with the batch entry points (batch.cpp)
 fft3d_status set_error(fft3d_status st, const std::string& msg) { return fail(st, msg); }
 fft3d_status set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
@@ -92,9 +126,9 @@ struct fft3d_plan_s {
         void* ws;
         hipGraphExec_t exec;
     };
-    bool use_graphs = false;  // replay is switched off (see fft3d_set_graphs)
+    bool use_graphs = false;  // multi-tile calls replay an explicit task graph (fft3d_set_graphs)
     std::vector<CachedGraph> graphs;
-    hipStream_t graph_stream = nullptr;  // stream of the last graph launch
+    hipEvent_t graph_done = nullptr;  // recorded after every graph launch
     // per-stage timing (tracing): events around every stage of the last call
     bool timing = false;
     std::vector<hipEvent_t> tev;  // 6 timing events (up to 5 stages)
@@ -439,15 +473,63 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
 void drop_graphs(fft3d_plan_s* p)
 {
     if (p->graphs.empty()) return;
-    hipStreamSynchronize(p->graph_stream);
+    // the caller's stream may be gone by now; the plan's own event is not
+    if (p->graph_done) hipEventSynchronize(p->graph_done);
     for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
     p->graphs.clear();
 }
 
 fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user);
 
-// Replay (capturing on first use) the forked pipeline of this operation and
-// these buffers on a non-default stream that is not being captured.
+// The task graph of one operation on these buffers as a hipGraph built node
+// by node: one kernel node per tile, whose dependencies are exactly the
+// tile's producers (the overlap edges of the pipeline; no streams, events or
+// stream capture are involved).  A tile with nothing to launch becomes an
+// empty node so that its consumers still follow its producers.
+fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraphExec_t* out)
+{
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    std::vector<hipGraphNode_t> node(pl.tasks.size(), nullptr);
+    for (size_t i = 0; i < pl.tasks.size() && e == hipSuccess; ++i) {
+        const Task& t = pl.tasks[i];
+        const Stage& st = pl.stages[t.stage];
+        std::vector<hipGraphNode_t> deps;
+        for (int d : t.deps) deps.push_back(node[d]);
+        KernelLaunch kl;
+        bool recorded = false;
+        set_launch_recorder(&kl, &recorded);
+        e = launch_task(p, st, make_args(p, st, t.box, bufs), nullptr);
+        set_launch_recorder(nullptr, nullptr);
+        if (e != hipSuccess) break;
+        if (recorded) {
+            void* kargs[] = {&kl.args};
+            hipKernelNodeParams kp;
+            memset(&kp, 0, sizeof kp);
+            kp.func = const_cast<void*>(kl.func);
+            kp.gridDim = kl.grid;
+            kp.blockDim = kl.block;
+            kp.sharedMemBytes = (unsigned)kl.lds;
+            kp.kernelParams = kargs;
+            kp.extra = nullptr;
+            e = hipGraphAddKernelNode(&node[i], g, deps.data(), deps.size(), &kp);
+        } else {
+            e = hipGraphAddEmptyNode(&node[i], g, deps.data(), deps.size());
+        }
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return hip_fail(e, "building the pipeline graph");
+    }
+    return FFT3D_OK;
+}
+
+// Replay (building on first use) the task graph of this operation and these
+// buffers on the caller's stream.
 fft3d_status run_graph(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user)
 {
     fft3d_plan_s::CachedGraph* hit = nullptr;
@@ -455,25 +537,20 @@ fft3d_status run_graph(fft3d_plan_s* p, int op, const Pipeline& pl, void* const 
         if (g.op == op && g.in == bufs[0] && g.out == bufs[1] && g.ws == bufs[2]) hit = &g;
     if (!hit) {
         if (p->graphs.size() >= kMaxGraphs) drop_graphs(p);
-        hipError_t e = hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        fft3d_status st = issue_forked(p, op, pl, bufs, user);
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(user, &graph);
-        if (st != FFT3D_OK) {
-            if (graph) hipGraphDestroy(graph);
-            return st;
-        }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
         hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        fft3d_status st = build_graph(p, pl, bufs, &exec);
+        if (st != FFT3D_OK) return st;
         p->graphs.push_back({op, bufs[0], bufs[1], bufs[2], exec});
         hit = &p->graphs.back();
     }
-    p->graph_stream = user;
-    hipError_t e = hipGraphLaunch(hit->exec, user);
+    hipError_t e = hipSuccess;
+    if (!p->graph_done) e = hipEventCreateWithFlags(&p->graph_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        p->graph_done = nullptr;
+        return hip_fail(e, "hipEventCreate");
+    }
+    e = hipGraphLaunch(hit->exec, user);
+    if (e == hipSuccess) e = hipEventRecord(p->graph_done, user);
     return e == hipSuccess ? FFT3D_OK : hip_fail(e, "hipGraphLaunch");
 }
 
@@ -486,6 +563,15 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (p->timing) return run_timed(p, pl, bufs, user);
+    if (p->use_graphs && (int64_t)p->d.p1 * p->d.p2 > 1) {
+        // a stream the caller is capturing takes the launches into the caller's graph
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (user) {
+            e = hipStreamIsCapturing(user, &cap);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+        }
+        if (cap == hipStreamCaptureStatusNone) return run_graph(p, op, pl, bufs, user);
+    }
     if (!forks(p)) {
         for (const Task& t : pl.tasks) {
             const Stage& st = pl.stages[t.stage];
@@ -493,14 +579,6 @@ fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* strea
             if (e != hipSuccess) return hip_fail(e, "kernel launch");
         }
         return FFT3D_OK;
-    }
-    if (p->use_graphs && user != nullptr) {
-        // the legacy default stream cannot be captured; a stream the caller is
-        // capturing takes the launches into the caller's graph
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        e = hipStreamIsCapturing(user, &cap);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
-        if (cap == hipStreamCaptureStatusNone) return run_graph(p, op, pl, bufs, user);
     }
     return issue_forked(p, op, pl, bufs, user);
 }
@@ -556,6 +634,7 @@ void release(fft3d_plan_s* p)
     for (hipEvent_t ev : p->tev)
         if (ev) hipEventDestroy(ev);
     if (p->fork) hipEventDestroy(p->fork);
+    if (p->graph_done) hipEventDestroy(p->graph_done);
     for (void* t : p->tw)
         if (t) hipFree(t);
     for (void* t : p->twp)
@@ -651,6 +730,7 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
     if (!r2c && p->d.staging == STAGING_IN_PLACE && p1 == 1 && ny > 1 &&
         plane_available(nx, ny, elem_bytes(dtype)))
         p->d.staging = STAGING_FUSED_XY;
+    p->use_graphs = (int64_t)p1 * p2 >= kGraphMinTiles;
     p->streams.assign(kMaxStreams, nullptr);
     if (forks(p)) {
         e = ensure_streams(p, p->nstreams);
@@ -826,10 +906,8 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
 fft3d_status fft3d_set_graphs(fft3d_plan_t p, int enable)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    if (enable)  // the first replay test of this path ended in a host segfault on MI355X, cause not found
-        return fail(FFT3D_ERR_INVALID_ARG, "graph replay of forked pipelines is switched off");
     drop_graphs(p);
-    p->use_graphs = false;
+    p->use_graphs = enable != 0;
     return FFT3D_OK;
 }
 

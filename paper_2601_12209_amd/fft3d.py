@@ -146,7 +146,9 @@ class Plan:
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
 
     def set_graphs(self, enable: bool):
-        """Replay forked pipelines from captured hipGraphs on non-default streams (default on)."""
+        """Replay tiled pipelines as explicit task graphs (one kernel node per tile,
+        edges = producer tiles), cached per operation and buffer set (default on
+        for plans with at least 16 tiles per stage)."""
         check(_lib.lib().fft3d_set_graphs(self._h, int(bool(enable))), "fft3d_set_graphs")
 
     def set_staging(self, staging: int):

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -89,8 +90,26 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
                 EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
             }
-            // graph replay of forked pipelines is switched off
-            EXPECT(fft3d_set_graphs(p, 1) == FFT3D_ERR_INVALID_ARG);
+            // task-graph replay: built per (operation, buffers), cached, replayed,
+            // dropped by the setters; more buffer sets than cache slots
+            EXPECT(fft3d_set_graphs(p, 1) == FFT3D_OK);
+            for (int rep = 0; rep < 2; ++rep) {
+                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, out.p, out.p, nullptr) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, out.p, in.p, user) == FFT3D_OK);
+            }
+            {
+                std::vector<std::unique_ptr<Buf>> extra;
+                for (int k = 0; k < 10; ++k) {
+                    extra.emplace_back(new Buf(bytes));
+                    EXPECT(fft3d_forward(p, in.p, extra.back()->p, user) == FFT3D_OK);
+                }
+                EXPECT(fft3d_set_streams(p, 3) == FFT3D_OK);  // drops the cached graphs first
+            }
+            EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+            (void)fft3d_set_stage_config(p, 1, 4, 1, 0, 0);  // where the shape fits
+            EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+            EXPECT(fft3d_set_stage_config(p, 1, 0, 1, 0, 0) == FFT3D_OK);
             EXPECT(fft3d_set_graphs(p, 0) == FFT3D_OK);
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
             if (bytes >= 2 * es_of(dtype))  // partial overlap

@@ -68,8 +68,17 @@ struct ihipEvent_t {
     int capture = 0;
 };
 
+struct hipGraphNode {
+    ihipGraph* owner = nullptr;
+};
+
 struct ihipGraph {
     unsigned magic = kGraphMagic;
+    std::vector<hipGraphNode*> nodes;  // built node by node (hipGraphAdd*Node)
+    ~ihipGraph()
+    {
+        for (hipGraphNode* n : nodes) delete n;
+    }
 };
 
 struct hipGraphExec {
@@ -325,6 +334,63 @@ hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g)
     return r;
 }
 
+hipError_t hipGraphCreate(hipGraph_t* g, unsigned int flags)
+{
+    if (!g || flags != 0) return hipErrorInvalidValue;
+    *g = new ihipGraph();
+    return hipSuccess;
+}
+
+namespace {
+hipError_t add_node(hipGraphNode_t* n, hipGraph_t g, const hipGraphNode_t* deps, size_t nd, const char* what)
+{
+    if (!n || !g || g->magic != kGraphMagic) {
+        violation("%s on an invalid graph", what);
+        return hipErrorInvalidValue;
+    }
+    for (size_t i = 0; i < nd; ++i) {
+        if (!deps || !deps[i] || deps[i]->owner != g) {
+            violation("%s with a dependency outside the graph", what);
+            return hipErrorInvalidValue;
+        }
+    }
+    hipGraphNode* node = new hipGraphNode();
+    node->owner = g;
+    g->nodes.push_back(node);
+    *n = node;
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t hipGraphAddKernelNode(hipGraphNode_t* n, hipGraph_t g, const hipGraphNode_t* deps, size_t nd,
+                                 const hipKernelNodeParams* kp)
+{
+    // the stage kernels take one StageArgs: the node must carry it
+    if (!kp || !kp->func || !kp->kernelParams || !kp->kernelParams[0] || kp->extra) {
+        violation("kernel node without a function or its StageArgs argument");
+        return hipErrorInvalidValue;
+    }
+    const unsigned threads = kp->blockDim.x * kp->blockDim.y * kp->blockDim.z;
+    if (threads == 0 || threads > 1024 || kp->sharedMemBytes > fft3d::kMaxLdsBytes)
+        violation("kernel node shape over the limits");
+    ++g_launches;
+    return add_node(n, g, deps, nd, "hipGraphAddKernelNode");
+}
+
+hipError_t hipGraphAddEmptyNode(hipGraphNode_t* n, hipGraph_t g, const hipGraphNode_t* deps, size_t nd)
+{
+    return add_node(n, g, deps, nd, "hipGraphAddEmptyNode");
+}
+
+hipError_t hipLaunchKernel(const void* f, dim3, dim3, void** args, size_t, hipStream_t s)
+{
+    if (!f || !args || !args[0]) violation("kernel launch without a function or arguments");
+    if (!stream_ok(s, "kernel launch")) return hipErrorInvalidHandle;
+    enqueue(s);
+    ++g_launches;
+    return hipSuccess;
+}
+
 hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, hipGraphNode_t*, char*, size_t)
 {
     if (!g || g->magic != kGraphMagic) {
@@ -402,12 +468,12 @@ void check_tables(const StageArgs& a, int n, size_t es, const char* what)
     if (s) in_alloc(a.twp, s * es, what);
 }
 
-hipError_t launched(hipStream_t s)
+// The checked launch goes through the library's launch hook, which launches
+// (hipLaunchKernel below) or records a graph node description.
+const int g_stub_kernel = 0;
+hipError_t launched(const fft3d::StageArgs& a, hipStream_t s)
 {
-    if (!stream_ok(s, "kernel launch")) return hipErrorInvalidHandle;
-    enqueue(s);
-    ++g_launches;
-    return hipSuccess;
+    return fft3d::launch_stage_kernel(&g_stub_kernel, dim3(1), dim3(64), a, 0, s);
 }
 
 }  // namespace
@@ -446,7 +512,7 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
         check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, n, 1, "c2c store");
     }
     check_tables(a, n, es, "c2c pass table");
-    return launched(s);
+    return launched(a, s);
 }
 
 static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -464,7 +530,7 @@ static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hi
     check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, lout, 1, r2c ? "r2c store" : "c2r store");
     in_alloc(a.tw, (size_t)(h + 1) * es, "real kernel root table");
     check_tables(a, h, es, "real kernel pass table");
-    return launched(s);
+    return launched(a, s);
 }
 
 hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(true, n, dtype, a, s); }
@@ -483,7 +549,7 @@ hipError_t launch_c2c_xy(int nx, int ny, int dtype, const StageArgs& a, hipStrea
     if (a.twp) check_tables(a, nx, es, "plane x pass table");
     const size_t sy = table_entries(ny);
     if (sy) in_alloc(a.twp2, sy * es, "plane y pass table");
-    return launched(s);
+    return launched(a, s);
 }
 
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -498,7 +564,7 @@ hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson load");
     check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "poisson store");
     check_tables(a, n, es, "poisson pass table");
-    return launched(s);
+    return launched(a, s);
 }
 
 }  // namespace fft3d

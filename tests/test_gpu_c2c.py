@@ -270,6 +270,76 @@ def test_graph_replay_of_forked_pipelines(gpu_lib, dtype):
     plan.close()
 
 
+GRAPH_CASES = [((24, 30, 40), (2, 3), 0), ((32, 32, 32), (2, 2), 1), ((16, 64, 64), (1, 4), 2)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid,staging", GRAPH_CASES, ids=[f"{s}-{g}-st{t}" for s, g, t in GRAPH_CASES])
+def test_task_graph_replay(gpu_lib, shape, grid, staging, dtype):
+    """Tiled pipelines replayed as explicit task graphs (one kernel node per tile,
+    edges = producer tiles): bitwise equal to direct issue, across replays with
+    eager work in between, on the default and a side stream, for more buffer
+    sets than the cache holds, in place, and after a setter dropped the graphs."""
+    print(f"case task graph shape={shape} grid={grid} staging={staging} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 43)
+    x = to_dev(a, dtype)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=3, staging=staging)
+    ref_f = plan.forward(x)
+    ref_i = plan.inverse(x)
+    ref_b = plan.backward(x)
+    torch.cuda.synchronize()
+    plan.set_graphs(True)
+    side = torch.cuda.Stream()
+    X = torch.empty_like(x)
+    Y = torch.empty_like(x)
+    B = torch.empty_like(x)
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            plan.forward(x, out=X)
+            plan.inverse(x, out=Y)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            plan.backward(x, out=B)
+        side.synchronize()
+        assert torch.equal(X, ref_f) and torch.equal(Y, ref_i) and torch.equal(B, ref_b), rep
+        del junk
+    X.zero_()
+    plan.forward(x, out=X)  # default stream
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref_f)
+    with torch.cuda.stream(side):
+        for _ in range(10):  # more buffer sets than cached graphs, in place
+            z = x.clone()
+            plan.forward(z, out=z)
+    side.synchronize()
+    assert torch.equal(z, ref_f)
+    plan.set_streams(2)  # drops the cached graphs
+    X.zero_()
+    plan.forward(x, out=X)
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref_f)
+    assert rel(to_host(X), oracle.fftn(promoted(a, dtype))) <= bound(dtype, a.size)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_task_graph_replay_r2c(gpu_lib, dtype):
+    shape, grid = (16, 24, 32), (2, 2)
+    print(f"case task graph r2c shape={shape} grid={grid} dtype={dtype}", flush=True)
+    f = synth.real_normal(shape, 44)
+    x = to_dev(f, dtype)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=2, r2c=True)
+    ref_h = plan.forward(x)
+    ref_p = plan.poisson(x)
+    torch.cuda.synchronize()
+    plan.set_graphs(True)
+    for rep in range(3):
+        H = plan.forward(x)
+        P = plan.poisson(x)
+        torch.cuda.synchronize()
+        assert torch.equal(H, ref_h) and torch.equal(P, ref_p), rep
+    plan.close()
+
+
 FUSED_CASES = [((40, 64, 64), (1, 4)), ((12, 120, 100), (1, 2)), ((8, 160, 80), (1, 1)), ((16, 128, 128), (1, 1)),
                ((7, 24, 24), (1, 1)), ((5, 8, 8), (1, 1)), ((3, 48, 48), (1, 3)), ((20, 96, 96), (1, 1))]
 

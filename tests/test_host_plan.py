@@ -246,6 +246,51 @@ def _simulate(fft3d, shape, grid, op, ns, inp, rng, staging=0):
 SIM_CASES = [((6, 4, 8), (2, 2), 2), ((5, 6, 10), (3, 2), 4), ((8, 6, 4), (1, 3), 1), ((4, 4, 6), (2, 1), 3)]
 
 
+def _simulate_graph(fft3d, shape, grid, op, inp, rng, staging=0, r2c=False):
+    """Run the tasks in a random order that respects only each task's producer
+    list (the dependencies of the graph-replay nodes; no stream order)."""
+    stages, tasks = fft3d.query_pipeline(shape, grid, r2c=r2c, op=op, nstreams=1, staging=staging)
+    nz, ny, nx = shape
+    nxc = nx // 2 + 1
+    if not r2c:
+        out = np.full(shape, np.nan + 0j)
+        ws = np.full(shape, np.nan + 0j) if staging == 1 else None
+    else:
+        out = np.full(shape, np.nan) if op in (1, 2, 3, 4) else np.full((nz, ny, nxc), np.nan + 0j)
+        ws = np.full((nz, ny, nxc), np.nan + 0j)
+    bufs = [inp.copy(), out, ws]
+    done = [False] * len(tasks)
+    for _ in range(len(tasks)):
+        ready = [i for i, t in enumerate(tasks) if not done[i] and all(done[d] for d in t["deps"])]
+        assert ready, "deadlock"
+        i = ready[rng.integers(len(ready))]
+        _apply_stage(stages[tasks[i]["stage"]], tasks[i]["box"], bufs, shape)
+        done[i] = True
+    return bufs[1]
+
+
+@pytest.mark.parametrize("shape,grid", [((6, 4, 8), (2, 2)), ((5, 6, 10), (3, 2)), ((8, 6, 4), (1, 3)),
+                                        ((12, 8, 8), (1, 2))])
+def test_producer_edges_alone_order_every_pipeline(fft3d, shape, grid):
+    """The graph-replay nodes depend only on their producer tiles: every random
+    order those edges allow gives the exact transform, for each staging and
+    operation."""
+    rng = np.random.default_rng(7)
+    a = synth.complex_normal(shape, 3)
+    stagings = [0, 1] + ([2] if grid[0] == 1 and shape[1] == shape[2] == 8 else [])
+    for staging in stagings:
+        for _ in range(3):
+            for op, want in ((0, oracle.fftn(a)), (1, oracle.ifftn(a)), (2, oracle.bfftn(a))):
+                got = _simulate_graph(fft3d, shape, grid, op, a, rng, staging)
+                assert oracle.rel_l2(got, want) < 1e-14, (staging, op)
+    f = synth.real_normal(shape, 4)
+    for staging in (0, 1):
+        got = _simulate_graph(fft3d, shape, grid, 0, f, rng, staging, r2c=True)
+        assert oracle.rel_l2(got, oracle.rfftn(f)) < 1e-14
+    phi = _simulate_graph(fft3d, shape, grid, 3, f, rng, 0, r2c=True)
+    assert oracle.rel_l2(phi, oracle.poisson(f)) < 1e-13
+
+
 @pytest.mark.parametrize("staging", [0, 1], ids=["in_place", "swap_yz"])
 @pytest.mark.parametrize("shape,grid,ns", SIM_CASES)
 def test_simulated_c2c(fft3d, shape, grid, ns, staging):
