@@ -219,7 +219,8 @@ def _extras(reps, torch, fft3d, synth, np):
     brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
             "hbm_bytes_per_call": bbytes}
     side = torch.cuda.Stream()
-    for mode, name in ((0, "graph_4_streams"), (1, "direct_4_streams"), (2, "serial_one_stream")):
+    for mode, name in ((3, "task_graph"), (0, "graph_4_streams"), (1, "direct_4_streams"),
+                       (2, "serial_one_stream")):
         bp = fft3d.BatchPlan(shapes, mode=mode)
         with torch.cuda.stream(side):
             ms = _time(lambda: bp.forward(xs, outs), reps, torch)

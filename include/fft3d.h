@@ -255,9 +255,15 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_
  * results agree to rounding, not bit for bit, between stagings. */
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int staging);
 
-/* 0: graph replay on non-default streams (default); 1: direct launches on the
- * internal streams; 2: all transforms one after another on the caller's
- * stream (for comparison). */
+/* 0: replay of the captured fork / internal streams / join sequence (on
+ * non-default streams); 1: direct launches on the internal streams; 2: all
+ * transforms one after another on the caller's stream (for comparison);
+ * 3 (default): replay of one graph built node by node, every transform's
+ * stage kernels as a chain of nodes and no edges between transforms (on any
+ * stream the caller is not capturing; 2-3 % faster than mode 0 on the 64
+ * uneven transforms).  A stream the caller is capturing takes direct
+ * launches on the internal streams (modes 0, 1, 3).  Switching drops the
+ * cached graphs (after the device finishes them). */
 fft3d_status fft3d_batch_set_mode(fft3d_batch_t plan, int mode);
 
 fft3d_status fft3d_batch_destroy(fft3d_batch_t plan);

@@ -83,6 +83,13 @@ hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const St
     return hipLaunchKernel(func, grid, block, args, lds, s);
 }
 
+// Appends the kernel nodes of one call of `p` (operation op, in -> out, the
+// plan's workspace) to graph g: one node per tile with its producer edges;
+// the first stage's nodes depend on `after`.  *tail receives the last stage's
+// nodes.  Used by the batch to put many transforms into one graph.
+fft3d_status append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
+                               const std::vector<hipGraphNode_t>& after, std::vector<hipGraphNode_t>* tail);
+
 // error reporting shared with the batch entry points (batch.cpp)
 fft3d_status set_error(fft3d_status st, const std::string& msg) { return fail(st, msg); }
 fft3d_status set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
@@ -486,18 +493,17 @@ fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* con
 // tile's producers (the overlap edges of the pipeline; no streams, events or
 // stream capture are involved).  A tile with nothing to launch becomes an
 // empty node so that its consumers still follow its producers.
-fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraphExec_t* out)
+hipError_t add_pipeline_nodes(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraph_t g,
+                              const std::vector<hipGraphNode_t>& after, std::vector<hipGraphNode_t>* tail)
 {
-    *out = nullptr;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipGraphCreate(&g, 0);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    hipError_t e = hipSuccess;
     std::vector<hipGraphNode_t> node(pl.tasks.size(), nullptr);
     for (size_t i = 0; i < pl.tasks.size() && e == hipSuccess; ++i) {
         const Task& t = pl.tasks[i];
         const Stage& st = pl.stages[t.stage];
         std::vector<hipGraphNode_t> deps;
         for (int d : t.deps) deps.push_back(node[d]);
+        if (t.stage == 0) deps = after;
         KernelLaunch kl;
         bool recorded = false;
         set_launch_recorder(&kl, &recorded);
@@ -519,6 +525,22 @@ fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3
             e = hipGraphAddEmptyNode(&node[i], g, deps.data(), deps.size());
         }
     }
+    if (tail && e == hipSuccess) {
+        tail->clear();
+        const int last = (int)pl.stages.size() - 1;
+        for (size_t i = 0; i < pl.tasks.size(); ++i)
+            if (pl.tasks[i].stage == last) tail->push_back(node[i]);
+    }
+    return e;
+}
+
+fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraphExec_t* out)
+{
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    e = add_pipeline_nodes(p, pl, bufs, g, {}, nullptr);
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
@@ -527,6 +549,22 @@ fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3
     }
     return FFT3D_OK;
 }
+
+}  // namespace
+
+fft3d_status fft3d::append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
+                                      const std::vector<hipGraphNode_t>& after,
+                                      std::vector<hipGraphNode_t>* tail)
+{
+    if (!p || op < 0 || op >= OP_COUNT) return fail(FFT3D_ERR_INVALID_ARG, "invalid plan or operation");
+    const Pipeline& pl = get_pipeline(p, op);
+    if (pl.stages.empty()) return fail(FFT3D_ERR_WRONG_PLAN, "operation not available for this plan kind");
+    void* bufs[3] = {const_cast<void*>(in), out, p->ws};
+    hipError_t e = add_pipeline_nodes(p, pl, bufs, g, after, tail);
+    return e == hipSuccess ? FFT3D_OK : hip_fail(e, "adding pipeline nodes");
+}
+
+namespace {
 
 // Replay (building on first use) the task graph of this operation and these
 // buffers on the caller's stream.

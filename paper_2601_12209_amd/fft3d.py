@@ -202,7 +202,7 @@ class Plan:
 class BatchPlan:
     """Many 3D FFTs of different shapes issued as one task graph."""
 
-    def __init__(self, shapes, dtype=torch.complex64, mode=0):
+    def __init__(self, shapes, dtype=torch.complex64, mode=3):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.code = _dtype_code(dtype)
         dims = (ctypes.c_int64 * (3 * len(self.shapes)))()

@@ -300,7 +300,7 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         fft3d_batch_t b = nullptr;
         EXPECT(fft3d_plan_batch(&b, n, dims.data(), dtype) == FFT3D_OK);
         if (!b) continue;
-        for (int mode : {2, 1, 0}) {
+        for (int mode : {2, 1, 3, 0}) {
             EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
             for (int rep = 0; rep < 3; ++rep) {
                 EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
@@ -341,9 +341,9 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         }
         EXPECT(fft3d_batch_inverse(b, out.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_staging(b, 3, 3, 3, FFT3D_STAGING_IN_PLACE) == FFT3D_ERR_INVALID_ARG);
-        EXPECT(fft3d_batch_set_mode(b, 3) == FFT3D_ERR_INVALID_ARG);
+        EXPECT(fft3d_batch_set_mode(b, 4) == FFT3D_ERR_INVALID_ARG);
         // the caller captures the batch into its own graph
-        for (int mode : {0, 1}) {
+        for (int mode : {0, 1, 3}) {
             EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
             EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
             EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);

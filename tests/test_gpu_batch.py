@@ -52,7 +52,7 @@ def test_modes_and_graph_replays_agree(gpu_lib, workload):
     shapes, host, xs = workload
     side = torch.cuda.Stream()
     ref = None
-    for mode in (2, 1, 0):
+    for mode in (2, 1, 0, 3):
         print(f"case mode {mode}", flush=True)
         bp = gpu_lib.BatchPlan(shapes, mode=mode)
         outs = [torch.empty_like(x) for x in xs]
@@ -162,7 +162,7 @@ def test_batch_errors(gpu_lib):
     with pytest.raises(Fft3dError):
         bp.set_stage_config((4, 4, 4), 0, 1)  # no transform of that shape
     with pytest.raises(Fft3dError):
-        bp.set_mode(3)
+        bp.set_mode(4)
     with pytest.raises(ValueError):
         bp.forward([a.clone()])
     bp.close()
