@@ -191,6 +191,20 @@ fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 fft3d_status fft3d_set_graphs(fft3d_plan_t plan, int enable);
 
 /*
+ * Row pitch, in complex elements, of the half-spectrum buffers an R2C plan
+ * exchanges with the caller (the output of fft3d_forward, the input of
+ * fft3d_inverse / fft3d_backward): element (kx, y, z) at kx + pitch*(y + Ny*z),
+ * kx <= Nx/2; the buffer then holds pitch*Ny*Nz values, and the columns past
+ * Nx/2 are neither written nor read.  0 (default) is the dense layout
+ * (pitch Nx/2 + 1).  A pitch that is a multiple of 128 bytes (16 complex64,
+ * 8 complex128 values) puts every row on cache-line bounds, so the strided
+ * stages that touch the caller's buffer read and write whole lines.  Not a
+ * C2C plan (FFT3D_ERR_WRONG_PLAN); 0 < pitch < Nx/2 + 1 -> FFT3D_ERR_INVALID_ARG.
+ * Drops the plan's cached graphs.
+ */
+fft3d_status fft3d_set_half_pitch(fft3d_plan_t plan, int64_t pitch);
+
+/*
  * Override the launch shape of the stage kernels along one axis (0 = x,
  * 1 = y, 2 = z) of this plan: lw lines per workgroup (a power of two; 0
  * restores the default shape), tdiv divides the threads that cooperate on one

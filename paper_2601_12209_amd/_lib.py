@@ -28,6 +28,7 @@ _SIGS = {
     "fft3d_set_streams": (I32, [P, I32]),
     "fft3d_set_staging": (I32, [P, I32]),
     "fft3d_set_graphs": (I32, [P, I32]),
+    "fft3d_set_half_pitch": (I32, [P, I64]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
     "fft3d_set_timing": (I32, [P, I32]),
     "fft3d_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), I32]),

@@ -236,7 +236,7 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
 
 // Row pitch (complex elements) of a complex buffer: the workspace rows are
 // padded to 128 bytes, caller buffers are dense.
-int64_t row_pitch(const PlanDesc& d, int buf) { return buf == BUF_WS ? d.wpitch() : d.nxc(); }
+int64_t row_pitch(const PlanDesc& d, int buf) { return buf == BUF_WS ? d.wpitch() : d.upitch(); }
 
 // Element strides (x, y, z) of a complex buffer in a layout.
 void layout_strides(const PlanDesc& d, int buf, int lay, int64_t st[3])
@@ -817,7 +817,7 @@ static fft3d_status c2c_or_r2c(fft3d_plan_t p, int op, const void* in, void* out
             (ranges_overlap(p->ws, p->ws_bytes, in, n * s) || ranges_overlap(p->ws, p->ws_bytes, out, n * s)))
             return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
     } else {
-        const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.nxc() * d.ny * d.nz * s;
+        const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.upitch() * d.ny * d.nz * s;
         const size_t in_bytes = op == OP_FORWARD ? real_bytes : half_bytes;
         const size_t out_bytes = op == OP_FORWARD ? half_bytes : real_bytes;
         if (ranges_overlap(in, in_bytes, out, out_bytes))
@@ -938,6 +938,16 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
         p->ws_owned = true;
         p->ws_bytes = need;
     }
+    return FFT3D_OK;
+}
+
+fft3d_status fft3d_set_half_pitch(fft3d_plan_t p, int64_t pitch)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    if (!p->d.r2c) return fail(FFT3D_ERR_WRONG_PLAN, "the half-spectrum pitch is for R2C plans");
+    if (pitch != 0 && pitch < p->d.nxc()) return fail(FFT3D_ERR_INVALID_ARG, "pitch must be 0 or >= nx/2 + 1");
+    drop_graphs(p);  // their launches hold the old addressing
+    p->d.hpitch = pitch;
     return FFT3D_OK;
 }
 

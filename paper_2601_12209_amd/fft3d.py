@@ -49,7 +49,8 @@ STAGING_FUSED_XY = 2
 class Plan:
     """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind."""
 
-    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None):
+    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None,
+                 half_pitch=None):
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
         self.code = _dtype_code(dtype)
@@ -61,6 +62,9 @@ class Plan:
         self._h = h
         self.device = torch.cuda.current_device()
         self._ws = None
+        self.half_pitch = 0
+        if half_pitch is not None:
+            self.set_half_pitch(half_pitch)
         if streams is not None:
             self.set_streams(streams)
         if staging is not None:
@@ -81,8 +85,15 @@ class Plan:
 
     @property
     def half_shape(self):
+        """Shape of the half-spectrum tensors this plan exchanges: (nz, ny, nx//2 + 1),
+        or (nz, ny, half_pitch) with a padded layout (only [..., :nx//2 + 1] is used)."""
         nz, ny, nx = self.shape
-        return (nz, ny, nx // 2 + 1)
+        return (nz, ny, self.half_pitch or nx // 2 + 1)
+
+    def set_half_pitch(self, pitch: int):
+        """R2C plans: row pitch of the half-spectrum tensors (0: dense nx//2 + 1)."""
+        check(_lib.lib().fft3d_set_half_pitch(self._h, int(pitch)), "fft3d_set_half_pitch")
+        self.half_pitch = int(pitch)
 
     def _check_tensor(self, t, dtype, shape, name):
         if not isinstance(t, torch.Tensor) or not t.is_cuda:

@@ -112,6 +112,7 @@ void c2c_cases(hipStream_t user)
             EXPECT(fft3d_set_stage_config(p, 1, 0, 1, 0, 0) == FFT3D_OK);
             EXPECT(fft3d_set_graphs(p, 0) == FFT3D_OK);
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_set_half_pitch(p, 64) == FFT3D_ERR_WRONG_PLAN);
             if (bytes >= 2 * es_of(dtype))  // partial overlap
                 EXPECT(fft3d_forward(p, in.p, (char*)in.p + es_of(dtype), user) == FFT3D_ERR_ALIAS);
             // swapped-y/z staging: owned workspace, then a caller one
@@ -228,6 +229,21 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_poisson_adjoint(p, r2.p, r.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
+            // padded half-spectrum rows: buffers of pitch * ny * nz values
+            {
+                const int64_t pitch = (int64_t)padded(c.nx / 2 + 1, dtype) + 3;
+                Buf hp((size_t)pitch * c.ny * c.nz * es);
+                EXPECT(fft3d_set_half_pitch(p, c.nx / 2) == FFT3D_ERR_INVALID_ARG);
+                EXPECT(fft3d_set_half_pitch(p, pitch) == FFT3D_OK);
+                for (int stg : {FFT3D_STAGING_IN_PLACE, FFT3D_STAGING_SWAP_YZ}) {
+                    EXPECT(fft3d_set_staging(p, stg) == FFT3D_OK);
+                    EXPECT(fft3d_forward(p, r.p, hp.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_inverse(p, hp.p, r2.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_backward(p, hp.p, r2.p, nullptr) == FFT3D_OK);
+                }
+                EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
+                EXPECT(fft3d_set_half_pitch(p, 0) == FFT3D_OK);
+            }
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) == FFT3D_ERR_WRONG_PLAN);
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
             for (int ns : {1, 3}) {
