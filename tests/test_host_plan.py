@@ -371,6 +371,27 @@ def test_simulated_r2c_family(fft3d, shape, grid, ns):
     assert oracle.rel_l2(gf, oracle.poisson_grad(w)) < 1e-13
 
 
+def test_graph_simulator_catches_a_missing_edge(fft3d, monkeypatch):
+    """Drop one producer edge: some order the remaining edges allow goes wrong, so
+    the producer-edge simulation above can tell a sufficient edge set."""
+    real_query = fft3d.query_pipeline
+
+    def broken(*args, **kw):
+        stages, tasks = real_query(*args, **kw)
+        for t in tasks:
+            if t["stage"] == 2 and t["deps"]:
+                t["deps"] = t["deps"][1:]
+                break
+        return stages, tasks
+
+    monkeypatch.setattr(fft3d, "query_pipeline", broken)
+    shape, grid = (6, 4, 8), (2, 2)
+    a = synth.complex_normal(shape, 1)
+    rng = np.random.default_rng(3)
+    errs = [oracle.rel_l2(_simulate_graph(fft3d, shape, grid, 0, a, rng), oracle.fftn(a)) for _ in range(12)]
+    assert max(e if np.isfinite(e) else np.inf for e in errs) > 1e-3
+
+
 def test_simulator_catches_a_missing_edge(fft3d, monkeypatch):
     """Drop one dependency from the library's graph: some random order then goes wrong."""
     real_query = fft3d.query_pipeline
