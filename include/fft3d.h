@@ -170,7 +170,8 @@ fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
  * Number of internal HIP streams the tiles are placed on (1..16; default 4).
  * The streams are created by the first call that needs them.  With 1 stream,
  * or a 1x1 pencil grid (one tile per stage), every tile is enqueued directly
- * on the caller's stream in dependency order.
+ * on the caller's stream in dependency order.  Calls that replay a task graph
+ * (fft3d_set_graphs) use no internal streams.  Drops the cached graphs.
  */
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
