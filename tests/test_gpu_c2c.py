@@ -219,9 +219,10 @@ def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
-@pytest.mark.skip(reason="its first run ended in a host segmentation fault inside the library call on "
-                         "MI355X (no GPU fault); cause not shown, so plan-level graph replay is switched off "
-                         "and this case stays off the GPU")
+@pytest.mark.skip(reason="its first run (stream-capture graph replay of forked pipelines) ended in a host "
+                         "segmentation fault inside the library call on MI355X (no GPU fault); cause not "
+                         "shown, so that capture path was removed and this case, which also captures a "
+                         "tiled plan into a caller's graph, stays off the GPU")
 def test_graph_replay_of_forked_pipelines(gpu_lib, dtype):
     """A forked tile pipeline on a non-default stream is captured into a hipGraph and
     replayed: bitwise equal to direct issue, across replays with eager work in
