@@ -64,8 +64,7 @@ struct fft3d_batch_s {
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
     std::vector<CachedGraph> graphs;
-    hipStream_t last_stream = nullptr;
-    bool used = false;
+    hipEvent_t done = nullptr;  // recorded on the caller's stream after each call
 };
 
 namespace {
@@ -81,9 +80,29 @@ void drop_graphs(fft3d_batch_s* b)
     b->graphs.clear();
 }
 
+// Wait for the work of the last call (the caller's stream itself may be gone).
+void wait_done(fft3d_batch_s* b)
+{
+    if (b->done) hipEventSynchronize(b->done);
+}
+
+// After a call issued on `s` (not into a capture): mark its end.
+fft3d_status finish(fft3d_batch_s* b, hipStream_t s, hipStreamCaptureStatus cap, fft3d_status st)
+{
+    if (st != FFT3D_OK || cap != hipStreamCaptureStatusNone) return st;
+    hipError_t e = hipSuccess;
+    if (!b->done) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        b->done = nullptr;
+        return set_hip_error(e, "hipEventCreate");
+    }
+    e = hipEventRecord(b->done, s);
+    return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipEventRecord");
+}
+
 void release(fft3d_batch_s* b)
 {
-    if (b->used) hipStreamSynchronize(b->last_stream);
+    wait_done(b);
     for (hipStream_t s : b->streams)
         if (s) {
             hipStreamSynchronize(s);
@@ -93,6 +112,7 @@ void release(fft3d_batch_s* b)
     for (hipEvent_t e : b->joins)
         if (e) hipEventDestroy(e);
     if (b->fork) hipEventDestroy(b->fork);
+    if (b->done) hipEventDestroy(b->done);
     for (auto& kv : b->plans) fft3d_destroy(kv.second);
     delete b;
 }
@@ -156,8 +176,6 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
     hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return set_hip_error(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    b->last_stream = s;
-    b->used = true;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (s != nullptr) {
         e = hipStreamIsCapturing(s, &cap);
@@ -166,7 +184,8 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
     // the legacy default stream cannot be captured; a stream the caller is
     // capturing records our launches into the caller's graph
     const bool dag = b->mode == 3 && cap == hipStreamCaptureStatusNone;
-    if (!dag && (b->mode != 0 || s == nullptr || cap != hipStreamCaptureStatusNone)) return issue(b, op, in, out, s);
+    if (!dag && (b->mode != 0 || s == nullptr || cap != hipStreamCaptureStatusNone))
+        return finish(b, s, cap, issue(b, op, in, out, s));
     CachedGraph* hit = nullptr;
     for (auto& g : b->graphs) {
         if (g.op != op) continue;
@@ -232,7 +251,7 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         hit = &b->graphs.back();
     }
     e = hipGraphLaunch(hit->exec, s);
-    return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch");
+    return finish(b, s, cap, e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch"));
 }
 
 std::vector<double> batch_costs(const std::vector<PlanDesc>& ffts)
@@ -320,7 +339,7 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
-    if (b->used) hipStreamSynchronize(b->last_stream);
+    wait_done(b);
     drop_graphs(b);  // launch shapes are baked into the captured graphs
     return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
 }
@@ -332,7 +351,7 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     if (staging != FFT3D_STAGING_IN_PLACE && staging != FFT3D_STAGING_FUSED_XY)
         return set_error(FFT3D_ERR_INVALID_ARG, "a batch stages in place or in fused x-y planes (no workspace)");
-    if (b->used) hipStreamSynchronize(b->last_stream);
+    wait_done(b);
     drop_graphs(b);  // the stage lists are baked into the captured graphs
     return fft3d_set_staging(it->second, staging);
 }
@@ -341,7 +360,7 @@ fft3d_status fft3d_batch_set_mode(fft3d_batch_t b, int mode)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
     if (mode < 0 || mode > 3) return set_error(FFT3D_ERR_INVALID_ARG, "mode must be 0, 1, 2 or 3");
-    if (b->used) hipStreamSynchronize(b->last_stream);
+    wait_done(b);
     drop_graphs(b);  // graphs of one mode are not replayed in another
     b->mode = mode;
     return FFT3D_OK;
