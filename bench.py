@@ -219,19 +219,36 @@ def _extras(reps, torch, fft3d, synth, np):
     brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
             "hbm_bytes_per_call": bbytes}
     side = torch.cuda.Stream()
+    # launch shapes per transform shape from the autotuner (untimed; measured
+    # once, then taken from its cache file, a temporary one here)
+    from paper_2601_12209_amd import autotune
+    import tempfile
+    tune_path = os.path.join(tempfile.gettempdir(), f"fft3d_tune_{os.getpid()}.json")
+    own_cache = "FFT3D_TUNE_CACHE" not in os.environ
+    if own_cache:
+        os.environ["FFT3D_TUNE_CACHE"] = tune_path
+    brep["launch_shapes"] = "autotuned"
     for mode, name in ((3, "task_graph"), (0, "graph_4_streams"), (1, "direct_4_streams"),
                        (2, "serial_one_stream")):
         bp = fft3d.BatchPlan(shapes, mode=mode)
+        autotune.tune_batch(bp, reps=5)
         with torch.cuda.stream(side):
             ms = _time(lambda: bp.forward(xs, outs), reps, torch)
         brep[name] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
                       "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bp.close()
     bp = fft3d.BatchPlan(shapes)
+    autotune.tune_batch(bp, reps=5)
     with torch.cuda.stream(side):
         bp.forward(xs, outs)
     torch.cuda.synchronize()
     bp.close()
+    if own_cache:
+        del os.environ["FFT3D_TUNE_CACHE"]
+        try:
+            os.remove(tune_path)
+        except OSError:
+            pass
     rep["batched_64_uneven_c64"] = brep
     checks.append(("batched_64_uneven_forward_worst", [o.cpu().numpy() for o in outs],
                    lambda: [_oracle().fftn(h.astype(np.complex128)) for h in host]))

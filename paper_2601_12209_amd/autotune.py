@@ -49,13 +49,14 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
-def _stage_key(plan: fft3d.Plan, axis: int) -> str:
+def _stage_key(plan: fft3d.Plan, axis: int, nstages: int = 3) -> str:
     nz, ny, nx = plan.shape
     n = (nx, ny, nz)[axis]
     nxc = (plan.half_pitch or nx // 2 + 1) if plan.r2c else nx
     stride = (1, nxc, nxc * ny)[axis]
     kind = "r2c" if (plan.r2c and axis == 0) else "c2c"
-    return f"{_arch()}|{'c64' if plan.code == fft3d.C64 else 'c128'}|{kind}|n{n}|axis{axis}|stride{stride}"
+    return (f"{_arch()}|{'c64' if plan.code == fft3d.C64 else 'c128'}|{kind}|n{n}|axis{axis}|stride{stride}"
+            f"|stages{nstages}")
 
 
 def stage_candidates(axis: int):
@@ -64,16 +65,22 @@ def stage_candidates(axis: int):
     return [(lw, td, sp, 0) for lw in (4, 8, 16, 32, 64) for td in (1, 2, 4) for sp in (0, 1)]
 
 
-def _time_stage(plan, x, out, axis, reps):
+def _forward_stage_count(plan, x, out):
+    plan.set_timing(True)
+    plan.forward(x, out=out)
+    n = len(plan.stage_times())
+    plan.set_timing(False)
+    return n
+
+
+def _time_stage(plan, x, out, index, reps):
     plan.set_timing(True)
     plan.forward(x, out=out)
     plan.stage_times()
     ts = []
     for _ in range(reps):
         plan.forward(x, out=out)
-        t = plan.stage_times()
-        # forward stages run x, y, z
-        ts.append(t[axis])
+        ts.append(plan.stage_times()[index])
     plan.set_timing(False)
     ts.sort()
     return ts[len(ts) // 2]
@@ -91,8 +98,12 @@ def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: 
     else:
         x = torch.randn(plan.shape, dtype=plan.complex_dtype, device="cuda")
         out = torch.empty_like(x)
-    for axis in (0, 1, 2):
-        key = _stage_key(plan, axis)
+    # forward stages: x, y, z; with fused x-y planes the plane kernel (a fixed
+    # launch shape) and then z, so only the z stage is tuned
+    nst = _forward_stage_count(plan, x, out)
+    stage_of = {0: 0, 1: 1, 2: 2} if nst == 3 else {2: nst - 1}
+    for axis, index in stage_of.items():
+        key = _stage_key(plan, axis, nst)
         if key in cache:
             shape = tuple(cache[key])
             try:
@@ -103,14 +114,14 @@ def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: 
                 pass
         best = None
         plan.set_stage_config(axis, 0)
-        t0 = _time_stage(plan, x, out, axis, reps)
+        t0 = _time_stage(plan, x, out, index, reps)
         best = (t0, None)
         for cand in stage_candidates(axis):
             try:
                 plan.set_stage_config(axis, *cand)
             except RuntimeError:
                 continue
-            t = _time_stage(plan, x, out, axis, reps)
+            t = _time_stage(plan, x, out, index, reps)
             if verbose:
                 print(f"axis {axis} {cand}: {t:.4f} ms")
             if t < best[0]:
