@@ -225,6 +225,13 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
     } else {
         int lw = 1;
         while (2 * lw * tpl <= 128) lw *= 2;
+        // lengths with factors 3, 5, 7 have thread counts per line (105 for
+        // 840, 45 for 720, 60 for 480) that leave 128-thread workgroups with
+        // partial wavefronts and too many workgroups: take >= 256 threads
+        // (measured x stage, complex64: 840^3 2.92 -> 2.09 ms, 720^3 1.64 ->
+        // 1.46-1.49, 480^3 0.38 -> 0.33-0.34)
+        if ((nk & (nk - 1)) != 0)
+            while (lw * tpl < 256) lw *= 2;
         c.lw = lw;
         c.split = c2c && c2c_variant_available(nk, 1, 1) ? 1 : 0;
         c.pad = 1;
