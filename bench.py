@@ -181,6 +181,29 @@ def _extras(reps, torch, fft3d, synth, np):
             p.close()
         del x
         torch.cuda.empty_cache()
+    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (replayed as a
+    # task graph) and on one tile per stage; the values do not change the
+    # timing, so the input is torch's normal generator (parity of the
+    # turbulence field at this size is a GPU test)
+    c3 = synth.CFG3
+    m3 = int(np.prod(c3["shape"]))
+    nh3 = (c3["shape"][2] // 2 + 1) * c3["shape"][0] * c3["shape"][1]
+    x = torch.randn(c3["shape"], dtype=torch.float32, device="cuda")
+    for grid in (tuple(c3["grid"]), (1, 1)):
+        p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True)
+        H = p.forward(x)
+        y = torch.empty_like(x)
+        with torch.cuda.stream(side):
+            ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), max(3, reps // 2), torch)
+        bytes_moved = 2 * m3 * 4 + 10 * nh3 * 2 * 4
+        rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}"] = {
+            "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * m3 * math.log2(m3) / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "issue": "task graph" if grid[0] * grid[1] >= 16 else "direct"}
+        p.close()
+        del H, y
+    del x
+    torch.cuda.empty_cache()
     # 840^3 complex64: the largest grid of the paper's GPU runs (lengths with a
     # factor 7), whole on one GPU; parity is covered by the GPU tests
     n8 = 840
