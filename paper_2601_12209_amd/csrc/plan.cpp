@@ -25,6 +25,24 @@ void split_range(int64_t n, int p, int i, int64_t* lo, int64_t* hi)
     *hi = *lo + q + (i < r ? 1 : 0);
 }
 
+// x ranges are the lanes of the y and z stages' row tiles: their edges are
+// rounded to whole cache lines (granule values) when every tile keeps at
+// least two lines, so no tile starts its rows in the middle of a line
+// (otherwise balanced as split_range)
+void split_x(int64_t n, int p, int i, int64_t granule, int64_t* lo, int64_t* hi)
+{
+    if (p > 1 && n / p >= 2 * granule) {
+        auto edge = [&](int k) -> int64_t {
+            if (k >= p) return n;
+            return std::min<int64_t>(n, ((int64_t)k * n / p + granule / 2) / granule * granule);
+        };
+        *lo = edge(i);
+        *hi = edge(i + 1);
+        return;
+    }
+    split_range(n, p, i, lo, hi);
+}
+
 std::vector<Box> stage_boxes(const PlanDesc& d, int axis)
 {
     const int64_t ext[3] = {d.nxc(), d.ny, d.nz};
@@ -39,7 +57,8 @@ std::vector<Box> stage_boxes(const PlanDesc& d, int axis)
             Box b;
             b.lo[axis] = 0;
             b.hi[axis] = ext[axis];
-            split_range(ext[s1], d.p1, j1, &b.lo[s1], &b.hi[s1]);
+            if (s1 == 0) split_x(ext[0], d.p1, j1, d.dtype == 1 ? 8 : 16, &b.lo[0], &b.hi[0]);
+            else split_range(ext[s1], d.p1, j1, &b.lo[s1], &b.hi[s1]);
             split_range(ext[s2], d.p2, j2, &b.lo[s2], &b.hi[s2]);
             out.push_back(b);
         }

@@ -496,3 +496,27 @@ def test_launch_query_rejects_bad_arguments(fft3d):
         fft3d.query_launches((8, 8, 8), "c64", r2c=True, staging=2)
     with pytest.raises(ValueError):
         fft3d.query_launches((8, 8, 11), "c64")
+
+
+def test_x_ranges_of_tiles_start_on_cache_lines(fft3d):
+    """y and z tiles split x on whole cache lines (16 complex64 / 8 complex128
+    values) when every tile keeps two lines, else balanced; a partition either way."""
+    for nx, p1, dtype_granule in ((1024, 8, 16), (512, 4, 16), (200, 3, 16)):
+        for op in (0, 1):
+            stages, tasks = fft3d.query_pipeline((16, 16, nx), (p1, 1), r2c=True, op=op, nstreams=1)
+            nxc = nx // 2 + 1
+            for t in tasks:
+                if stages[t["stage"]]["axis"] == 0:
+                    continue
+                x0, x1 = t["box"][0], t["box"][1]
+                if nxc // p1 >= 2 * dtype_granule:
+                    assert x0 % dtype_granule == 0, (nx, p1, t["box"])
+                assert x1 > x0
+    # 513 values over 8 tiles: edges 0, 64, ..., 448, 513
+    stages, tasks = fft3d.query_pipeline((8, 8, 1024), (8, 1), r2c=True, op=0, nstreams=1)
+    xs = sorted({(t["box"][0], t["box"][1]) for t in tasks if stages[t["stage"]]["axis"] == 1})
+    assert xs == [(64 * k, 64 * (k + 1)) for k in range(7)] + [(448, 513)]
+    # too narrow for two lines per tile: balanced (20 values over 3 tiles)
+    stages, tasks = fft3d.query_pipeline((8, 8, 20), (3, 1), op=0, nstreams=1)
+    xs = sorted({(t["box"][0], t["box"][1]) for t in tasks if stages[t["stage"]]["axis"] == 1})
+    assert xs == [(0, 7), (7, 14), (14, 20)]
