@@ -158,7 +158,8 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
  * `out`) and SWAP_YZ (forward only: x writes `out`, y writes the workspace
  * with y and z swapped, z reads it back into `out`; bitwise the same result);
  * their inverse, backward and Poisson stages do not change.  Default for R2C:
- * SWAP_YZ when the half spectrum takes at least 512 MiB, else IN_PLACE.
+ * SWAP_YZ when the half spectrum takes at least 512 MiB and less than 2 GiB
+ * (faster at 512^3, slower at 1024^3 on MI355X), else IN_PLACE.
  * FUSED_XY on an R2C plan -> FFT3D_ERR_WRONG_PLAN.
  */
 #define FFT3D_STAGING_IN_PLACE 0

@@ -51,6 +51,7 @@ constexpr int64_t kGraphMinTiles = 16;
 // faster at 512^3, slower at 256^3, whose 128-256 MiB field stays in the
 // 256 MB Infinity Cache)
 constexpr size_t kSwapStagingMinBytes = (size_t)512 << 20;
+constexpr size_t kR2CSwapMaxBytes = (size_t)2 << 30;  // R2C: half spectra from here stage in place
 
 }  // namespace
 
@@ -754,8 +755,11 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         }
         p->ws_owned = true;
         // the forward then runs x into the output, y into the swapped
-        // workspace and z back (512^3: 0.79 -> 0.73 ms f32, 1.47 -> 1.41 ms f64)
-        if (ny > 1 && nz > 1 && (size_t)d.nxc() * ny * nz * elem_bytes(dtype) >= kSwapStagingMinBytes)
+        // workspace and z back (512^3: 0.79 -> 0.73 ms f32, 1.47 -> 1.41 ms
+        // f64); at 1024^3 f32 (4.3 GB) in place is the faster one (forward
+        // 6.54 ms against 6.97), so only half spectra below 2 GiB swap
+        const size_t half = (size_t)d.nxc() * ny * nz * elem_bytes(dtype);
+        if (ny > 1 && nz > 1 && half >= kSwapStagingMinBytes && half < kR2CSwapMaxBytes)
             p->d.staging = STAGING_SWAP_YZ;
     }
     // large C2C plans stage through a y/z-swapped workspace by default (see
