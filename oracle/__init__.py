@@ -51,8 +51,13 @@ def _load():
         lib.oracle_c2r3d.argtypes = [L, L, L, P, P, I]
         lib.oracle_poisson3d.argtypes = [L, L, L, P, P]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_r2r1d.argtypes = [L, P, P, I]
+        lib.oracle_ppb_forward3d.argtypes = [L, L, L, P, P, I]
+        lib.oracle_ppb_inverse3d.argtypes = [L, L, L, P, P, I]
+        lib.oracle_poisson_ppb3d.argtypes = [L, L, L, P, P, I]
         for f in ("oracle_dft1d", "oracle_c2c3d", "oracle_brute3d", "oracle_dft3d_points",
-                  "oracle_r2c3d", "oracle_c2r3d", "oracle_poisson3d", "oracle_num_threads"):
+                  "oracle_r2c3d", "oracle_c2r3d", "oracle_poisson3d", "oracle_num_threads",
+                  "oracle_r2r1d", "oracle_ppb_forward3d", "oracle_ppb_inverse3d", "oracle_poisson_ppb3d"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -181,6 +186,89 @@ def poisson_grad(w) -> np.ndarray:
     CPU tests pin this identity numerically (adjointness and finite differences).
     """
     return poisson(w)
+
+
+def dft3d_lines(a, kx, ky, sign: int = -1) -> np.ndarray:
+    """Whole z-lines of the 3D DFT: out[:, i] = X[0..nz-1, ky[i], kx[i]].
+
+    The definition's triple sum factored per axis, X[kz, ky, kx] =
+    sum_z w_z^(kz z) sum_y w_y^(ky y) sum_x w_x^(kx x) a[z, y, x]: first the
+    x sums for the distinct kx (a matrix product with those root columns), then
+    the y sums, then the z sums for every kz (the length-nz DFT matrix).  Each
+    root is exp(sign 2 pi i m / n) with the exponent m = k j reduced mod n
+    before it is evaluated.  ``a`` is real or complex (nz, ny, nx); kx, ky are
+    equal-length integer sequences.  Costs O(N * #distinct kx), so whole lines
+    of a 1024^3 field take seconds.
+    """
+    a = np.asarray(a)
+    nz, ny, nx = a.shape
+    kx = np.asarray(kx, dtype=np.int64).ravel()
+    ky = np.asarray(ky, dtype=np.int64).ravel()
+    if kx.shape != ky.shape or np.any(kx < 0) or np.any(kx >= nx) or np.any(ky < 0) or np.any(ky >= ny):
+        raise ValueError("kx, ky must be equal-length index sequences within the grid")
+
+    def roots(k, n):  # (n, len(k)) matrix exp(sign 2 pi i (k j mod n) / n)
+        m = (np.arange(n, dtype=np.int64)[:, None] * k[None, :]) % n
+        return np.exp(sign * 2j * np.pi * m / n)
+
+    ux, inv_x = np.unique(kx, return_inverse=True)
+    flat = a.reshape(nz * ny, nx)
+    wx = roots(ux, nx)
+    if np.iscomplexobj(flat):
+        sx = flat.astype(np.complex128, copy=False) @ wx
+    else:  # real field: two real products keep the temporaries real
+        f64 = flat.astype(np.float64, copy=False)
+        sx = f64 @ wx.real + 1j * (f64 @ wx.imag)
+    sx = sx.reshape(nz, ny, len(ux))[:, :, inv_x]      # (nz, ny, npairs)
+    wy = roots(ky, ny)                                  # (ny, npairs)
+    sxy = np.einsum("zyp,yp->zp", sx, wy)              # (nz, npairs)
+    wz = roots(np.arange(nz, dtype=np.int64), nz)       # (nz, nz), symmetric
+    return wz @ sxy
+
+
+def r2r1d(x, kind: int) -> np.ndarray:
+    """Real-to-real transform of one real line, unnormalised (FFTW's REDFT/RODFT kinds):
+    0 DCT-II, 1 DCT-III, 2 DST-II, 3 DST-III; kinds 1 and 3 undo 0 and 2 up to 2n."""
+    x = _f64(x).ravel()
+    out = np.empty_like(x)
+    _check(_load().oracle_r2r1d(x.size, _ptr(x), _ptr(out), int(kind)), "r2r1d")
+    return out
+
+
+BC_NEUMANN, BC_DIRICHLET = 0, 1
+
+
+def ppb_forward(f, bc: int = BC_NEUMANN) -> np.ndarray:
+    """(Periodic, Periodic, Bounded) forward transform of a real (nz, ny, nx) field:
+    DFT along x (kx = 0..nx//2) and y, then DCT-II (Neumann) or DST-II (Dirichlet)
+    along z, unscaled; shape (nz, ny, nx//2 + 1)."""
+    f = _f64(f)
+    nz, ny, nx = f.shape
+    out = np.empty((nz, ny, nx // 2 + 1), dtype=np.complex128)
+    _check(_load().oracle_ppb_forward3d(nx, ny, nz, _ptr(f), _ptr(out), int(bc)), "ppb_forward3d")
+    return out
+
+
+def ppb_inverse(h, nx: int, bc: int = BC_NEUMANN) -> np.ndarray:
+    """Inverse of :func:`ppb_forward` (DCT-III / DST-III over 2 nz, inverse DFT along y, C2R along x)."""
+    h = _c128(h)
+    nz, ny, nh = h.shape
+    if nh != nx // 2 + 1:
+        raise ValueError("half-spectrum width must be nx//2+1")
+    out = np.empty((nz, ny, nx), dtype=np.float64)
+    _check(_load().oracle_ppb_inverse3d(nx, ny, nz, _ptr(h), _ptr(out), int(bc)), "ppb_inverse3d")
+    return out
+
+
+def poisson_ppb(f, bc: int = BC_NEUMANN) -> np.ndarray:
+    """Spectral Poisson solve with x, y periodic (side 2 pi) and z bounded (0, pi), cell-centred:
+    phi = ppb_inverse(M * ppb_forward(f)), M = -1/|k|^2 (0 for the zero wavenumber); z
+    wavenumbers k (Neumann, cos modes) or k + 1 (Dirichlet, sin modes)."""
+    f = _f64(f)
+    nz, ny, nx = f.shape
+    out = np.empty_like(f)
+    _check(_load().oracle_poisson_ppb3d(nx, ny, nz, _ptr(f), _ptr(out), int(bc)), "poisson_ppb3d")
+    return out
 
 
 def rel_l2(y, ref) -> float:

@@ -34,8 +34,13 @@
  *  - Poisson multiplier (periodic box of length 2*pi): M(k) = -1/|k|^2 with
  *    integer wavenumbers k_j = j for j <= n/2 and j - n above, M(0) = 0.
  *
+ * Real-to-real transforms (DCT-II/III, DST-II/III) and the transforms and
+ * Poisson solve of the (Periodic, Periodic, Bounded) topology are below,
+ * with their own readings.
+ *
  * Parity status: every exported function is pinned by the CPU tests against
- * closed forms, invariants, brute force and numpy.fft; none is unpinned.
+ * closed forms, invariants, brute force, numpy.fft and scipy.fft's DCT/DST;
+ * none is unpinned.
  */
 #include <complex.h>
 #include <math.h>
@@ -392,6 +397,215 @@ int oracle_poisson3d(long nx, long ny, long nz, const double *f, double *phi)
                     H[kx + nh * (ky + ny * kz)] *= m;
                 }
         err = oracle_c2r3d(nx, ny, nz, (const double *)H, phi, 1);
+    }
+    free(H);
+    return err;
+}
+
+/* ------------------------------------------------------- R2R along z */
+
+/* Real-to-real transforms of one real sequence of length n (the DCT and DST
+ * that the paper's plan supports besides C2C and R2C, Sec. V-B), written as
+ * the plain O(n^2) sums, in the unnormalised convention of FFTW's REDFT and
+ * RODFT kinds:
+ *   kind 0, DCT-II : Y_k = 2 sum_{j<n} x_j cos(pi (j+1/2) k / n)
+ *   kind 1, DCT-III: Y_k = x_0 + 2 sum_{0<j<n} x_j cos(pi j (k+1/2) / n)
+ *   kind 2, DST-II : Y_k = 2 sum_{j<n} x_j sin(pi (j+1/2) (k+1) / n)
+ *   kind 3, DST-III: Y_k = (-1)^k x_{n-1} + 2 sum_{j<n-1} x_j sin(pi (j+1) (k+1/2) / n)
+ * Kinds 1 and 3 undo kinds 0 and 2 up to the factor 2n.  Every angle is an
+ * integer multiple of 2 pi / (4n) and is taken from the long-double root
+ * table of that order. */
+static double r2r_term(long n, long j, long k, int kind, const long double *c4, const long double *s4)
+{
+    long m;
+    switch (kind) {
+    case 0: m = ((2 * j + 1) * k) % (4 * n); return (double)c4[m];
+    case 1: m = (j * (2 * k + 1)) % (4 * n); return (double)c4[m];
+    case 2: m = ((2 * j + 1) * (k + 1)) % (4 * n); return (double)s4[m];
+    default: m = ((j + 1) * (2 * k + 1)) % (4 * n); return (double)s4[m];
+    }
+}
+
+static int r2r_tables(long n, long double **c4, long double **s4)
+{
+    *c4 = (long double *)malloc(sizeof(long double) * (size_t)(4 * n));
+    *s4 = (long double *)malloc(sizeof(long double) * (size_t)(4 * n));
+    if (!*c4 || !*s4) {
+        free(*c4); free(*s4);
+        return -2;
+    }
+    for (long m = 0; m < 4 * n; m++) unit_root(m, 4 * n, &(*c4)[m], &(*s4)[m]);
+    return 0;
+}
+
+/* out = kind(in) for one line; in and out are n doubles (need not differ). */
+static void r2r_line(long n, const double *in, double *out, int kind, const long double *c4,
+                     const long double *s4)
+{
+    for (long k = 0; k < n; k++) {
+        double acc = 0.0;
+        for (long j = 0; j < n; j++) {
+            double w;
+            if (kind == 1 && j == 0) w = 1.0;
+            else if (kind == 3 && j == n - 1) w = (k % 2 == 0) ? 1.0 : -1.0;
+            else w = 2.0 * r2r_term(n, j, k, kind, c4, s4);
+            acc += w * in[j];
+        }
+        out[k] = acc;
+    }
+}
+
+int oracle_r2r1d(long n, const double *in, double *out, int kind)
+{
+    if (n < 1 || !in || !out || kind < 0 || kind > 3) return -1;
+    long double *c4, *s4;
+    if (r2r_tables(n, &c4, &s4)) return -2;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!tmp) {
+        free(c4); free(s4);
+        return -2;
+    }
+    r2r_line(n, in, tmp, kind, c4, s4);
+    memcpy(out, tmp, sizeof(double) * (size_t)n);
+    free(tmp); free(c4); free(s4);
+    return 0;
+}
+
+/* The R2R transform of `kind` along z of a complex (nxh x ny x nz) array, on
+ * the real and the imaginary parts separately (the transform is real-linear),
+ * times `scale`. */
+static int r2r_axis_z(dcplx *a, long nxh, long ny, long nz, int kind, double scale)
+{
+    long double *c4, *s4;
+    if (r2r_tables(nz, &c4, &s4)) return -2;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *re = (double *)malloc(sizeof(double) * (size_t)nz);
+        double *im = (double *)malloc(sizeof(double) * (size_t)nz);
+        double *ro = (double *)malloc(sizeof(double) * (size_t)nz);
+        double *io = (double *)malloc(sizeof(double) * (size_t)nz);
+        int ok = re && im && ro && io;
+        if (!ok) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (long l = 0; l < nxh * ny; l++) {
+            if (!ok) continue;
+            for (long z = 0; z < nz; z++) {
+                re[z] = creal(a[l + nxh * ny * z]);
+                im[z] = cimag(a[l + nxh * ny * z]);
+            }
+            r2r_line(nz, re, ro, kind, c4, s4);
+            r2r_line(nz, im, io, kind, c4, s4);
+            for (long z = 0; z < nz; z++) a[l + nxh * ny * z] = (ro[z] + I * io[z]) * scale;
+        }
+        free(re); free(im); free(ro); free(io);
+    }
+    free(c4); free(s4);
+    return err;
+}
+
+/* Forward transform of the (Periodic, Periodic, Bounded) topology (the
+ * Poisson solver case of Sec. VI-B): real f (Nx x Ny x Nz) -> its DFT along x
+ * (kx = 0..Nx/2 kept, Hermitian symmetry) and y, then along the bounded z
+ * axis the DCT-II (bc 0: homogeneous Neumann walls) or the DST-II (bc 1:
+ * homogeneous Dirichlet walls), all unscaled; out is (Nx/2+1) x Ny x Nz
+ * complex. */
+int oracle_ppb_forward3d(long nx, long ny, long nz, const double *f, double *out, int bc)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !f || !out || bc < 0 || bc > 1) return -1;
+    long n = nx * ny * nz, nh = nx / 2 + 1;
+    dcplx *full = (dcplx *)malloc(sizeof(dcplx) * (size_t)n);
+    if (!full) return -2;
+    for (long i = 0; i < n; i++) full[i] = f[i];
+    int err = dft_axis(full, nx, ny, nz, 0, -1);
+    if (!err) err = dft_axis(full, nx, ny, nz, 1, -1);
+    dcplx *H = (dcplx *)out;
+    if (!err) {
+        for (long zy = 0; zy < ny * nz; zy++)
+            for (long kx = 0; kx < nh; kx++) H[kx + nh * zy] = full[kx + nx * zy];
+        err = r2r_axis_z(H, nh, ny, nz, bc == 0 ? 0 : 2, 1.0);
+    }
+    free(full);
+    return err;
+}
+
+/* Inverse of oracle_ppb_forward3d: along z the DCT-III (bc 0) or DST-III
+ * (bc 1) divided by 2 Nz, then the inverse DFT along y (1/Ny) and the
+ * Hermitian-extended inverse DFT of every x-line (1/Nx, real part kept; the
+ * imaginary parts of the kx = 0 and kx = Nx/2 bins dropped as in
+ * oracle_c2r3d). */
+int oracle_ppb_inverse3d(long nx, long ny, long nz, const double *in, double *out, int bc)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !in || !out || bc < 0 || bc > 1) return -1;
+    long nh = nx / 2 + 1, nhalf = nh * ny * nz;
+    dcplx *h = (dcplx *)malloc(sizeof(dcplx) * (size_t)nhalf);
+    if (!h) return -2;
+    memcpy(h, in, sizeof(dcplx) * (size_t)nhalf);
+    int err = r2r_axis_z(h, nh, ny, nz, bc == 0 ? 1 : 3, 1.0 / (2.0 * (double)nz));
+    if (!err) err = dft_axis(h, nh, ny, nz, 1, +1);
+    dcplx *w = err ? NULL : make_roots(nx, +1);
+    if (!err && !w) err = -2;
+    if (err) {
+        free(h);
+        return err;
+    }
+    const double f = 1.0 / ((double)nx * (double)ny);
+#pragma omp parallel
+    {
+        dcplx *line = (dcplx *)malloc(sizeof(dcplx) * (size_t)nx);
+        dcplx *res = (dcplx *)malloc(sizeof(dcplx) * (size_t)nx);
+        dcplx *tmp = (dcplx *)malloc(sizeof(dcplx) * (size_t)(2 * nx));
+        int ok = line && res && tmp;
+        if (!ok) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (long zy = 0; zy < ny * nz; zy++) {
+            if (!ok) continue;
+            const dcplx *src = h + nh * zy;
+            for (long kx = 0; kx < nh; kx++) line[kx] = src[kx];
+            line[0] = creal(line[0]);
+            if (nx % 2 == 0) line[nx / 2] = creal(line[nx / 2]);
+            for (long kx = nh; kx < nx; kx++) line[kx] = conj(line[nx - kx]);
+            dft_rec(nx, line, 1, res, w, nx, tmp);
+            for (long x = 0; x < nx; x++) out[x + nx * zy] = creal(res[x]) * f;
+        }
+        free(line); free(res); free(tmp);
+    }
+    free(w);
+    free(h);
+    return err;
+}
+
+/* Spectral Poisson solve of the (Periodic, Periodic, Bounded) topology:
+ * phi = ppb_inverse( M .* ppb_forward(f) ).  x and y are periodic of side
+ * 2 pi (integer wavenumbers as in oracle_poisson3d); z is the interval
+ * (0, pi) of Nz cells with values at the cell centres pi (j + 1/2) / Nz, whose
+ * Neumann modes cos(k z) (bc 0, k = 0..Nz-1) and Dirichlet modes sin(k z)
+ * (bc 1, k = 1..Nz) have integer wavenumbers.  M = -1/|k|^2, and 0 for the
+ * all-zero wavenumber (Neumann only). */
+int oracle_poisson_ppb3d(long nx, long ny, long nz, const double *f, double *phi, int bc)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !f || !phi || bc < 0 || bc > 1) return -1;
+    long nh = nx / 2 + 1;
+    dcplx *H = (dcplx *)malloc(sizeof(dcplx) * (size_t)(nh * ny * nz));
+    if (!H) return -2;
+    int err = oracle_ppb_forward3d(nx, ny, nz, f, (double *)H, bc);
+    if (!err) {
+        for (long kz = 0; kz < nz; kz++)
+            for (long ky = 0; ky < ny; ky++)
+                for (long kx = 0; kx < nh; kx++) {
+                    double a = wavenumber(kx, nx), b = wavenumber(ky, ny);
+                    double c = (double)(bc == 0 ? kz : kz + 1);
+                    double k2 = a * a + b * b + c * c;
+                    double m = (k2 == 0.0) ? 0.0 : -1.0 / k2;
+                    H[kx + nh * (ky + ny * kz)] *= m;
+                }
+        err = oracle_ppb_inverse3d(nx, ny, nz, (const double *)H, phi, bc);
     }
     free(H);
     return err;

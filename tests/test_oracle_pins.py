@@ -258,3 +258,135 @@ def test_turbulence_field_recovers_projected_spectrum():
                 + np.arange(nx // 2 + 1)[None, None, :] ** 2)
     inner = np.abs(S[:, :, 1:nx // 2])
     assert np.allclose(inner, k[:, :, 1:nx // 2] ** (-11.0 / 6.0), rtol=1e-12)
+
+
+# ------------------------------------------------------------------ sampled lines
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (5, 3, 7), (8, 8, 9)])
+def test_dft3d_lines_against_brute_force_and_numpy(shape):
+    """Whole z-lines of the DFT at chosen (kx, ky) against the literal triple sum
+    (complex input) and numpy.fft (real input)."""
+    nz, ny, nx = shape
+    a = _rand(shape, 71)
+    kx = [0, nx - 1, 1, nx // 2, 0]
+    ky = [0, 1, ny - 1, ny // 2, ny - 1]
+    want = oracle.brute3d(a)[:, ky, kx]
+    np.testing.assert_allclose(oracle.dft3d_lines(a, kx, ky), want, rtol=0, atol=1e-12)
+    r = a.real.copy()
+    np.testing.assert_allclose(oracle.dft3d_lines(r, kx, ky), np.fft.fftn(r)[:, ky, kx], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.dft3d_lines(a, kx, ky, +1), oracle.brute3d(a, +1)[:, ky, kx], atol=1e-12)
+
+
+def test_dft3d_lines_cosine_closed_form():
+    """cos(2 pi (p x/nx + q y/ny + s z/nz)) has N/2 at (p, q, s) and (-p, -q, -s), 0 elsewhere."""
+    shape = (6, 10, 12)
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    p, q, s = 3, 2, 1
+    a = np.cos(2 * np.pi * (p * x / nx + q * y / ny + s * z / nz))
+    lines = oracle.dft3d_lines(a, [p, nx - p, 0], [q, ny - q, q])
+    want = np.zeros((nz, 3), complex)
+    want[s, 0] = n / 2
+    want[nz - s, 1] = n / 2
+    np.testing.assert_allclose(lines, want, atol=1e-10)
+
+
+# ------------------------------------------------------------------ real-to-real
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 12, 16, 30, 64])
+def test_r2r1d_against_scipy(n):
+    """DCT-II/III and DST-II/III (unnormalised) against scipy.fft (an independent library)."""
+    import scipy.fft as sfft
+
+    x = synth.real_normal((n,), 80 + n)
+    np.testing.assert_allclose(oracle.r2r1d(x, 0), sfft.dct(x, type=2), rtol=0, atol=1e-12 * n)
+    np.testing.assert_allclose(oracle.r2r1d(x, 1), sfft.dct(x, type=3), rtol=0, atol=1e-12 * n)
+    np.testing.assert_allclose(oracle.r2r1d(x, 2), sfft.dst(x, type=2), rtol=0, atol=1e-12 * n)
+    np.testing.assert_allclose(oracle.r2r1d(x, 3), sfft.dst(x, type=3), rtol=0, atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("n", [4, 7, 16])
+def test_r2r1d_closed_forms_and_inverses(n):
+    j = np.arange(n)
+    for p in range(n):
+        # a sampled Neumann mode maps to one spike (2n for the constant, n otherwise)
+        spike = np.zeros(n)
+        spike[p] = 2 * n if p == 0 else n
+        np.testing.assert_allclose(oracle.r2r1d(np.cos(np.pi * p * (j + 0.5) / n), 0), spike, atol=1e-12)
+        # a sampled Dirichlet mode sin((p+1) z) maps to one spike n (2n for the
+        # alternating top mode sin(n z), as the constant for the DCT)
+        spike = np.zeros(n)
+        spike[p] = 2 * n if p == n - 1 else n
+        np.testing.assert_allclose(oracle.r2r1d(np.sin(np.pi * (p + 1) * (j + 0.5) / n), 2), spike, atol=1e-12)
+    x = synth.real_normal((n,), 5)
+    np.testing.assert_allclose(oracle.r2r1d(oracle.r2r1d(x, 0), 1), 2 * n * x, atol=1e-12)
+    np.testing.assert_allclose(oracle.r2r1d(oracle.r2r1d(x, 2), 3), 2 * n * x, atol=1e-12)
+    # the type-III sums are the transposes of the type-II sums, up to the single
+    # weight-1 term (first input of DCT-III, last of DST-III): <A x, y> = <x, B(e y)>
+    y = synth.real_normal((n,), 6)
+    e = np.ones(n)
+    e[0] = 2.0
+    assert abs(np.dot(oracle.r2r1d(x, 0), y) - np.dot(x, oracle.r2r1d(y * e, 1))) < 1e-11 * n
+    e = np.ones(n)
+    e[-1] = 2.0
+    assert abs(np.dot(oracle.r2r1d(x, 2), y) - np.dot(x, oracle.r2r1d(y * e, 3))) < 1e-11 * n
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (6, 5, 10), (3, 4, 6)])
+@pytest.mark.parametrize("bc", [0, 1], ids=["neumann", "dirichlet"])
+def test_ppb_transforms_against_library_composition(shape, bc):
+    """(P, P, B) forward = numpy rfft along x, fft along y, scipy DCT-II / DST-II along z;
+    the inverse undoes it."""
+    import scipy.fft as sfft
+
+    nz, ny, nx = shape
+    f = synth.real_normal(shape, 90 + bc)
+    h = np.fft.fft(np.fft.rfft(f, axis=2), axis=1)
+    r2r = sfft.dct if bc == 0 else sfft.dst
+    want = r2r(h.real, type=2, axis=0) + 1j * r2r(h.imag, type=2, axis=0)
+    got = oracle.ppb_forward(f, bc)
+    assert oracle.rel_l2(got, want) < 1e-14
+    np.testing.assert_allclose(oracle.ppb_inverse(got, nx, bc), f, atol=1e-13)
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["neumann", "dirichlet"])
+def test_poisson_ppb_closed_form(bc):
+    """cos(a x + b y) cos(c z) (Neumann) or cos(a x + b y) sin(c z) (Dirichlet), with
+    x, y on 2 pi-periodic grids and z at the cell centres of (0, pi): phi = -f / (a^2+b^2+c^2)."""
+    shape = (12, 10, 16)
+    nz, ny, nx = shape
+    zc = np.pi * (np.arange(nz) + 0.5) / nz
+    z, y, x = np.meshgrid(zc, 2 * np.pi * np.arange(ny) / ny, 2 * np.pi * np.arange(nx) / nx, indexing="ij")
+    for a, b, c in ((1, 0, 0), (3, 2, 1), (0, 4, 5), (2, 1, 3)):
+        if bc == 1 and c == 0:
+            continue
+        f = np.cos(a * x + b * y) * (np.cos(c * z) if bc == 0 else np.sin(c * z))
+        np.testing.assert_allclose(oracle.poisson_ppb(f, bc), -f / (a * a + b * b + c * c), atol=1e-13)
+    if bc == 0:  # the constant (zero wavenumber) is dropped
+        np.testing.assert_allclose(oracle.poisson_ppb(np.full(shape, 2.0), 0), 0, atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["neumann", "dirichlet"])
+def test_poisson_ppb_self_adjoint_and_laplacian(bc):
+    """<P f, w> = <f, P w> (so the gradient of sum(P(f) w) is P(w)); and the spectral
+    Laplacian of phi, taken with library transforms, gives back f (minus its mean for Neumann)."""
+    import scipy.fft as sfft
+
+    shape = (8, 6, 10)
+    nz, ny, nx = shape
+    f, w = synth.real_normal(shape, 11), synth.real_normal(shape, 12)
+    lhs = np.sum(oracle.poisson_ppb(f, bc) * w)
+    rhs = np.sum(f * oracle.poisson_ppb(w, bc))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    phi = oracle.poisson_ppb(f, bc)
+    r2r = sfft.dct if bc == 0 else sfft.dst
+    kz = np.arange(nz) + (0 if bc == 0 else 1)
+    k2 = (kz[:, None, None] ** 2 + _wavenumbers(ny)[None, :, None] ** 2
+          + _wavenumbers(nx)[None, None, :] ** 2)
+    spec = np.fft.fft2(r2r(phi, type=2, axis=0), axes=(1, 2))
+    lap_spec = -k2 * spec
+    lap = np.fft.ifft2(lap_spec, axes=(1, 2))
+    lap = r2r(lap.real, type=3, axis=0) / (2 * nz)
+    want = f - f.mean() if bc == 0 else f
+    np.testing.assert_allclose(lap, want, atol=1e-12)
