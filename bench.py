@@ -146,9 +146,20 @@ def _extras(reps, torch, fft3d, synth, np):
         y = p.inverse(H)
         ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), reps, torch)
         bytes_moved = 2 * N * sr + 10 * nh * 2 * sr  # x stage real in/out, 5 half-spectrum passes each way
+        # per pass: the real x stages move N reals and nh complex values, the
+        # half-spectrum passes nh complex values in and out
+        fwd_st, inv_st = _stage_profile(p, x, H, y, max(3, min(reps, 10)), torch)
+        pass_bytes_x = N * sr + nh * 2 * sr
+        pass_bytes_c = 2 * nh * 2 * sr
+        passes = {}
+        for tag2, st in (("fwd", fwd_st), ("inv", inv_st)):
+            names = ("x", "y", "z") if tag2 == "fwd" else ("z", "y", "x")
+            for nm, t in zip(names, st):
+                b = pass_bytes_x if nm == "x" else pass_bytes_c
+                passes[f"{tag2}_{nm}"] = {"ms": round(t, 4), "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         rep[f"r2c_512cubed_fwd_inv_{tag}"] = {
             "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "passes": passes}
         Hh, yh = H.cpu().numpy(), y.cpu().numpy()
         checks.append((f"r2c_512cubed_{tag}_forward", Hh, lambda f=f: _oracle().rfftn(f.astype(np.float64))))
         checks.append((f"r2c_512cubed_{tag}_roundtrip", yh, lambda f=f: f.astype(np.float64)))
@@ -251,15 +262,34 @@ def _extras(reps, torch, fft3d, synth, np):
     if own_cache:
         os.environ["FFT3D_TUNE_CACHE"] = tune_path
     brep["launch_shapes"] = "autotuned"
-    for mode, name in ((3, "task_graph"), (0, "graph_4_streams"), (1, "direct_4_streams"),
-                       (2, "serial_one_stream")):
-        bp = fft3d.BatchPlan(shapes, mode=mode)
-        autotune.tune_batch(bp, reps=5)
-        with torch.cuda.stream(side):
-            ms = _time(lambda: bp.forward(xs, outs), reps, torch)
-        brep[name] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
-                      "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        bp.close()
+    bp = fft3d.BatchPlan(shapes)
+    autotune.tune_batch(bp, reps=5)
+    with torch.cuda.stream(side):
+        ms = _time(lambda: bp.forward(xs, outs), reps, torch)
+    brep["task_graph"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    bp.close()
+    # for comparison: the same transforms one after another, each through its own
+    # plan (same staging per shape, default launch shapes) on one stream
+    plans = {}
+    for sh in set(shapes):
+        pl = fft3d.Plan(sh, torch.complex64)
+        if sh in fused:
+            pl.set_staging(fft3d.STAGING_FUSED_XY)
+        else:
+            pl.set_staging(fft3d.STAGING_IN_PLACE)
+        plans[sh] = pl
+
+    def serial():
+        for sh, x_, o_ in zip(shapes, xs, outs):
+            plans[sh].forward(x_, out=o_)
+
+    with torch.cuda.stream(side):
+        ms = _time(serial, reps, torch)
+    brep["serial_one_stream"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+                                 "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for pl in plans.values():
+        pl.close()
     bp = fft3d.BatchPlan(shapes)
     autotune.tune_batch(bp, reps=5)
     with torch.cuda.stream(side):
@@ -284,8 +314,8 @@ def _extras(reps, torch, fft3d, synth, np):
     fd, wd = torch.from_numpy(f).cuda(), torch.from_numpy(w).cuda()
     p = fft3d.Plan(c5["shape"], torch.float32, r2c=True)
     phi = p.poisson(fd)
-    g = p.poisson_adjoint(wd)
-    ms = _time(lambda: (p.poisson(fd, out=phi), p.poisson_adjoint(wd, out=g)), reps, torch)
+    g = p.poisson_backward(wd)
+    ms = _time(lambda: (p.poisson(fd, out=phi), p.poisson_backward(wd, out=g)), reps, torch)
     m = int(np.prod(c5["shape"]))
     mh = (c5["shape"][2] // 2 + 1) * c5["shape"][0] * c5["shape"][1]
     pbytes = 2 * (2 * m * 4 + 8 * mh * 8)  # per solve: real in/out + 4 half-spectrum passes
@@ -295,6 +325,17 @@ def _extras(reps, torch, fft3d, synth, np):
     checks.append(("poisson_256cubed_gradient", g.cpu().numpy(), lambda: _oracle().poisson_grad(w.astype(np.float64))))
     p.close()
     return rep, checks
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _oracle():
@@ -459,6 +500,7 @@ def main():
         result["cpu_baseline"] = {
             "value": round(2 * flop_per_transform / t_cpu / 1e9, 3), "unit": "GFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
+            "host_cpus_available": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(),
             "sample": (f"FP64 forward + inverse of the same {n_edge}^3 field, median of {len(runs)} runs "
                        f"({t_cpu:.2f} s each, {sum(runs):.1f} s total)"),
             "rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in errs.items()},

@@ -19,8 +19,15 @@
  * `stream` argument is a hipStream_t (NULL: the default stream); all work is
  * enqueued after the work already on that stream and completes before work
  * enqueued on it later.  No call blocks the host on the GPU except
- * fft3d_plan and fft3d_destroy.  A plan may be used from one host thread at a
- * time and by one stream at a time (its workspace and events are shared).
+ * fft3d_plan, fft3d_destroy and the setters that free or rebuild plan memory.
+ * Calls on one plan are serialised on the host (a per-plan lock), and a call
+ * on a different stream than the plan's previous call first waits for that
+ * call's completion on the device (the plan's workspace is shared), so one
+ * plan may be used from several host threads and streams; its calls then run
+ * one after another.  A call into a stream that is being captured records its
+ * kernels in order on that stream (no internal streams, no waits on earlier
+ * calls): the caller orders replays of the captured graph against other uses
+ * of the plan.
  *
  * Errors: every call returns an fft3d_status.  Argument errors are detected
  * before any work is enqueued.  An asynchronous GPU fault surfaces as
@@ -71,8 +78,8 @@ typedef enum {
 fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype,
                         int p1, int p2, int r2c);
 
-/* Release everything the plan allocated (not caller buffers).  Synchronises
- * the plan's streams first.  NULL is accepted. */
+/* Release everything the plan allocated (not caller buffers), after waiting
+ * for the plan's last call to finish on the device.  NULL is accepted. */
 fft3d_status fft3d_destroy(fft3d_plan_t plan);
 
 /*
@@ -103,7 +110,8 @@ fft3d_status fft3d_inverse(fft3d_plan_t plan, const void* in, void* out, void* s
 fft3d_status fft3d_backward(fft3d_plan_t plan, const void* in, void* out, void* stream);
 
 /*
- * Spectral Poisson solve on a periodic box of side 2 pi (R2C plans only):
+ * Spectral Poisson solve on a periodic box of side 2 pi (R2C plans only; the
+ * paper's Poisson application, Sec. VI-B, (Periodic, Periodic, Periodic)):
  *   phi = irfftn( M .* rfftn(f) ),  M(k) = -1/|k|^2,  M(0) = 0,
  * with integer wavenumbers k_j = j for j <= n/2 and j - n otherwise.  The
  * z stage runs forward FFT, multiplier and inverse FFT in one kernel.  f and
@@ -113,11 +121,11 @@ fft3d_status fft3d_backward(fft3d_plan_t plan, const void* in, void* out, void* 
 fft3d_status fft3d_poisson(fft3d_plan_t plan, const void* f, void* phi, void* stream);
 
 /*
- * Adjoint of fft3d_poisson (gradient of sum(phi * g) with respect to f, given
- * g = gphi): the adjoint of every stage of the solve, applied in reverse
- * order.  Same buffer rules as fft3d_poisson.
+ * Backward of fft3d_poisson (its adjoint: the gradient of sum(phi * g) with
+ * respect to f, given g = gphi): the adjoint of every stage of the solve,
+ * applied in reverse order.  Same buffer rules as fft3d_poisson.
  */
-fft3d_status fft3d_poisson_adjoint(fft3d_plan_t plan, const void* gphi, void* gf, void* stream);
+fft3d_status fft3d_poisson_backward(fft3d_plan_t plan, const void* gphi, void* gf, void* stream);
 
 /* Bytes of the plan's workspace: R2C plans (Nx/2+1)*Ny*Nz complex values,
  * C2C plans Nx*Ny*Nz complex values with FFT3D_STAGING_SWAP_YZ, else 0. */
@@ -144,7 +152,9 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
  *   FFT3D_STAGING_FUSED_XY: one kernel loads each z-plane (Nx x Ny) into LDS
  *     and runs its x and y FFTs there, then the z stage works in place on
  *     `out`: two passes over memory instead of three, no workspace (the slab
- *     form of Sec. III-A: two local transforms, then the third).  Only for
+ *     form of Sec. III-A: two local transforms, then the third).  Its lines
+ *     run the same arithmetic as the x and y stages, so the forward is bitwise
+ *     equal to IN_PLACE.  Only for
  *     the planes with a compiled kernel that fit in 160 KiB of LDS (complex64:
  *     squares 8, 16, 24, 32, 48, 64, 96, 128 and 100 x 120, 80 x 160;
  *     complex128: the squares up to 96) and p1 == 1 (else
@@ -167,6 +177,10 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t plan, void* ws, size_t bytes);
 #define FFT3D_STAGING_FUSED_XY 2
 fft3d_status fft3d_set_staging(fft3d_plan_t plan, int staging);
 
+/* The plan's current staging (one of the FFT3D_STAGING_* values), or -1 for
+ * a NULL plan. */
+int fft3d_get_staging(fft3d_plan_t plan);
+
 /*
  * Number of internal HIP streams the tiles are placed on (1..16; default 4).
  * The streams are created by the first call that needs them.  With 1 stream,
@@ -184,27 +198,13 @@ fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
  * launches it on the caller's stream (the plan's streams and events are not
  * used; at most 8 graphs are cached, the oldest set is dropped when full).
  * Results are bitwise identical to direct issue.  A call on a stream the
- * caller is capturing is issued directly (into the caller's graph).  Cached
+ * caller is capturing issues its tiles in order on that stream.  Cached
  * graphs are dropped (after the device finishes them) by every setter that
  * changes launches.  Default: 1 for plans with at least 16 tiles per stage
  * (p1 * p2 >= 16), where the graph measured 10-22 % faster than direct issue
  * on MI355X; 0 below (fewer, larger tiles issue faster directly).
  */
 fft3d_status fft3d_set_graphs(fft3d_plan_t plan, int enable);
-
-/*
- * Row pitch, in complex elements, of the half-spectrum buffers an R2C plan
- * exchanges with the caller (the output of fft3d_forward, the input of
- * fft3d_inverse / fft3d_backward): element (kx, y, z) at kx + pitch*(y + Ny*z),
- * kx <= Nx/2; the buffer then holds pitch*Ny*Nz values, and the columns past
- * Nx/2 are neither written nor read.  0 (default) is the dense layout
- * (pitch Nx/2 + 1).  A pitch that is a multiple of 128 bytes (16 complex64,
- * 8 complex128 values) puts every row on cache-line bounds, so the strided
- * stages that touch the caller's buffer read and write whole lines.  Not a
- * C2C plan (FFT3D_ERR_WRONG_PLAN); 0 < pitch < Nx/2 + 1 -> FFT3D_ERR_INVALID_ARG.
- * Drops the plan's cached graphs.
- */
-fft3d_status fft3d_set_half_pitch(fft3d_plan_t plan, int64_t pitch);
 
 /*
  * Override the launch shape of the stage kernels along one axis (0 = x,
@@ -236,55 +236,45 @@ const char* fft3d_last_error(void);
 
 /* --------------------------------------------------------- batches
  * Many independent 3D transforms of (possibly) different sizes issued as one
- * task graph: every transform runs the stage kernels of its shape on one of
- * four internal streams, transforms placed in decreasing order of cost on the
- * least-loaded stream (Alg. 3 placement), so the stages of different
- * transforms overlap with no barrier between them (the paper's dynamically
- * scheduled FFT tasks, Sec. III-C and IV-D).  On a non-default stream the
- * whole batch (fork, per-stream launches, join) is captured into a hipGraph
- * on first use for each operation and pointer set, and replayed afterwards;
- * if the caller is capturing the stream, the launches join that capture. */
+ * task graph (the paper's dynamically scheduled FFT tasks over uneven work,
+ * Sec. III-C and IV-D): the stage kernels of every transform are appended,
+ * node by node, to one hipGraph per operation and pointer set, a chain of
+ * producer edges per transform and no edge between transforms, largest
+ * transform first (the order of Alg. 3's placement); the graph is built on
+ * first use and replayed afterwards (at most 8 cached), and the runtime
+ * overlaps the stages of different transforms.  A call into a stream the
+ * caller is capturing issues the transforms one after another on it. */
 typedef struct fft3d_batch_s* fft3d_batch_t;
 
 /* dims holds count triples (nx, ny, nz), each a shape fft3d_plan accepts;
- * dtype FFT3D_C64 or FFT3D_C128.  Creates one plan per distinct shape, the
- * streams and events. */
+ * dtype FFT3D_C64 or FFT3D_C128.  Creates one plan per distinct shape. */
 fft3d_status fft3d_plan_batch(fft3d_batch_t* plan, int count, const int64_t* dims, int dtype);
 
 /* Forward (sign -1, unscaled) / inverse (sign +1, 1/N per transform) of every
  * transform: in[f], out[f] are device pointers to Nx*Ny*Nz complex values (x
  * fastest); in[f] == out[f] is allowed, a partial overlap is FFT3D_ERR_ALIAS,
  * and so is any overlap between buffers of different transforms. */
-fft3d_status fft3d_batch_forward(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
-fft3d_status fft3d_batch_inverse(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
+fft3d_status fft3d_forward_batch(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
+fft3d_status fft3d_inverse_batch(fft3d_batch_t plan, const void* const* in, void* const* out, void* stream);
 
 /* Launch shape of one stage of the transforms of one shape (arguments as
- * fft3d_set_stage_config); drops the captured graphs.  Used by the
- * autotuner; results do not depend on it. */
+ * fft3d_set_stage_config); waits for the last call and drops the cached
+ * graphs.  Used by the autotuner; results do not depend on it. */
 fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
                                           int lw, int tdiv, int split, int pad);
 
 /* Staging of the transforms of one shape: FFT3D_STAGING_IN_PLACE or
- * FFT3D_STAGING_FUSED_XY (UNSUPPORTED_SIZE where no fused kernel fits that
- * plane); a workspace staging is FFT3D_ERR_INVALID_ARG, since transforms of
- * one shape share their plan across streams.  Drops the captured graphs;
- * results agree to rounding, not bit for bit, between stagings. */
+ * FFT3D_STAGING_FUSED_XY (the default where a fused kernel fits the plane;
+ * UNSUPPORTED_SIZE where none does); a workspace staging is
+ * FFT3D_ERR_INVALID_ARG, since transforms of one shape share their plan.
+ * Waits for the last call and drops the cached graphs; results are bitwise
+ * the same in both stagings. */
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int staging);
-
-/* 0: replay of the captured fork / internal streams / join sequence (on
- * non-default streams); 1: direct launches on the internal streams; 2: all
- * transforms one after another on the caller's stream (for comparison);
- * 3 (default): replay of one graph built node by node, every transform's
- * stage kernels as a chain of nodes and no edges between transforms (on any
- * stream the caller is not capturing; 2-3 % faster than mode 0 on the 64
- * uneven transforms).  A stream the caller is capturing takes direct
- * launches on the internal streams (modes 0, 1, 3).  Switching drops the
- * cached graphs (after the device finishes them). */
-fft3d_status fft3d_batch_set_mode(fft3d_batch_t plan, int mode);
 
 fft3d_status fft3d_batch_destroy(fft3d_batch_t plan);
 
-/* Host-only: placement of a batch on nstreams streams as int64 records
+/* Host-only: Alg. 3's placement of a batch on nstreams streams (the batch's
+ * issue order is the placement on one stream) as int64 records
  * [nstreams] then per stream [n, transform indices in issue order...].
  * Returns the number of values needed; writes them if cap is large enough;
  * -1 on invalid arguments. */

@@ -218,10 +218,13 @@ def dft3d_lines(a, kx, ky, sign: int = -1) -> np.ndarray:
         sx = flat.astype(np.complex128, copy=False) @ wx
     else:  # real field: two real products keep the temporaries real
         f64 = flat.astype(np.float64, copy=False)
-        sx = f64 @ wx.real + 1j * (f64 @ wx.imag)
-    sx = sx.reshape(nz, ny, len(ux))[:, :, inv_x]      # (nz, ny, npairs)
+        sx = f64 @ np.ascontiguousarray(wx.real) + 1j * (f64 @ np.ascontiguousarray(wx.imag))
+    sx = sx.reshape(nz, ny, len(ux))
     wy = roots(ky, ny)                                  # (ny, npairs)
-    sxy = np.einsum("zyp,yp->zp", sx, wy)              # (nz, npairs)
+    sxy = np.empty((nz, kx.size), dtype=np.complex128)
+    for i in range(len(ux)):                            # the y sums of the pairs with this kx
+        sel = np.nonzero(inv_x == i)[0]
+        sxy[:, sel] = sx[:, :, i] @ wy[:, sel]
     wz = roots(np.arange(nz, dtype=np.int64), nz)       # (nz, nz), symmetric
     return wz @ sxy
 

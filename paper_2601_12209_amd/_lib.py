@@ -22,22 +22,21 @@ _SIGS = {
     "fft3d_inverse": (I32, [P, P, P, P]),
     "fft3d_backward": (I32, [P, P, P, P]),
     "fft3d_poisson": (I32, [P, P, P, P]),
-    "fft3d_poisson_adjoint": (I32, [P, P, P, P]),
+    "fft3d_poisson_backward": (I32, [P, P, P, P]),
     "fft3d_workspace_bytes": (SZ, [P]),
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
     "fft3d_set_staging": (I32, [P, I32]),
     "fft3d_set_graphs": (I32, [P, I32]),
-    "fft3d_set_half_pitch": (I32, [P, I64]),
+    "fft3d_get_staging": (I32, [P]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
     "fft3d_set_timing": (I32, [P, I32]),
     "fft3d_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), I32]),
     "fft3d_plan_batch": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64), I32]),
-    "fft3d_batch_forward": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
-    "fft3d_batch_inverse": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
+    "fft3d_forward_batch": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
+    "fft3d_inverse_batch": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
     "fft3d_batch_set_stage_config": (I32, [P, I64, I64, I64, I32, I32, I32, I32, I32]),
     "fft3d_batch_set_staging": (I32, [P, I64, I64, I64, I32]),
-    "fft3d_batch_set_mode": (I32, [P, I32]),
     "fft3d_batch_destroy": (I32, [P]),
     "fft3d_query_batch_placement": (I64, [I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I64), I64]),
     "fft3d_status_string": (ctypes.c_char_p, [I32]),

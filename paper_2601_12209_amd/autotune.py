@@ -52,7 +52,7 @@ def _arch() -> str:
 def _stage_key(plan: fft3d.Plan, axis: int, nstages: int = 3) -> str:
     nz, ny, nx = plan.shape
     n = (nx, ny, nz)[axis]
-    nxc = (plan.half_pitch or nx // 2 + 1) if plan.r2c else nx
+    nxc = nx // 2 + 1 if plan.r2c else nx
     stride = (1, nxc, nxc * ny)[axis]
     kind = "r2c" if (plan.r2c and axis == 0) else "c2c"
     return (f"{_arch()}|{'c64' if plan.code == fft3d.C64 else 'c128'}|{kind}|n{n}|axis{axis}|stride{stride}"

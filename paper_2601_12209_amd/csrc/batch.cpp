@@ -1,14 +1,12 @@
 // C ABI of batched transforms: many independent, unevenly sized 3D FFTs
-// issued as one task graph.  Every transform runs its x, y, z stage kernels
-// (the single-transform plan of its shape) on one of several internal
-// streams; transforms are placed on the least-loaded stream in decreasing
-// order of cost (the paper's Alg. 3 placement), so the GPU's hardware queues
-// overlap the stages of different transforms with no barrier between them.
-// By default the transforms' stage kernels are appended node by node to one
-// hipGraph per operation and pointer set (a chain per transform, no edges
-// between transforms), which is replayed; the older mode captures the fork /
-// per-stream work / join sequence instead (measured 2-3 % slower on the 64
-// uneven transforms).
+// issued as one task graph.  Every transform runs the x, y, z stage kernels of
+// the single-transform plan of its shape; the transforms' stage kernels are
+// appended node by node to one hipGraph per operation and pointer set (a chain
+// of producer edges per transform, no edges between transforms), which is
+// replayed, so the runtime overlaps the stages of different transforms with
+// no barrier between them (the paper's dynamically scheduled FFT tasks,
+// Sec. III-C and IV-D).  Transforms are appended largest first (the order of
+// the paper's Alg. 3 placement).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -38,7 +36,6 @@ using namespace fft3d;
 
 namespace {
 
-constexpr int kBatchStreams = 4;
 constexpr size_t kMaxGraphs = 8;
 
 using Shape = std::tuple<int64_t, int64_t, int64_t>;
@@ -57,12 +54,8 @@ struct fft3d_batch_s {
     std::vector<PlanDesc> ffts;
     int dtype = 0;
     int device = 0;
-    int mode = 3;  // fft3d_batch_set_mode
     std::map<Shape, fft3d_plan_t> plans;  // one single-stream plan per distinct shape
-    std::vector<std::vector<int>> placement;
-    std::vector<hipStream_t> streams;
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> joins;
+    std::vector<int> order;               // transforms in decreasing cost (issue order)
     std::vector<CachedGraph> graphs;
     hipEvent_t done = nullptr;  // recorded on the caller's stream after each call
 };
@@ -71,8 +64,15 @@ namespace {
 
 Shape shape_of(const PlanDesc& d) { return Shape(d.nx, d.ny, d.nz); }
 
+// Wait for the work of the last call (the caller's stream itself may be gone).
+void wait_done(fft3d_batch_s* b)
+{
+    if (b->done) hipEventSynchronize(b->done);
+}
+
 void drop_graphs(fft3d_batch_s* b)
 {
+    wait_done(b);
     for (auto& g : b->graphs) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         if (g.graph) hipGraphDestroy(g.graph);
@@ -80,16 +80,10 @@ void drop_graphs(fft3d_batch_s* b)
     b->graphs.clear();
 }
 
-// Wait for the work of the last call (the caller's stream itself may be gone).
-void wait_done(fft3d_batch_s* b)
-{
-    if (b->done) hipEventSynchronize(b->done);
-}
-
 // After a call issued on `s` (not into a capture): mark its end.
-fft3d_status finish(fft3d_batch_s* b, hipStream_t s, hipStreamCaptureStatus cap, fft3d_status st)
+fft3d_status finish(fft3d_batch_s* b, hipStream_t s, bool capturing, fft3d_status st)
 {
-    if (st != FFT3D_OK || cap != hipStreamCaptureStatusNone) return st;
+    if (st != FFT3D_OK || capturing) return st;
     hipError_t e = hipSuccess;
     if (!b->done) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -102,16 +96,7 @@ fft3d_status finish(fft3d_batch_s* b, hipStream_t s, hipStreamCaptureStatus cap,
 
 void release(fft3d_batch_s* b)
 {
-    wait_done(b);
-    for (hipStream_t s : b->streams)
-        if (s) {
-            hipStreamSynchronize(s);
-            hipStreamDestroy(s);
-        }
     drop_graphs(b);
-    for (hipEvent_t e : b->joins)
-        if (e) hipEventDestroy(e);
-    if (b->fork) hipEventDestroy(b->fork);
     if (b->done) hipEventDestroy(b->done);
     for (auto& kv : b->plans) fft3d_destroy(kv.second);
     delete b;
@@ -124,40 +109,6 @@ bool overlap(const void* a, size_t na, const void* c, size_t nc)
     return pa < pc + nc && pc < pa + na;
 }
 
-fft3d_status run_one(fft3d_batch_s* b, int op, int f, const void* in, void* out, hipStream_t s)
-{
-    fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
-    return op == 0 ? fft3d_forward(p, in, out, s) : fft3d_inverse(p, in, out, s);
-}
-
-// Enqueue the whole batch on `s`: fork, per-stream transforms, join.
-fft3d_status issue(fft3d_batch_s* b, int op, const void* const* in, void* const* out, hipStream_t s)
-{
-    if (b->mode == 2) {  // one stream, transforms one after another
-        for (const auto& per : b->placement)
-            for (int f : per) {
-                fft3d_status st = run_one(b, op, f, in[f], out[f], s);
-                if (st != FFT3D_OK) return st;
-            }
-        return FFT3D_OK;
-    }
-    hipError_t e = hipEventRecord(b->fork, s);
-    if (e != hipSuccess) return set_hip_error(e, "hipEventRecord(fork)");
-    for (size_t k = 0; k < b->placement.size(); ++k) {
-        if (b->placement[k].empty()) continue;
-        e = hipStreamWaitEvent(b->streams[k], b->fork, 0);
-        if (e != hipSuccess) return set_hip_error(e, "hipStreamWaitEvent(fork)");
-        for (int f : b->placement[k]) {
-            fft3d_status st = run_one(b, op, f, in[f], out[f], b->streams[k]);
-            if (st != FFT3D_OK) return st;
-        }
-        e = hipEventRecord(b->joins[k], b->streams[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[k], 0);
-        if (e != hipSuccess) return set_hip_error(e, "batch join");
-    }
-    return FFT3D_OK;
-}
-
 fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* const* out, void* stream)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
@@ -168,6 +119,8 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
     for (int f = 0; f < count; ++f) {
         if (!in[f] || !out[f]) return set_error(FFT3D_ERR_INVALID_ARG, "null buffer");
         bytes[f] = (size_t)b->ffts[f].nx * b->ffts[f].ny * b->ffts[f].nz * es;
+        if (in[f] != out[f] && overlap(in[f], bytes[f], out[f], bytes[f]))
+            return set_error(FFT3D_ERR_ALIAS, "in and out of one transform partially overlap");
     }
     for (int f = 0; f < count; ++f)
         for (int g = 0; g < count; ++g)
@@ -177,15 +130,20 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
     if (e != hipSuccess) return set_hip_error(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (s != nullptr) {
+    if (s != nullptr) {  // the legacy default stream cannot be captured
         e = hipStreamIsCapturing(s, &cap);
         if (e != hipSuccess) return set_hip_error(e, "hipStreamIsCapturing");
     }
-    // the legacy default stream cannot be captured; a stream the caller is
-    // capturing records our launches into the caller's graph
-    const bool dag = b->mode == 3 && cap == hipStreamCaptureStatusNone;
-    if (!dag && (b->mode != 0 || s == nullptr || cap != hipStreamCaptureStatusNone))
-        return finish(b, s, cap, issue(b, op, in, out, s));
+    if (cap != hipStreamCaptureStatusNone) {
+        // a stream the caller is capturing: every transform in order on it
+        // (each plan issues its stages in order on a capturing stream)
+        for (int f : b->order) {
+            fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
+            fft3d_status st = op == 0 ? fft3d_forward(p, in[f], out[f], s) : fft3d_inverse(p, in[f], out[f], s);
+            if (st != FFT3D_OK) return st;
+        }
+        return FFT3D_OK;
+    }
     CachedGraph* hit = nullptr;
     for (auto& g : b->graphs) {
         if (g.op != op) continue;
@@ -197,51 +155,21 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         }
     }
     if (!hit) {
-        if (b->graphs.size() >= kMaxGraphs) {
-            hipStreamSynchronize(s);
-            drop_graphs(b);
-        }
+        if (b->graphs.size() >= kMaxGraphs) drop_graphs(b);
         CachedGraph g;
         g.op = op;
         g.in.assign(in, in + count);
         g.out.assign(out, out + count);
-        if (dag) {
-            // every transform's stage nodes appended to one graph, no edges
-            // between transforms (largest first, as placed)
-            e = hipGraphCreate(&g.graph, 0);
-            if (e != hipSuccess) return set_hip_error(e, "hipGraphCreate");
-            for (const auto& per : b->placement)
-                for (int f : per) {
-                    fft3d_status st = append_plan_nodes(b->plans[shape_of(b->ffts[f])], op == 0 ? OP_FORWARD : OP_INVERSE,
-                                                        in[f], out[f], g.graph, {}, nullptr);
-                    if (st != FFT3D_OK) {
-                        hipGraphDestroy(g.graph);
-                        return st;
-                    }
-                }
-            e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
+        e = hipGraphCreate(&g.graph, 0);
+        if (e != hipSuccess) return set_hip_error(e, "hipGraphCreate");
+        for (int f : b->order) {
+            fft3d_status st = append_plan_nodes(b->plans[shape_of(b->ffts[f])], op == 0 ? OP_FORWARD : OP_INVERSE,
+                                                in[f], out[f], g.graph, {}, nullptr);
+            if (st != FFT3D_OK) {
                 hipGraphDestroy(g.graph);
-                return set_hip_error(e, "hipGraphInstantiate");
+                return st;
             }
-            b->graphs.push_back(g);
-            hit = &b->graphs.back();
         }
-    }
-    if (!hit) {
-        CachedGraph g;
-        g.op = op;
-        g.in.assign(in, in + count);
-        g.out.assign(out, out + count);
-        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return set_hip_error(e, "hipStreamBeginCapture");
-        fft3d_status st = issue(b, op, in, out, s);
-        e = hipStreamEndCapture(s, &g.graph);
-        if (st != FFT3D_OK) {
-            if (g.graph) hipGraphDestroy(g.graph);
-            return st;
-        }
-        if (e != hipSuccess) return set_hip_error(e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             hipGraphDestroy(g.graph);
@@ -251,7 +179,7 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         hit = &b->graphs.back();
     }
     e = hipGraphLaunch(hit->exec, s);
-    return finish(b, s, cap, e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch"));
+    return finish(b, s, false, e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch"));
 }
 
 std::vector<double> batch_costs(const std::vector<PlanDesc>& ffts)
@@ -286,8 +214,8 @@ fft3d_status fft3d_plan_batch(fft3d_batch_t* out, int count, const int64_t* dims
         fft3d_plan_t p = nullptr;
         fft3d_status st = fft3d_plan(&p, d.nx, d.ny, d.nz, dtype, 1, 1, 0);
         if (st == FFT3D_OK) st = fft3d_set_streams(p, 1);
-        // transforms of one shape share the plan across streams: no workspace
-        // (fused x-y planes where the plane fits in LDS, else in place)
+        // transforms of one shape share the plan: no workspace (fused x-y
+        // planes where the plane fits in LDS, else in place)
         if (st == FFT3D_OK && fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) != FFT3D_OK)
             st = fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE);
         if (st != FFT3D_OK) {
@@ -302,33 +230,17 @@ fft3d_status fft3d_plan_batch(fft3d_batch_t* out, int count, const int64_t* dims
         release(b);
         return set_hip_error(e, "hipGetDevice");
     }
-    const int ns = std::min(kBatchStreams, count);
-    b->placement = place_batch(batch_costs(b->ffts), ns);
-    b->streams.assign(ns, nullptr);
-    b->joins.assign(ns, nullptr);
-    for (int k = 0; k < ns; ++k) {
-        e = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            release(b);
-            return set_hip_error(e, "batch stream creation");
-        }
-    }
-    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        release(b);
-        return set_hip_error(e, "hipEventCreate");
-    }
+    b->order = place_batch(batch_costs(b->ffts), 1)[0];
     *out = b;
     return FFT3D_OK;
 }
 
-fft3d_status fft3d_batch_forward(fft3d_batch_t b, const void* const* in, void* const* out, void* stream)
+fft3d_status fft3d_forward_batch(fft3d_batch_t b, const void* const* in, void* const* out, void* stream)
 {
     return run_batch(b, 0, in, out, stream);
 }
 
-fft3d_status fft3d_batch_inverse(fft3d_batch_t b, const void* const* in, void* const* out, void* stream)
+fft3d_status fft3d_inverse_batch(fft3d_batch_t b, const void* const* in, void* const* out, void* stream)
 {
     return run_batch(b, 1, in, out, stream);
 }
@@ -339,8 +251,7 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
-    wait_done(b);
-    drop_graphs(b);  // launch shapes are baked into the captured graphs
+    drop_graphs(b);  // launch shapes are baked into the graphs
     return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
 }
 
@@ -351,19 +262,8 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     if (staging != FFT3D_STAGING_IN_PLACE && staging != FFT3D_STAGING_FUSED_XY)
         return set_error(FFT3D_ERR_INVALID_ARG, "a batch stages in place or in fused x-y planes (no workspace)");
-    wait_done(b);
-    drop_graphs(b);  // the stage lists are baked into the captured graphs
+    drop_graphs(b);  // the stage lists are baked into the graphs
     return fft3d_set_staging(it->second, staging);
-}
-
-fft3d_status fft3d_batch_set_mode(fft3d_batch_t b, int mode)
-{
-    if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
-    if (mode < 0 || mode > 3) return set_error(FFT3D_ERR_INVALID_ARG, "mode must be 0, 1, 2 or 3");
-    wait_done(b);
-    drop_graphs(b);  // graphs of one mode are not replayed in another
-    b->mode = mode;
-    return FFT3D_OK;
 }
 
 fft3d_status fft3d_batch_destroy(fft3d_batch_t b)

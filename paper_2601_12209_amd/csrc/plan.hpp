@@ -39,10 +39,7 @@ struct PlanDesc {
     int p1, p2;
     int r2c;
     int staging = STAGING_IN_PLACE;  // R2C: IN_PLACE or SWAP_YZ (forward only)
-    int64_t hpitch = 0;  // R2C: row pitch of the caller's half-spectrum buffers (0: dense)
-    int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent
-    // row pitch (complex elements) of the caller's complex buffers
-    int64_t upitch() const { return r2c && hpitch > 0 ? hpitch : nxc(); }
+    int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent (row pitch of caller buffers)
     // row pitch (complex elements) of the workspace: the complex x extent
     // rounded up to 128 bytes, so workspace rows start on cache-line bounds
     int64_t wpitch() const

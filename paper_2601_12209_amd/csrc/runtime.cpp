@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,9 @@ fft3d_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr int kMaxStreams = 16;
+// Tiles per stage a plan may have: the planner's dependency search is
+// quadratic in it and a plan creates five events per tile.
+constexpr int64_t kMaxTiles = 1024;
 constexpr size_t kMaxGraphs = 8;  // cached pipeline graphs per plan
 // Plans with at least this many tiles per stage replay their task graphs by
 // default.  Measured on MI355X, fwd+inv complex64: 256^3 on 4x4 tiles 0.83 ms
@@ -136,7 +140,14 @@ struct fft3d_plan_s {
     };
     bool use_graphs = false;  // multi-tile calls replay an explicit task graph (fft3d_set_graphs)
     std::vector<CachedGraph> graphs;
-    hipEvent_t graph_done = nullptr;  // recorded after every graph launch
+    // Completion of the last call issued outside a stream capture, recorded on
+    // that call's stream.  A call on another stream first waits on it, so two
+    // streams never use the plan's workspace at once; the destructor and the
+    // setters wait on it before they free or rebuild anything.
+    hipEvent_t call_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool called = false;
+    std::mutex mu;  // one host thread at a time inside a call or setter
     // per-stage timing (tracing): events around every stage of the last call
     bool timing = false;
     std::vector<hipEvent_t> tev;  // 6 timing events (up to 5 stages)
@@ -244,7 +255,7 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
 
 // Row pitch (complex elements) of a complex buffer: the workspace rows are
 // padded to 128 bytes, caller buffers are dense.
-int64_t row_pitch(const PlanDesc& d, int buf) { return buf == BUF_WS ? d.wpitch() : d.upitch(); }
+int64_t row_pitch(const PlanDesc& d, int buf) { return buf == BUF_WS ? d.wpitch() : d.nxc(); }
 
 // Element strides (x, y, z) of a complex buffer in a layout.
 void layout_strides(const PlanDesc& d, int buf, int lay, int64_t st[3])
@@ -393,6 +404,7 @@ fft3d_status validate_desc(const PlanDesc& d)
     }
     if (d.p1 < 1 || d.p2 < 1 || d.p1 > std::min(d.ny, d.nxc()) || d.p2 > std::min(d.nz, d.ny))
         return fail(FFT3D_ERR_INVALID_ARG, "pencil grid must satisfy 1<=p1<=min(ny,nxc), 1<=p2<=min(nz,ny)");
+    if ((int64_t)d.p1 * d.p2 > kMaxTiles) return fail(FFT3D_ERR_INVALID_ARG, "at most 1024 tiles per stage (p1*p2)");
     return FFT3D_OK;
 }
 
@@ -484,12 +496,12 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
     return FFT3D_OK;
 }
 
-// Destroy the cached graphs (after the last replay has finished).
+// Wait until the last call has finished (its work may still use the
+// workspace or replay a graph), then destroy the cached graphs.
 void drop_graphs(fft3d_plan_s* p)
 {
-    if (p->graphs.empty()) return;
     // the caller's stream may be gone by now; the plan's own event is not
-    if (p->graph_done) hipEventSynchronize(p->graph_done);
+    if (p->called) hipEventSynchronize(p->call_done);
     for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
     p->graphs.clear();
 }
@@ -589,44 +601,59 @@ fft3d_status run_graph(fft3d_plan_s* p, int op, const Pipeline& pl, void* const 
         p->graphs.push_back({op, bufs[0], bufs[1], bufs[2], exec});
         hit = &p->graphs.back();
     }
-    hipError_t e = hipSuccess;
-    if (!p->graph_done) e = hipEventCreateWithFlags(&p->graph_done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        p->graph_done = nullptr;
-        return hip_fail(e, "hipEventCreate");
-    }
-    e = hipGraphLaunch(hit->exec, user);
-    if (e == hipSuccess) e = hipEventRecord(p->graph_done, user);
+    hipError_t e = hipGraphLaunch(hit->exec, user);
     return e == hipSuccess ? FFT3D_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+fft3d_status issue(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user,
+                   bool capturing)
+{
+    if (p->timing && !capturing) return run_timed(p, pl, bufs, user);
+    if (p->use_graphs && (int64_t)p->d.p1 * p->d.p2 > 1 && !capturing) return run_graph(p, op, pl, bufs, user);
+    // In order on the caller's stream: plans with one stream or one tile per
+    // stage, and every call into a stream the caller is capturing (forking
+    // onto the plan's streams there would put cross-stream event edges into
+    // the caller's graph; the tile order is a topological order of the task
+    // graph, so the captured sequence is correct as it stands).
+    if (!forks(p) || capturing) {
+        for (const Task& t : pl.tasks) {
+            const Stage& st = pl.stages[t.stage];
+            hipError_t e = launch_task(p, st, make_args(p, st, t.box, bufs), user);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+        return FFT3D_OK;
+    }
+    return issue_forked(p, op, pl, bufs, user);
 }
 
 fft3d_status run(fft3d_plan_s* p, int op, const void* in, void* out, void* stream)
 {
+    std::lock_guard<std::mutex> lock(p->mu);
     const Pipeline& pl = get_pipeline(p, op);
     if (pl.stages.empty()) return fail(FFT3D_ERR_WRONG_PLAN, "operation not available for this plan kind");
     hipStream_t user = (hipStream_t)stream;
     void* bufs[3] = {const_cast<void*>(in), out, p->ws};
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if (p->timing) return run_timed(p, pl, bufs, user);
-    if (p->use_graphs && (int64_t)p->d.p1 * p->d.p2 > 1) {
-        // a stream the caller is capturing takes the launches into the caller's graph
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (user) {
-            e = hipStreamIsCapturing(user, &cap);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
-        }
-        if (cap == hipStreamCaptureStatusNone) return run_graph(p, op, pl, bufs, user);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (user) {  // the legacy default stream cannot be captured
+        e = hipStreamIsCapturing(user, &cap);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     }
-    if (!forks(p)) {
-        for (const Task& t : pl.tasks) {
-            const Stage& st = pl.stages[t.stage];
-            e = launch_task(p, st, make_args(p, st, t.box, bufs), user);
-            if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        }
-        return FFT3D_OK;
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    // the previous call on another stream may still use the workspace
+    if (!capturing && p->called && p->last_stream != user) {
+        e = hipStreamWaitEvent(user, p->call_done, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(previous call)");
     }
-    return issue_forked(p, op, pl, bufs, user);
+    if (capturing) p->timed_stages = 0;  // no timing events inside a capture
+    fft3d_status st = issue(p, op, pl, bufs, user, capturing);
+    if (st != FFT3D_OK || capturing) return st;
+    e = hipEventRecord(p->call_done, user);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(call)");
+    p->last_stream = user;
+    p->called = true;
+    return FFT3D_OK;
 }
 
 // Fork onto the plan's streams, one event edge per cross-stream dependency,
@@ -669,6 +696,7 @@ fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* con
 
 void release(fft3d_plan_s* p)
 {
+    if (p->called) hipEventSynchronize(p->call_done);  // work still reading or writing plan memory
     drop_graphs(p);
     for (hipStream_t s : p->streams)
         if (s) {
@@ -680,7 +708,7 @@ void release(fft3d_plan_s* p)
     for (hipEvent_t ev : p->tev)
         if (ev) hipEventDestroy(ev);
     if (p->fork) hipEventDestroy(p->fork);
-    if (p->graph_done) hipEventDestroy(p->graph_done);
+    if (p->call_done) hipEventDestroy(p->call_done);
     for (void* t : p->tw)
         if (t) hipFree(t);
     for (void* t : p->twp)
@@ -799,8 +827,8 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         }
     }
     e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->call_done, hipEventDisableTiming);
     if (e != hipSuccess) {
-        p->fork = nullptr;
         release(p);
         return hip_fail(e, "hipEventCreate");
     }
@@ -828,7 +856,7 @@ static fft3d_status c2c_or_r2c(fft3d_plan_t p, int op, const void* in, void* out
             (ranges_overlap(p->ws, p->ws_bytes, in, n * s) || ranges_overlap(p->ws, p->ws_bytes, out, n * s)))
             return fail(FFT3D_ERR_ALIAS, "workspace overlaps a buffer");
     } else {
-        const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.upitch() * d.ny * d.nz * s;
+        const size_t real_bytes = n * s / 2, half_bytes = (size_t)d.nxc() * d.ny * d.nz * s;
         const size_t in_bytes = op == OP_FORWARD ? real_bytes : half_bytes;
         const size_t out_bytes = op == OP_FORWARD ? half_bytes : real_bytes;
         if (ranges_overlap(in, in_bytes, out, out_bytes))
@@ -872,9 +900,19 @@ fft3d_status fft3d_poisson(fft3d_plan_t p, const void* f, void* phi, void* strea
     return poisson_op(p, OP_POISSON, f, phi, stream);
 }
 
-fft3d_status fft3d_poisson_adjoint(fft3d_plan_t p, const void* gphi, void* gf, void* stream)
+fft3d_status fft3d_poisson_backward(fft3d_plan_t p, const void* gphi, void* gf, void* stream)
 {
     return poisson_op(p, OP_POISSON_ADJ, gphi, gf, stream);
+}
+
+int fft3d_get_staging(fft3d_plan_t p)
+{
+    if (!p) {
+        fail(FFT3D_ERR_INVALID_ARG, "null plan");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    return p->d.staging;
 }
 
 size_t fft3d_workspace_bytes(fft3d_plan_t p)
@@ -887,6 +925,7 @@ size_t fft3d_workspace_bytes(fft3d_plan_t p)
 fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     if (!p->d.r2c && p->d.staging != STAGING_SWAP_YZ)
         return ws ? fail(FFT3D_ERR_WRONG_PLAN, "in-place C2C staging uses no workspace") : FFT3D_OK;
     const size_t need = fft3d_workspace_bytes(p);
@@ -894,8 +933,6 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
     if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     // the old workspace may still be in use by enqueued work
     drop_graphs(p);
-    for (hipStream_t s : p->streams)
-        if (s) hipStreamSynchronize(s);
     if (ws) {
         if (p->ws_owned) hipFree(p->ws);
         p->ws = ws;
@@ -916,6 +953,7 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
 fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     if (staging != STAGING_IN_PLACE && staging != STAGING_SWAP_YZ && staging != STAGING_FUSED_XY)
         return fail(FFT3D_ERR_INVALID_ARG, "staging must be 0 (in place), 1 (swap y/z) or 2 (fused x-y planes)");
     if (p->d.r2c) {
@@ -930,8 +968,7 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     if (staging == STAGING_FUSED_XY && (p->d.p1 != 1 || !plane_available(p->d.nx, p->d.ny, elem_bytes(p->d.dtype))))
         return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "no fused x-y kernel for this plane (or p1 > 1)");
     if (staging == p->d.staging) return FFT3D_OK;
-    drop_graphs(p);
-    // enqueued work may still use the old workspace (hipFree waits for the device)
+    drop_graphs(p);  // waits for the last call, which may still use the old workspace
     if (p->ws && p->ws_owned) hipFree(p->ws);
     p->ws = nullptr;
     p->ws_owned = false;
@@ -952,19 +989,10 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     return FFT3D_OK;
 }
 
-fft3d_status fft3d_set_half_pitch(fft3d_plan_t p, int64_t pitch)
-{
-    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    if (!p->d.r2c) return fail(FFT3D_ERR_WRONG_PLAN, "the half-spectrum pitch is for R2C plans");
-    if (pitch != 0 && pitch < p->d.nxc()) return fail(FFT3D_ERR_INVALID_ARG, "pitch must be 0 or >= nx/2 + 1");
-    drop_graphs(p);  // their launches hold the old addressing
-    p->d.hpitch = pitch;
-    return FFT3D_OK;
-}
-
 fft3d_status fft3d_set_graphs(fft3d_plan_t p, int enable)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     drop_graphs(p);
     p->use_graphs = enable != 0;
     return FFT3D_OK;
@@ -973,6 +1001,7 @@ fft3d_status fft3d_set_graphs(fft3d_plan_t p, int enable)
 fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     if (nstreams < 1 || nstreams > kMaxStreams) return fail(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
     drop_graphs(p);
     p->nstreams = nstreams;
@@ -986,6 +1015,7 @@ fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
 fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, int split, int pad)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
     if (lw == 0) {
         drop_graphs(p);
@@ -1015,6 +1045,7 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
 fft3d_status fft3d_set_timing(fft3d_plan_t p, int enable)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
     if (enable && p->tev.empty()) {
         p->tev.assign(6, nullptr);
         for (auto& ev : p->tev) {
@@ -1032,7 +1063,12 @@ fft3d_status fft3d_set_timing(fft3d_plan_t p, int enable)
 
 int fft3d_stage_times(fft3d_plan_t p, float* ms, int cap)
 {
-    if (!p || !ms || p->timed_stages == 0) {
+    if (!p || !ms) {
+        fail(FFT3D_ERR_INVALID_ARG, "null plan or output");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->timed_stages == 0) {
         fail(FFT3D_ERR_INVALID_ARG, "no timed call recorded");
         return -1;
     }

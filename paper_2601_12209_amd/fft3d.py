@@ -49,8 +49,7 @@ STAGING_FUSED_XY = 2
 class Plan:
     """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind."""
 
-    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None,
-                 half_pitch=None):
+    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None):
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
         self.code = _dtype_code(dtype)
@@ -62,9 +61,6 @@ class Plan:
         self._h = h
         self.device = torch.cuda.current_device()
         self._ws = None
-        self.half_pitch = 0
-        if half_pitch is not None:
-            self.set_half_pitch(half_pitch)
         if streams is not None:
             self.set_streams(streams)
         if staging is not None:
@@ -85,15 +81,14 @@ class Plan:
 
     @property
     def half_shape(self):
-        """Shape of the half-spectrum tensors this plan exchanges: (nz, ny, nx//2 + 1),
-        or (nz, ny, half_pitch) with a padded layout (only [..., :nx//2 + 1] is used)."""
+        """Shape of the half-spectrum tensors this plan exchanges: (nz, ny, nx//2 + 1)."""
         nz, ny, nx = self.shape
-        return (nz, ny, self.half_pitch or nx // 2 + 1)
+        return (nz, ny, nx // 2 + 1)
 
-    def set_half_pitch(self, pitch: int):
-        """R2C plans: row pitch of the half-spectrum tensors (0: dense nx//2 + 1)."""
-        check(_lib.lib().fft3d_set_half_pitch(self._h, int(pitch)), "fft3d_set_half_pitch")
-        self.half_pitch = int(pitch)
+    @property
+    def staging(self) -> int:
+        """The plan's current staging (STAGING_IN_PLACE, STAGING_SWAP_YZ or STAGING_FUSED_XY)."""
+        return int(_lib.lib().fft3d_get_staging(self._h))
 
     def _check_tensor(self, t, dtype, shape, name):
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -147,9 +142,9 @@ class Plan:
         return self._call(_lib.lib().fft3d_poisson, f, out, self.real_dtype, self.shape,
                           self.real_dtype, self.shape, stream)
 
-    def poisson_adjoint(self, g, out=None, stream=None):
-        """Adjoint of :meth:`poisson` applied to g."""
-        return self._call(_lib.lib().fft3d_poisson_adjoint, g, out, self.real_dtype, self.shape,
+    def poisson_backward(self, g, out=None, stream=None):
+        """Backward (adjoint) of :meth:`poisson` applied to g."""
+        return self._call(_lib.lib().fft3d_poisson_backward, g, out, self.real_dtype, self.shape,
                           self.real_dtype, self.shape, stream)
 
     # ------------------------------------------------------------ tuning
@@ -211,9 +206,10 @@ class Plan:
 
 
 class BatchPlan:
-    """Many 3D FFTs of different shapes issued as one task graph."""
+    """Many 3D FFTs of different shapes issued as one task graph (one hipGraph
+    of every transform's stage kernels, replayed)."""
 
-    def __init__(self, shapes, dtype=torch.complex64, mode=3):
+    def __init__(self, shapes, dtype=torch.complex64):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.code = _dtype_code(dtype)
         dims = (ctypes.c_int64 * (3 * len(self.shapes)))()
@@ -223,10 +219,6 @@ class BatchPlan:
         check(_lib.lib().fft3d_plan_batch(ctypes.byref(h), len(self.shapes), dims, self.code),
               "fft3d_plan_batch")
         self._h = h
-        self.set_mode(mode)
-
-    def set_mode(self, mode: int):
-        check(_lib.lib().fft3d_batch_set_mode(self._h, int(mode)), "fft3d_batch_set_mode")
 
     def set_stage_config(self, shape, axis: int, lw: int, tdiv: int = 1, split: int = 0, pad: int = 0):
         nz, ny, nx = shape
@@ -257,10 +249,10 @@ class BatchPlan:
         return outs
 
     def forward(self, xs, outs=None, stream=None):
-        return self._run(_lib.lib().fft3d_batch_forward, xs, outs, stream)
+        return self._run(_lib.lib().fft3d_forward_batch, xs, outs, stream)
 
     def inverse(self, xs, outs=None, stream=None):
-        return self._run(_lib.lib().fft3d_batch_inverse, xs, outs, stream)
+        return self._run(_lib.lib().fft3d_inverse_batch, xs, outs, stream)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -300,7 +292,10 @@ _cache_lock = threading.Lock()
 
 
 def get_plan(shape, dtype, grid=(1, 1), r2c=False) -> Plan:
-    """Plan cache keyed by (shape, precision, grid, r2c, device)."""
+    """Plan cache keyed by (shape, precision, grid, r2c, device).  A cached plan
+    may be shared by several threads and streams: the library serialises its
+    calls on the host and orders a call on a new stream after the previous
+    call on the device."""
     key = (tuple(int(v) for v in shape), _dtype_code(dtype), tuple(grid), bool(r2c),
            torch.cuda.current_device())
     with _cache_lock:
@@ -342,8 +337,8 @@ def irfftn(h, nx: int, grid=(1, 1), out=None):
 class SpectralPoisson(torch.autograd.Function):
     """phi = irfftn(rfftn(f) / (-|k|^2)), k = 0 mode zeroed, differentiable in f.
 
-    The backward pass runs the library's adjoint entry point (each stage of the
-    solve replaced by its adjoint, in reverse order).
+    The backward pass runs the library's fft3d_poisson_backward (each stage of
+    the solve replaced by its adjoint, in reverse order).
     """
 
     @staticmethod
@@ -354,7 +349,7 @@ class SpectralPoisson(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gphi):
-        return ctx.plan.poisson_adjoint(gphi.contiguous()), None
+        return ctx.plan.poisson_backward(gphi.contiguous()), None
 
 
 def poisson(f, grid=(1, 1)):

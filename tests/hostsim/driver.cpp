@@ -22,6 +22,7 @@
 #include "../../paper_2601_12209_amd/csrc/plane_list.hpp"
 
 extern "C" int hostsim_violations();
+extern "C" size_t hostsim_last_capture_members();
 extern "C" long hostsim_launches();
 extern "C" size_t hostsim_live_allocations();
 
@@ -112,7 +113,7 @@ void c2c_cases(hipStream_t user)
             EXPECT(fft3d_set_stage_config(p, 1, 0, 1, 0, 0) == FFT3D_OK);
             EXPECT(fft3d_set_graphs(p, 0) == FFT3D_OK);
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
-            EXPECT(fft3d_set_half_pitch(p, 64) == FFT3D_ERR_WRONG_PLAN);
+            EXPECT(fft3d_get_staging(p) >= 0);
             if (bytes >= 2 * es_of(dtype))  // partial overlap
                 EXPECT(fft3d_forward(p, in.p, (char*)in.p + es_of(dtype), user) == FFT3D_ERR_ALIAS);
             // swapped-y/z staging: owned workspace, then a caller one
@@ -226,24 +227,18 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, h.p, r2.p, nullptr) == FFT3D_OK);
                 EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
                 EXPECT(fft3d_poisson(p, r.p, r.p, user) == FFT3D_OK);
-                EXPECT(fft3d_poisson_adjoint(p, r2.p, r.p, user) == FFT3D_OK);
+                EXPECT(fft3d_poisson_backward(p, r2.p, r.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
-            // padded half-spectrum rows: buffers of pitch * ny * nz values
-            {
-                const int64_t pitch = (int64_t)padded(c.nx / 2 + 1, dtype) + 3;
-                Buf hp((size_t)pitch * c.ny * c.nz * es);
-                EXPECT(fft3d_set_half_pitch(p, c.nx / 2) == FFT3D_ERR_INVALID_ARG);
-                EXPECT(fft3d_set_half_pitch(p, pitch) == FFT3D_OK);
-                for (int stg : {FFT3D_STAGING_IN_PLACE, FFT3D_STAGING_SWAP_YZ}) {
-                    EXPECT(fft3d_set_staging(p, stg) == FFT3D_OK);
-                    EXPECT(fft3d_forward(p, r.p, hp.p, user) == FFT3D_OK);
-                    EXPECT(fft3d_inverse(p, hp.p, r2.p, user) == FFT3D_OK);
-                    EXPECT(fft3d_backward(p, hp.p, r2.p, nullptr) == FFT3D_OK);
-                }
-                EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
-                EXPECT(fft3d_set_half_pitch(p, 0) == FFT3D_OK);
+            // both forward stagings, then back to in place
+            for (int stg : {FFT3D_STAGING_IN_PLACE, FFT3D_STAGING_SWAP_YZ}) {
+                EXPECT(fft3d_set_staging(p, stg) == FFT3D_OK);
+                EXPECT(fft3d_get_staging(p) == stg);
+                EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, h.p, r2.p, user) == FFT3D_OK);
+                EXPECT(fft3d_backward(p, h.p, r2.p, nullptr) == FFT3D_OK);
             }
+            EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) == FFT3D_ERR_WRONG_PLAN);
             EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
             for (int ns : {1, 3}) {
@@ -265,7 +260,7 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_backward(p, ws.p, r2.p, user) == FFT3D_ERR_ALIAS);
                 EXPECT(fft3d_set_workspace(p, nullptr, 0) == FFT3D_OK);
             }
-            EXPECT(fft3d_poisson_adjoint(p, r.p, r2.p, user) == FFT3D_OK);
+            EXPECT(fft3d_poisson_backward(p, r.p, r2.p, user) == FFT3D_OK);
             // timing mode
             EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
             float ms[8];
@@ -289,13 +284,27 @@ void caller_capture_plan(hipStream_t user)
     if (!p) return;
     Buf in(32 * 24 * 20 * 8), out(32 * 24 * 20 * 8);
     EXPECT(fft3d_set_streams(p, 4) == FFT3D_OK);
-    EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
-    EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+    for (int graphs : {0, 1}) {
+        EXPECT(fft3d_set_graphs(p, graphs) == FFT3D_OK);
+        EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);  // an eager call first
+        EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
+        EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+        EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+        hipGraph_t g = nullptr;
+        EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
+        // the tiles went in order onto the capturing stream: no internal stream joined
+        EXPECT(hostsim_last_capture_members() == 1);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    // a call on another stream after one on `user`, then back
+    hipStream_t other = make_stream();
+    EXPECT(fft3d_forward(p, in.p, out.p, other) == FFT3D_OK);
     EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
-    hipGraph_t g = nullptr;
-    EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
-    if (g) (void)hipGraphDestroy(g);
     EXPECT(fft3d_destroy(p) == FFT3D_OK);
+    (void)hipStreamDestroy(other);
+    // the tile cap
+    EXPECT(fft3d_plan(&p, 64, 64, 64, FFT3D_C64, 33, 32, 0) == FFT3D_ERR_INVALID_ARG);
+    EXPECT(p == nullptr);
 }
 
 void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
@@ -316,16 +325,12 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         fft3d_batch_t b = nullptr;
         EXPECT(fft3d_plan_batch(&b, n, dims.data(), dtype) == FFT3D_OK);
         if (!b) continue;
-        for (int mode : {2, 1, 3, 0}) {
-            EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
-            for (int rep = 0; rep < 3; ++rep) {
-                EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
-                EXPECT(fft3d_batch_inverse(b, out.data(), out.data(), user) == FFT3D_OK);
-                EXPECT(fft3d_batch_forward(b, in.data(), out.data(), nullptr) == FFT3D_OK);
-            }
+        for (int rep = 0; rep < 3; ++rep) {
+            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), nullptr) == FFT3D_OK);
         }
-        // more pointer sets than cached graphs (mode 0 on a stream: one graph each)
-        EXPECT(fft3d_batch_set_mode(b, 0) == FFT3D_OK);
+        // more pointer sets than cached graphs (one graph each)
         for (int rep = 0; rep < 12; ++rep) {
             std::vector<Buf*> fresh;
             std::vector<void*> o2;
@@ -333,8 +338,8 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
                 fresh.push_back(new Buf(bufs2[f]->bytes));
                 o2.push_back(fresh.back()->p);
             }
-            EXPECT(fft3d_batch_forward(b, in.data(), o2.data(), user) == FFT3D_OK);
-            EXPECT(fft3d_batch_forward(b, in.data(), in2.data(), user) == FFT3D_OK);  // in place
+            EXPECT(fft3d_forward_batch(b, in.data(), o2.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), in2.data(), user) == FFT3D_OK);  // in place
             EXPECT(hipStreamSynchronize(user) == hipSuccess);
             for (Buf* x : fresh) delete x;
         }
@@ -343,7 +348,7 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
             EXPECT(fft3d_batch_set_stage_config(b, dims[3 * f], dims[3 * f + 1], dims[3 * f + 2], 1, 4, 1, 0, 0) ==
                    FFT3D_OK);
         }
-        EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+        EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_stage_config(b, 3, 3, 3, 0, 1, 1, 0, 0) == FFT3D_ERR_INVALID_ARG);
         // staging per shape: in place always, fused planes where a kernel fits
         for (int f = 0; f < n; ++f) {
@@ -351,27 +356,32 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
             const bool planes = d[1] > 1 && fft3d::plane_available(d[0], d[1], es_of(dtype));
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_FUSED_XY) ==
                    (planes ? FFT3D_OK : FFT3D_ERR_UNSUPPORTED_SIZE));
-            EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_INVALID_ARG);
         }
-        EXPECT(fft3d_batch_inverse(b, out.data(), out.data(), user) == FFT3D_OK);
+        EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_staging(b, 3, 3, 3, FFT3D_STAGING_IN_PLACE) == FFT3D_ERR_INVALID_ARG);
-        EXPECT(fft3d_batch_set_mode(b, 4) == FFT3D_ERR_INVALID_ARG);
-        // the caller captures the batch into its own graph
-        for (int mode : {0, 1, 3}) {
-            EXPECT(fft3d_batch_set_mode(b, mode) == FFT3D_OK);
+        // the caller captures the batch into its own graph (twice: replays of
+        // the plans' direct issue)
+        for (int rep = 0; rep < 2; ++rep) {
             EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
-            EXPECT(fft3d_batch_forward(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
             hipGraph_t g = nullptr;
             EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
             if (g) (void)hipGraphDestroy(g);
+        }
+        // a partial overlap of one transform's input and output
+        if (bufs[0]->bytes >= 2 * es_of(dtype)) {
+            std::vector<void*> shifted(out.begin(), out.end());
+            shifted[0] = (char*)in2[0] + es_of(dtype);
+            EXPECT(fft3d_forward_batch(b, in.data(), shifted.data(), user) == FFT3D_ERR_ALIAS);
         }
         // overlapping outputs of two transforms
         if (n >= 2) {
             std::vector<void*> bad(out.begin(), out.end());
             bad[1] = bad[0];
-            EXPECT(fft3d_batch_forward(b, in.data(), bad.data(), user) == FFT3D_ERR_ALIAS);
+            EXPECT(fft3d_forward_batch(b, in.data(), bad.data(), user) == FFT3D_ERR_ALIAS);
         }
         EXPECT(fft3d_batch_destroy(b) == FFT3D_OK);
         for (Buf* x : bufs) delete x;

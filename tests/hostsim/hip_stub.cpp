@@ -136,6 +136,9 @@ void enqueue(hipStream_t s) { if (s) ++s->ops; }
 
 }  // namespace
 
+// streams that took part in the most recently ended capture
+size_t g_last_capture_members = 0;
+extern "C" size_t hostsim_last_capture_members() { return g_last_capture_members; }
 extern "C" int hostsim_violations() { return g_violations; }
 extern "C" long hostsim_launches() { return g_launches; }
 extern "C" size_t hostsim_live_allocations() { return g_allocs.size(); }
@@ -325,6 +328,7 @@ hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g)
         }
     }
     g_edges.erase(s->capture);
+    g_last_capture_members = g_members[s->capture].size();
     for (ihipStream_t* m : g_members[s->capture]) {
         m->capture = 0;
         m->origin = nullptr;

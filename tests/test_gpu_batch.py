@@ -3,9 +3,9 @@
 The 64-transform workload (sizes drawn from a seed among 48^3, 64^3, 96^3,
 100x120x128, 160x160x80, complex64): every output against its own FP64
 oracle transform; bitwise equality with the same transform run alone through
-a single-transform plan (the batch runs the same stage kernels); graph replay,
-direct multi-stream issue and serial issue agree bit for bit, also when the
-caller captures the batch into a graph of its own.
+a single-transform plan (the batch runs the same stage kernels); graph replays
+agree bit for bit with the transforms run one by one, also when the caller
+captures the batch into a graph of its own.
 """
 import numpy as np
 import pytest
@@ -14,7 +14,7 @@ import torch
 import oracle
 from paper_2601_12209_amd._lib import Fft3dError
 import synth
-from _util import FP64_BOUND, fp32_bound, rel, to_host
+from _util import assert_parity, FP64_BOUND, fp32_bound, rel, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def test_config4_each_against_oracle_and_single_plan(gpu_lib, workload):
     torch.cuda.synchronize()
     for i, (s, a) in enumerate(zip(shapes, host)):
         got = to_host(outs[i])
-        assert rel(got, oracle.fftn(a.astype(np.complex128))) <= fp32_bound(a.size), (i, s)
+        assert_parity(got, oracle.fftn(a.astype(np.complex128)), fp32_bound(a.size), str((i, s)))
     # bitwise equal to the single-transform plan (same stage kernels)
     for i, s in enumerate(shapes[:12]):
         single = gpu_lib.Plan(s, torch.complex64).forward(xs[i])
@@ -44,31 +44,38 @@ def test_config4_each_against_oracle_and_single_plan(gpu_lib, workload):
     back = bp.inverse(outs)
     torch.cuda.synchronize()
     for i, a in enumerate(host):
-        assert rel(to_host(back[i]), a.astype(np.complex128)) <= fp32_bound(a.size), i
+        assert_parity(to_host(back[i]), a.astype(np.complex128), fp32_bound(a.size), str(i))
     bp.close()
 
 
-def test_modes_and_graph_replays_agree(gpu_lib, workload):
+def test_graph_replays_agree_with_serial_plans(gpu_lib, workload):
+    """Replays of the batch's graph, with eager torch work in between, equal the
+    transforms run one by one through their own plans, bit for bit."""
     shapes, host, xs = workload
     side = torch.cuda.Stream()
-    ref = None
-    for mode in (2, 1, 0, 3):
-        print(f"case mode {mode}", flush=True)
-        bp = gpu_lib.BatchPlan(shapes, mode=mode)
-        outs = [torch.empty_like(x) for x in xs]
+    plans = {s: gpu_lib.Plan(s, torch.complex64) for s in set(shapes)}
+    for p in plans.values():  # the batch's staging per shape: fused planes where they fit
+        try:
+            p.set_staging(gpu_lib.STAGING_FUSED_XY)
+        except Fft3dError:
+            p.set_staging(gpu_lib.STAGING_IN_PLACE)
+    ref = [plans[s].forward(x) for s, x in zip(shapes, xs)]
+    torch.cuda.synchronize()
+    bp = gpu_lib.BatchPlan(shapes)
+    outs = [torch.empty_like(x) for x in xs]
+    for rep in range(3):
+        print(f"case replay {rep}", flush=True)
+        with torch.cuda.stream(side):
+            bp.forward(xs, outs)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+        side.synchronize()
         torch.cuda.synchronize()
-        for rep in range(3):  # graph replays, with eager torch work in between
-            with torch.cuda.stream(side):
-                bp.forward(xs, outs)
-                junk = torch.randn(1 << 20, device="cuda").sum()
-            side.synchronize()
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = [o.clone() for o in outs]
-            for i in range(len(xs)):
-                assert torch.equal(outs[i], ref[i]), (mode, rep, i)
-            del junk
-        bp.close()
+        for i in range(len(xs)):
+            assert torch.equal(outs[i], ref[i]), (rep, i)
+        del junk
+    bp.close()
+    for p in plans.values():
+        p.close()
 
 
 def test_caller_captures_batch(gpu_lib, workload):
@@ -76,7 +83,7 @@ def test_caller_captures_batch(gpu_lib, workload):
     sub = list(range(10))
     s10 = [shapes[i] for i in sub]
     x10 = [xs[i] for i in sub]
-    bp = gpu_lib.BatchPlan(s10, mode=1)
+    bp = gpu_lib.BatchPlan(s10)
     ref = [o.clone() for o in bp.forward(x10)]
     outs = [torch.empty_like(x) for x in x10]
     torch.cuda.synchronize()
@@ -105,8 +112,8 @@ def test_complex128_batch(gpu_lib):
     torch.cuda.synchronize()
     for i, a in enumerate(host):
         a64 = a.astype(np.complex128)
-        assert rel(to_host(outs[i]), oracle.fftn(a64)) <= FP64_BOUND, i
-        assert rel(to_host(back[i]), a64) <= FP64_BOUND, i
+        assert_parity(to_host(outs[i]), oracle.fftn(a64), FP64_BOUND, str(i))
+        assert_parity(to_host(back[i]), a64, FP64_BOUND, str(i))
     bp.close()
 
 
@@ -161,8 +168,9 @@ def test_batch_errors(gpu_lib):
         bp.forward([a.clone(), a.clone()], [a, b])
     with pytest.raises(Fft3dError):
         bp.set_stage_config((4, 4, 4), 0, 1)  # no transform of that shape
-    with pytest.raises(Fft3dError):
-        bp.set_mode(4)
+    x8 = torch.zeros(8, 8, 8, dtype=torch.complex64, device="cuda")
+    with pytest.raises(Fft3dError):  # one transform's input and output partially overlap
+        bp.forward([buf[:512].view(8, 8, 8), x8], [buf[256:768].view(8, 8, 8), x8.clone()])
     with pytest.raises(ValueError):
         bp.forward([a.clone()])
     bp.close()
@@ -184,8 +192,8 @@ def test_batch_staging_per_shape(gpu_lib, workload):
     torch.cuda.synchronize()
     for i, s in enumerate(s16):
         ref = oracle.fftn(host[i].astype(np.complex128))
-        assert rel(to_host(outs[i]), ref) <= fp32_bound(host[i].size), (i, s)
-        assert rel(to_host(fused[i]), ref) <= fp32_bound(host[i].size), (i, s)
+        assert_parity(to_host(outs[i]), ref, fp32_bound(host[i].size), str((i, s)))
+        assert_parity(to_host(fused[i]), ref, fp32_bound(host[i].size), str((i, s)))
     for i, s in enumerate(s16[:6]):
         single = gpu_lib.Plan(s, torch.complex64)
         single.set_staging(gpu_lib.STAGING_IN_PLACE)

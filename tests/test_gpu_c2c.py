@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from _util import bound, promoted, rel, to_dev, to_host
+from _util import assert_parity, bound, promoted, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -59,13 +59,13 @@ def test_forward_inverse_backward(gpu_lib, shape, grid, dtype):
     X = plan.forward(x)
     torch.cuda.synchronize()
     want = oracle.fftn(ref_in)
-    assert rel(to_host(X), want) <= bound(dtype, n)
+    assert_parity(to_host(X), want, bound(dtype, n))
     # inverse of an arbitrary spectrum, and the unscaled adjoint
     xi = plan.inverse(x)
     xb = plan.backward(x)
     torch.cuda.synchronize()
-    assert rel(to_host(xi), oracle.ifftn(ref_in)) <= bound(dtype, n)
-    assert rel(to_host(xb), oracle.bfftn(ref_in)) <= bound(dtype, n)
+    assert_parity(to_host(xi), oracle.ifftn(ref_in), bound(dtype, n))
+    assert_parity(to_host(xb), oracle.bfftn(ref_in), bound(dtype, n))
     # input untouched
     assert torch.equal(x, to_dev(a, dtype))
     plan.close()
@@ -84,9 +84,9 @@ def test_config1_32cubed_against_brute_force(gpu_lib, dtype):
     torch.cuda.synchronize()
     brute = oracle.brute3d(ref_in)
     tol = bound(dtype, ref_in.size)
-    assert rel(to_host(X), brute) <= tol
-    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
-    assert rel(to_host(back), ref_in) <= tol
+    assert_parity(to_host(X), brute, tol)
+    assert_parity(to_host(X), oracle.fftn(ref_in), tol)
+    assert_parity(to_host(back), ref_in, tol)
     plan.close()
 
 
@@ -97,10 +97,10 @@ def test_in_place(gpu_lib):
     x = to_dev(a, torch.complex128)
     plan.forward(x, out=x)
     torch.cuda.synchronize()
-    assert rel(to_host(x), oracle.fftn(a)) <= 1e-12
+    assert_parity(to_host(x), oracle.fftn(a), 1e-12)
     plan.inverse(x, out=x)
     torch.cuda.synchronize()
-    assert rel(to_host(x), a) <= 1e-12
+    assert_parity(to_host(x), a, 1e-12)
     plan.close()
 
 
@@ -149,7 +149,7 @@ def test_kernel_shape_variants_bitwise(gpu_lib, shape, dtype):
     plan = gpu_lib.Plan(shape, dtype)
     ref = plan.forward(x).clone()
     torch.cuda.synchronize()
-    assert rel(to_host(ref), oracle.fftn(promoted(a, dtype))) <= bound(dtype, a.size)
+    assert_parity(to_host(ref), oracle.fftn(promoted(a, dtype)), bound(dtype, a.size))
     from paper_2601_12209_amd._lib import Fft3dError
 
     tried = 0
@@ -199,9 +199,9 @@ def test_swap_yz_staging(gpu_lib, shape, grid, dtype):
     xb = plan.backward(x)
     torch.cuda.synchronize()
     assert torch.equal(X, want_fwd)
-    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
-    assert rel(to_host(xi), oracle.ifftn(ref_in)) <= tol
-    assert rel(to_host(xb), oracle.bfftn(ref_in)) <= tol
+    assert_parity(to_host(X), oracle.fftn(ref_in), tol)
+    assert_parity(to_host(xi), oracle.ifftn(ref_in), tol)
+    assert_parity(to_host(xb), oracle.bfftn(ref_in), tol)
     # in place, then with a caller workspace
     y = x.clone()
     plan.forward(y, out=y)
@@ -254,7 +254,7 @@ def test_graph_replay_of_forked_pipelines(gpu_lib, dtype):
             plan.forward(z, out=z)
     side.synchronize()
     assert torch.equal(z, ref_f)
-    assert rel(to_host(X), oracle.fftn(promoted(a, dtype))) <= bound(dtype, a.size)
+    assert_parity(to_host(X), oracle.fftn(promoted(a, dtype)), bound(dtype, a.size))
     # the caller captures the forked pipeline into its own graph
     out = torch.empty_like(x)
     torch.cuda.synchronize()
@@ -318,7 +318,43 @@ def test_task_graph_replay(gpu_lib, shape, grid, staging, dtype):
     plan.forward(x, out=X)
     torch.cuda.synchronize()
     assert torch.equal(X, ref_f)
-    assert rel(to_host(X), oracle.fftn(promoted(a, dtype))) <= bound(dtype, a.size)
+    assert_parity(to_host(X), oracle.fftn(promoted(a, dtype)), bound(dtype, a.size))
+    plan.close()
+
+
+CAPTURE_CASES = [((24, 30, 40), (2, 3)), ((32, 32, 32), (4, 4))]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid", CAPTURE_CASES, ids=[f"{s}-{g}" for s, g in CAPTURE_CASES])
+def test_caller_captures_tiled_plan(gpu_lib, shape, grid, dtype):
+    """A tiled plan with several streams (and, at 4x4, task-graph replay), called
+    inside a graph the caller captures, records its tiles in order on the
+    capturing stream: every replay, with eager calls of the same plan and other
+    work in between, equals the eager result bit for bit."""
+    print(f"case caller capture shape={shape} grid={grid} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 45)
+    x = to_dev(a, dtype)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=3)
+    ref = plan.forward(x)
+    ref_i = plan.inverse(x)
+    torch.cuda.synchronize()
+    out = torch.empty_like(x)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(x, out=out)
+    for rep in range(3):
+        out.zero_()
+        y = plan.inverse(x)  # an eager call of the same plan between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        assert torch.equal(y, ref_i), rep
+        del junk
+    assert_parity(out, oracle.fftn(promoted(a, dtype)), bound(dtype, a.size), "captured forward")
+    del g
     plan.close()
 
 
@@ -374,8 +410,8 @@ def test_fused_xy_planes(gpu_lib, shape, grid, dtype):
     torch.cuda.synchronize()
     assert torch.equal(X, want)
     assert torch.equal(y, want)
-    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
-    assert rel(to_host(xi), oracle.ifftn(ref_in)) <= tol
-    assert rel(to_host(xb), oracle.bfftn(ref_in)) <= tol
+    assert_parity(to_host(X), oracle.fftn(ref_in), tol)
+    assert_parity(to_host(xi), oracle.ifftn(ref_in), tol)
+    assert_parity(to_host(xb), oracle.bfftn(ref_in), tol)
     plan.close()
     base.close()

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synth
-from _util import bound, promoted, rel, to_dev, to_host
+from _util import assert_parity, bound, promoted, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +28,11 @@ def test_poisson_forward_and_adjoint(gpu_lib, shape, grid, dtype):
     w = synth.real_normal(shape, 22)
     plan = gpu_lib.Plan(shape, dtype, grid, r2c=True)
     phi = plan.poisson(to_dev(f, dtype))
-    gf = plan.poisson_adjoint(to_dev(w, dtype))
+    gf = plan.poisson_backward(to_dev(w, dtype))
     torch.cuda.synchronize()
     n = f.size
-    assert rel(to_host(phi), oracle.poisson(promoted(f, dtype))) <= bound(dtype, n)
-    assert rel(to_host(gf), oracle.poisson_grad(promoted(w, dtype))) <= bound(dtype, n)
+    assert_parity(to_host(phi), oracle.poisson(promoted(f, dtype)), bound(dtype, n))
+    assert_parity(to_host(gf), oracle.poisson_grad(promoted(w, dtype)), bound(dtype, n))
     plan.close()
 
 
@@ -53,7 +53,7 @@ def test_poisson_in_place(gpu_lib):
     t = to_dev(f, torch.float64)
     plan.poisson(t, out=t)
     torch.cuda.synchronize()
-    assert rel(to_host(t), oracle.poisson(f)) <= 1e-12
+    assert_parity(to_host(t), oracle.poisson(f), 1e-12)
     plan.close()
 
 
@@ -77,10 +77,10 @@ def test_config5_256cubed_gradient(gpu_lib, dtype):
     torch.cuda.synchronize()
     n = f.size
     f_in, w_in = promoted(f, dtype), promoted(w, dtype)
-    assert rel(to_host(phi), oracle.poisson(f_in)) <= bound(dtype, n)
+    assert_parity(to_host(phi), oracle.poisson(f_in), bound(dtype, n))
     grad = to_host(fd.grad)
     ref_grad = oracle.poisson_grad(w_in)  # FP64 reference gradient
-    assert rel(grad, ref_grad) <= bound(dtype, n)
+    assert_parity(grad, ref_grad, bound(dtype, n))
     # directional finite difference, loss summed in FP64
     d = synth.real_normal(shape, 7)
     eps = np.linalg.norm(f) / np.linalg.norm(d)  # L is linear: any step is exact up to rounding

@@ -1,18 +1,23 @@
 """GPU parity at the full workload sizes, in the launch configuration the
-benchmark times.
+benchmark times.  Every compared array is checked by rel-L2 and by the largest
+single-element error relative to the RMS of the reference (see _util).
 
 * 512^3 complex64 and complex128, grid 1x1 (the headline step): forward and
   inverse against the FP64 oracle on every output.
+* 512^3 float32 and float64 R2C + C2R at the default plan (swapped-y/z
+  forward staging, the cache policy of fields larger than the Infinity
+  Cache): the forward on every output against the oracle's R2C, the C2R of
+  the oracle's half spectrum against the oracle's C2R, and the round trip.
 * 256^3 complex64 and complex128, pencil grid 4x4: forward and inverse against
   the oracle on every output.
 * 840^3 complex64 (radix-7 lengths, the largest grid of the paper's GPU
-  runs) by 32 sampled outputs and the round trip.
+  runs): 64 whole z-lines (53,760 outputs) against the oracle and the round
+  trip on every point.
 * 1024^3 real float32 turbulence field, pencil grid 8x8, R2C then C2R: the
-  FP64 oracle cannot take the whole transform in test time, so (i) 82 outputs
-  (18 low and Nyquist modes plus 64 seeded random ones) against
-  per-point O(N) oracle sums, with their error measured against the field's
-  spectral RMS known exactly from Parseval; (ii) Parseval on the GPU half
-  spectrum; (iii) the C2R round trip on every point.
+  whole z-lines through every tile edge of the 8x8 grid in x and y (16 x 16
+  lines, 262,144 outputs, every z tile edge included) against the oracle, with
+  errors relative to the spectral RMS known exactly from Parseval; Parseval on
+  the GPU half spectrum; the C2R round trip on every point.
 """
 import math
 
@@ -22,7 +27,7 @@ import torch
 
 import oracle
 import synth
-from _util import bound, fp32_bound, promoted, rel, to_dev, to_host
+from _util import assert_parity, bound, fp32_bound, promoted, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +39,7 @@ def test_headline_512cubed_full_field(gpu_lib, dtype):
     a = synth.complex_normal(cfg["shape"], cfg["seed"], np.complex64 if dtype == torch.complex64 else np.complex128)
     x = to_dev(a, dtype)
     plan = gpu_lib.Plan(cfg["shape"], dtype, (1, 1), streams=1)
+    assert plan.staging == gpu_lib.STAGING_SWAP_YZ  # the benchmark's configuration
     X = plan.forward(x)
     Y = plan.inverse(X)
     torch.cuda.synchronize()
@@ -41,13 +47,47 @@ def test_headline_512cubed_full_field(gpu_lib, dtype):
     del x
     want = oracle.fftn(ref_in)
     tol = bound(dtype, a.size)
-    err = rel(to_host(X), want)
-    print(f"forward rel-L2 {err:.3e} (bound {tol:.1e})", flush=True)
-    assert err <= tol
+    assert_parity(X, want, tol, "forward")
+    print(f"forward rel-L2 {rel(to_host(X), want):.3e} (bound {tol:.1e})", flush=True)
     del want, X
-    err = rel(to_host(Y), ref_in)
-    print(f"round trip rel-L2 {err:.3e}", flush=True)
-    assert err <= tol
+    assert_parity(Y, ref_in, tol, "round trip")
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_headline_512cubed_r2c_full_field(gpu_lib, dtype):
+    """The R2C half of the headline target at the plan's default configuration."""
+    n = 512
+    shape = (n, n, n)
+    cdt = torch.complex64 if dtype == torch.float32 else torch.complex128
+    print(f"case 512^3 r2c {dtype} default plan", flush=True)
+    f = synth.real_normal(shape, 10, np.float32 if dtype == torch.float32 else np.float64)
+    x = to_dev(f, dtype)
+    plan = gpu_lib.Plan(shape, dtype, r2c=True)
+    assert plan.staging == gpu_lib.STAGING_SWAP_YZ  # half spectrum of 0.5-1 GiB: swapped forward staging
+    H = plan.forward(x)
+    back = plan.inverse(H)
+    torch.cuda.synchronize()
+    del x
+    tol = bound(dtype, f.size)
+    f_in = f.astype(np.float64)
+    want = oracle.rfftn(f_in)
+    print("oracle r2c done", flush=True)
+    assert_parity(H, want, tol, "forward")
+    del H
+    assert_parity(back, f_in, tol, "round trip")
+    del back
+    # the C2R on its own: the oracle's half spectrum (rounded to the plan precision) back to real
+    h_in = want.astype(np.complex64 if dtype == torch.float32 else np.complex128)
+    del want
+    hd = to_dev(h_in, cdt)
+    y = plan.inverse(hd)
+    torch.cuda.synchronize()
+    del hd
+    want_y = oracle.irfftn(h_in.astype(np.complex128), n)
+    print("oracle c2r done", flush=True)
+    assert_parity(y, want_y, tol, "inverse of the oracle spectrum")
     plan.close()
 
 
@@ -63,20 +103,31 @@ def test_config2_256cubed_grid4x4(gpu_lib, dtype):
     torch.cuda.synchronize()
     ref_in = promoted(a, dtype)
     tol = bound(dtype, a.size)
-    assert rel(to_host(X), oracle.fftn(ref_in)) <= tol
-    assert rel(to_host(Y), oracle.ifftn(oracle.fftn(ref_in))) <= tol
+    want = oracle.fftn(ref_in)
+    assert_parity(X, want, tol, "forward")
+    assert_parity(Y, oracle.ifftn(want), tol, "inverse")
     plan.close()
 
 
-def _sample_points(shape, fixed, rng, n_random):
-    """The fixed (kz, ky, kx) points plus n_random distinct seeded ones."""
-    nz, ny, nx = shape
-    pts = [tuple(p) for p in fixed]
-    while len(pts) < len(fixed) + n_random:
-        p = (int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx // 2 + 1)))
-        if p not in pts:
-            pts.append(p)
-    return np.array(pts, dtype=np.int64)
+def _edges(bounds, n):
+    """Both sides of every boundary in bounds (a sorted list of range starts), within [0, n)."""
+    out = set()
+    for b in bounds:
+        for v in (b - 1, b):
+            if 0 <= v < n:
+                out.add(v)
+    return sorted(out)
+
+
+def _check_lines(got, want, rms_all, tol, what):
+    """Sampled outputs: their RMS and largest error, both relative to the RMS of
+    all N outputs of the transform (the scale FFT rounding errors follow)."""
+    d = np.abs(got - want)
+    e_rms = float(np.sqrt(np.mean(d ** 2))) / rms_all
+    e_max = float(d.max()) / rms_all
+    print(f"{what}: {got.size} outputs, rms error {e_rms:.3e}, max error {e_max:.3e} "
+          f"(relative to the spectral RMS; bound {tol:.1e})", flush=True)
+    assert e_rms <= tol and e_max <= tol, what
 
 
 @pytest.mark.timeout(900)
@@ -85,6 +136,7 @@ def test_config3_1024cubed_r2c_turbulence(gpu_lib):
     shape = cfg["shape"]
     nz, ny, nx = shape
     n = nz * ny * nx
+    p1, p2 = cfg["grid"]
     print("case 1024^3 r2c turbulence grid 8x8: building the field", flush=True)
     u = synth.turbulence_field(shape, cfg["seed"], np.float32)
     print("field built", flush=True)
@@ -104,36 +156,38 @@ def test_config3_1024cubed_r2c_turbulence(gpu_lib):
     print(f"Parseval: spectrum {spec_energy:.6e} field*N {field_energy:.6e}", flush=True)
     assert abs(spec_energy - field_energy) <= 1e-5 * field_energy
 
-    # (i) sampled outputs against per-point oracle sums; error relative to the
-    # spectral RMS over all N outputs (= sqrt(field_energy / N))
-    rng = np.random.default_rng(1234)
-    low = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 1), (1, 1, 0), (1, 0, 1), (1, 1, 1), (0, 0, 2),
-           (0, 2, 0), (2, 0, 0), (0, ny - 1, 1), (nz - 1, 0, 1), (nz - 1, ny - 1, 1), (0, 0, nx // 2),
-           (0, ny // 2, 0), (nz // 2, 0, 0), (nz // 2, ny // 2, nx // 2), (0, 0, 0)]
-    pts = _sample_points(shape, low, rng, 64)
-    want = oracle.dft3d_points(u64, pts)
-    Hh = H[pts[:, 0], pts[:, 1], pts[:, 2]].cpu().numpy().astype(np.complex128)
+    # (i) whole z-lines through every tile edge in x and y: the x edges of the
+    # y- and z-pencil tiles (the plan's task graph gives them), the y edges of
+    # the x- and z-pencil tiles; every kz covers the z edges of the x- and
+    # y-pencil tiles
+    _, tasks = gpu_lib.query_pipeline(shape, cfg["grid"], r2c=True, op=0, nstreams=1)
+    xb = sorted({t["box"][0] for t in tasks} | {t["box"][1] for t in tasks})
+    yb = sorted({t["box"][2] for t in tasks} | {t["box"][3] for t in tasks})
+    kxs = _edges(xb, nx // 2 + 1)
+    kys = _edges(yb, ny)
+    assert len(kxs) >= 2 * (p1 - 1) + 2 and len(kys) >= 2 * (p2 - 1) + 2, (kxs, kys)
+    kx = np.repeat(kxs, len(kys))
+    ky = np.tile(kys, len(kxs))
+    want = oracle.dft3d_lines(u64, kx, ky)  # (nz, pairs)
+    got = H[:, torch.as_tensor(ky, device="cuda"), torch.as_tensor(kx, device="cuda")].cpu().numpy()
     rms_all = math.sqrt(field_energy / n)
-    err = float(np.sqrt(np.mean(np.abs(Hh - want) ** 2)) / rms_all)
-    print(f"sampled error / spectral RMS: {err:.3e} (bound {fp32_bound(n):.1e})", flush=True)
-    assert err <= fp32_bound(n)
-    del u64
+    _check_lines(got.astype(np.complex128), want, rms_all, fp32_bound(n), "1024^3 r2c tile-edge lines")
+    del u64, want
 
     # (iii) round trip on every point
     back = plan.inverse(H)
     torch.cuda.synchronize()
     del H
-    err = rel(to_host(back), u.astype(np.float64))
-    print(f"round trip rel-L2 {err:.3e}", flush=True)
-    assert err <= fp32_bound(n)
+    assert_parity(back, u.astype(np.float64), fp32_bound(n), "round trip")
     plan.close()
 
 
 @pytest.mark.timeout(900)
 def test_840cubed_radix7_sampled(gpu_lib):
     """The largest grid of the paper's GPU runs, 840^3 = (8*3*5*7)^3 complex64, on
-    one GPU: 32 seeded outputs against per-point oracle sums (error measured
-    against the spectral RMS from Parseval) and the round trip on every point."""
+    one GPU: 64 whole z-lines (8 x 8 seeded (kx, ky) pairs plus the first and last
+    bins) against the oracle, errors relative to the spectral RMS from
+    Parseval, and the round trip on every point."""
     shape = (840, 840, 840)
     n = 840 ** 3
     print("case 840^3 c64: building the field", flush=True)
@@ -143,23 +197,20 @@ def test_840cubed_radix7_sampled(gpu_lib):
     X = plan.forward(x)
     torch.cuda.synchronize()
     rng = np.random.default_rng(99)
-    pts = np.stack([rng.integers(840, size=32) for _ in range(3)], axis=1)
-    pts[0] = (0, 0, 0)
-    pts[1] = (0, 0, 1)
+    kxs = sorted(set([0, 839] + list(rng.integers(840, size=6))))
+    kys = sorted(set([0, 839] + list(rng.integers(840, size=6))))
+    kx = np.repeat(kxs, len(kys))
+    ky = np.tile(kys, len(kxs))
     a128 = a.astype(np.complex128)
-    want = oracle.dft3d_points(a128, pts)
-    got = X[pts[:, 0], pts[:, 1], pts[:, 2]].cpu().numpy().astype(np.complex128)
-    rms_all = math.sqrt(n * float(np.vdot(a128.ravel(), a128.ravel()).real) / n)
-    err = float(np.sqrt(np.mean(np.abs(got - want) ** 2)) / rms_all)
-    print(f"sampled error / spectral RMS: {err:.3e}", flush=True)
-    assert err <= fp32_bound(n)
-    del a128
+    want = oracle.dft3d_lines(a128, kx, ky)
+    got = X[:, torch.as_tensor(ky, device="cuda"), torch.as_tensor(kx, device="cuda")].cpu().numpy()
+    rms_all = math.sqrt(float(np.vdot(a128.ravel(), a128.ravel()).real))
+    _check_lines(got.astype(np.complex128), want, rms_all, fp32_bound(n), "840^3 lines")
+    del a128, want
     Y = plan.inverse(X)
     torch.cuda.synchronize()
     del X
-    err = rel(to_host(Y), a.astype(np.complex128))
-    print(f"round trip rel-L2 {err:.3e}", flush=True)
-    assert err <= fp32_bound(n)
+    assert_parity(Y, a.astype(np.complex128), fp32_bound(n), "round trip")
     plan.close()
 
 
