@@ -130,6 +130,10 @@ def _time(fn, reps, torch):
     return start.elapsed_time(end) / reps
 
 
+def _progress(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
 def _extras(reps, torch, fft3d, synth, np):
     """The other workloads, timed on the GPU.  Returns (report, checks) where
     checks holds (name, GPU result on the host, function giving the FP64 oracle
@@ -139,6 +143,7 @@ def _extras(reps, torch, fft3d, synth, np):
     N = n ** 3
     nh = (n // 2 + 1) * n * n
     for dt, tag, sr, npdt in ((torch.float32, "f32", 4, np.float32), (torch.float64, "f64", 8, np.float64)):
+        _progress(f"extras: 512^3 r2c {tag}")
         f = synth.real_normal((n, n, n), 10, npdt)
         x = torch.from_numpy(f).cuda()
         p = fft3d.Plan((n, n, n), dt, r2c=True)
@@ -146,20 +151,9 @@ def _extras(reps, torch, fft3d, synth, np):
         y = p.inverse(H)
         ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), reps, torch)
         bytes_moved = 2 * N * sr + 10 * nh * 2 * sr  # x stage real in/out, 5 half-spectrum passes each way
-        # per pass: the real x stages move N reals and nh complex values, the
-        # half-spectrum passes nh complex values in and out
-        fwd_st, inv_st = _stage_profile(p, x, H, y, max(3, min(reps, 10)), torch)
-        pass_bytes_x = N * sr + nh * 2 * sr
-        pass_bytes_c = 2 * nh * 2 * sr
-        passes = {}
-        for tag2, st in (("fwd", fwd_st), ("inv", inv_st)):
-            names = ("x", "y", "z") if tag2 == "fwd" else ("z", "y", "x")
-            for nm, t in zip(names, st):
-                b = pass_bytes_x if nm == "x" else pass_bytes_c
-                passes[f"{tag2}_{nm}"] = {"ms": round(t, 4), "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         rep[f"r2c_512cubed_fwd_inv_{tag}"] = {
             "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "passes": passes}
+            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         Hh, yh = H.cpu().numpy(), y.cpu().numpy()
         checks.append((f"r2c_512cubed_{tag}_forward", Hh, lambda f=f: _oracle().rfftn(f.astype(np.float64))))
         checks.append((f"r2c_512cubed_{tag}_roundtrip", yh, lambda f=f: f.astype(np.float64)))
@@ -172,6 +166,7 @@ def _extras(reps, torch, fft3d, synth, np):
     a = synth.complex_normal(cfg["shape"], cfg["seed"], np.complex64)
     side = torch.cuda.Stream()
     for dt, tag, es in ((torch.complex64, "c64", 8), (torch.complex128, "c128", 16)):
+        _progress(f"extras: 256^3 c2c {tag}")
         x = torch.from_numpy(a).to("cuda", dt)
         for grid, ns in ((tuple(cfg["grid"]), 4), ((1, 1), 1)):
             p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns)
@@ -201,6 +196,7 @@ def _extras(reps, torch, fft3d, synth, np):
     nh3 = (c3["shape"][2] // 2 + 1) * c3["shape"][0] * c3["shape"][1]
     x = torch.randn(c3["shape"], dtype=torch.float32, device="cuda")
     for grid in (tuple(c3["grid"]), (1, 1)):
+        _progress(f"extras: 1024^3 r2c grid {grid}")
         p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True)
         H = p.forward(x)
         y = torch.empty_like(x)
@@ -217,6 +213,7 @@ def _extras(reps, torch, fft3d, synth, np):
     torch.cuda.empty_cache()
     # 840^3 complex64: the largest grid of the paper's GPU runs (lengths with a
     # factor 7), whole on one GPU; parity is covered by the GPU tests
+    _progress("extras: 840^3 c2c")
     n8 = 840
     m8 = n8 ** 3
     x = torch.randn((n8, n8, n8), dtype=torch.complex64, device="cuda")
@@ -232,6 +229,7 @@ def _extras(reps, torch, fft3d, synth, np):
     del x, X, Y
     torch.cuda.empty_cache()
     # 64 uneven transforms issued as one task graph, on a non-default stream
+    _progress("extras: 64 uneven transforms")
     shapes = synth.batch_sizes()
     host = synth.batch_inputs(shapes, synth.CFG4["seed"])
     xs = [torch.from_numpy(h).cuda() for h in host]
@@ -308,6 +306,7 @@ def _extras(reps, torch, fft3d, synth, np):
     del xs, outs
     torch.cuda.empty_cache()
     # differentiable Poisson solve, 256^3 float32: forward solve + adjoint (one gradient step)
+    _progress("extras: 256^3 Poisson")
     c5 = synth.CFG5
     f = synth.smooth_field(c5["shape"], c5["seed_f"], c5["sigma"], np.float32)
     w = synth.real_normal(c5["shape"], c5["seed_w"], np.float32)
@@ -344,6 +343,56 @@ def _oracle():
     return oracle
 
 
+def _run_extras_child(args):
+    """The other workloads in a child process (its own HIP context), so that a
+    failure there cannot take the headline record with it.  Returns (report,
+    rel-L2 errors against the oracle)."""
+    import subprocess
+    import tempfile
+
+    fd, path = tempfile.mkstemp(prefix="fft3d_extras_", suffix=".json")
+    os.close(fd)
+    cmd = [sys.executable, os.path.abspath(__file__), "--extras-child", path, "--steps", str(args.steps)]
+    if args.no_cpu_baseline:
+        cmd.append("--no-cpu-baseline")
+    try:
+        rc = subprocess.run(cmd).returncode
+        if rc != 0:
+            return {"error": f"extras process exited with status {rc}"}, {}
+        with open(path) as fh:
+            rec = json.load(fh)
+        return rec["extras"], rec["errs"]
+    finally:
+        try:
+            os.remove(path)
+        except OSError:
+            pass
+
+
+def _extras_child(args):
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import synth
+    from paper_2601_12209_amd import fft3d
+
+    fft3d.load()
+    rep, checks = _extras(max(3, min(args.steps, 10)), torch, fft3d, synth, np)
+    errs = {}
+    if not args.no_cpu_baseline:
+        oracle = _oracle()
+        _progress("extras: oracle comparisons")
+        for name, got, ref_fn in checks:
+            ref = ref_fn()
+            if isinstance(got, list):
+                errs[name] = max(oracle.rel_l2(g, r) for g, r in zip(got, ref))
+            else:
+                errs[name] = oracle.rel_l2(got, ref)
+    with open(args.extras_child, "w") as fh:
+        json.dump({"extras": rep, "errs": errs}, fh)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,7 +411,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy the complex64 field once with a plain device copy "
                          "(a known-size reference for HBM byte counters)")
+    ap.add_argument("--extras-child", metavar="PATH", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.extras_child:
+        _extras_child(args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -454,7 +507,7 @@ def main():
                           "stages_c128": stage_report(r64, 16),
                           "fp32_over_fp64_speedup": round(r64["ms"] / r32["ms"], 3)}
 
-    checks = []
+    extras_errs = {}
     if not args.no_extras:
         # keep the headline results on the host for the oracle comparison, free the GPU
         for r in (r32, r64):
@@ -463,8 +516,8 @@ def main():
             elif r is not None:
                 r.pop("X"), r.pop("Y")
         torch.cuda.empty_cache()
-        print("# extras", file=sys.stderr, flush=True)
-        result["extras"], checks = _extras(max(3, min(args.steps, 10)), torch, fft3d, synth, np)
+        print("# extras (child process)", file=sys.stderr, flush=True)
+        result["extras"], extras_errs = _run_extras_child(args)
 
     if not args.no_cpu_baseline:
         import oracle  # test infrastructure: the CPU baseline leg only
@@ -489,14 +542,8 @@ def main():
         if r64 is not None:
             errs["c128_forward"] = oracle.rel_l2(host(r64["X"]), X_ref)
             errs["c128_inverse_of_forward"] = oracle.rel_l2(host(r64["Y"]), a128)
-        del X_ref
-        for name, got, ref_fn in checks:
-            ref = ref_fn()
-            if isinstance(got, list):
-                errs[name] = max(oracle.rel_l2(g, r) for g, r in zip(got, ref))
-            else:
-                errs[name] = oracle.rel_l2(got, ref)
-        del Y_ref
+        del X_ref, Y_ref
+        errs.update(extras_errs)
         result["cpu_baseline"] = {
             "value": round(2 * flop_per_transform / t_cpu / 1e9, 3), "unit": "GFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",

@@ -29,6 +29,7 @@ extern "C" size_t hostsim_live_allocations();
 namespace {
 
 int g_failures = 0;
+std::vector<int64_t> g_batch_dims;  // the batch shapes (x fastest)
 
 #define EXPECT(cond)                                                                              \
     do {                                                                                          \
@@ -393,10 +394,238 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
     EXPECT(b == nullptr);
 }
 
+
+// The C-ABI call sequence of bench.py at its full sizes (headline 512^3
+// C2C in both precisions, then every extra workload), on the legacy default
+// stream and a second stream the way torch hands them over.
+void bench_sequence()
+{
+    hipStream_t side = make_stream();
+    float ms[8];
+    auto step = [&](const char* what) { printf("bench step: %s\n", what); fflush(stdout); };
+    // headline: 512^3 C2C, grid 1x1, one stream, swapped staging
+    for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+        step(dtype == FFT3D_C64 ? "512^3 c64" : "512^3 c128");
+        const size_t b = (size_t)512 * 512 * 512 * es_of(dtype);
+        Buf x(b), X(b), Y(b);
+        fft3d_plan_t p = nullptr;
+        EXPECT(fft3d_plan(&p, 512, 512, 512, dtype, 1, 1, 0) == FFT3D_OK);
+        if (!p) continue;
+        EXPECT(fft3d_set_streams(p, 1) == FFT3D_OK);
+        EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_OK);
+        for (int i = 0; i < 23; ++i) {
+            EXPECT(fft3d_forward(p, x.p, X.p, side) == FFT3D_OK);
+            EXPECT(fft3d_inverse(p, X.p, Y.p, side) == FFT3D_OK);
+        }
+        EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+        for (int i = 0; i < 10; ++i) {
+            EXPECT(fft3d_forward(p, x.p, X.p, nullptr) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) == 3);
+            EXPECT(fft3d_inverse(p, X.p, Y.p, nullptr) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) == 3);
+        }
+        EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+        EXPECT(fft3d_forward(p, x.p, X.p, nullptr) == FFT3D_OK);
+        EXPECT(fft3d_inverse(p, X.p, Y.p, nullptr) == FFT3D_OK);
+        EXPECT(fft3d_destroy(p) == FFT3D_OK);
+    }
+    // 512^3 R2C + C2R in both precisions, default stream, with timing
+    for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+        step(dtype == FFT3D_C64 ? "512^3 r2c f32" : "512^3 r2c f64");
+        const size_t es = es_of(dtype);
+        Buf x((size_t)512 * 512 * 512 * es / 2), H((size_t)257 * 512 * 512 * es), y((size_t)512 * 512 * 512 * es / 2);
+        fft3d_plan_t p = nullptr;
+        EXPECT(fft3d_plan(&p, 512, 512, 512, dtype, 1, 1, 1) == FFT3D_OK);
+        if (!p) continue;
+        for (int i = 0; i < 13; ++i) {
+            EXPECT(fft3d_forward(p, x.p, H.p, nullptr) == FFT3D_OK);
+            EXPECT(fft3d_inverse(p, H.p, y.p, nullptr) == FFT3D_OK);
+        }
+        EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+        for (int i = 0; i < 10; ++i) {
+            EXPECT(fft3d_forward(p, x.p, H.p, nullptr) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) == 3);
+            EXPECT(fft3d_inverse(p, H.p, y.p, nullptr) == FFT3D_OK);
+            EXPECT(fft3d_stage_times(p, ms, 8) == 3);
+        }
+        EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+        EXPECT(fft3d_destroy(p) == FFT3D_OK);
+    }
+    // 256^3 C2C on the 4x4 grid (4 streams, task graph) and 1x1 (1 stream)
+    for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+        step(dtype == FFT3D_C64 ? "256^3 c64" : "256^3 c128");
+        const size_t b = (size_t)256 * 256 * 256 * es_of(dtype);
+        Buf x(b), X(b), Y(b);
+        for (int g : {4, 1}) {
+            fft3d_plan_t p = nullptr;
+            EXPECT(fft3d_plan(&p, 256, 256, 256, dtype, g, g, 0) == FFT3D_OK);
+            if (!p) continue;
+            EXPECT(fft3d_set_streams(p, g == 4 ? 4 : 1) == FFT3D_OK);
+            EXPECT(fft3d_forward(p, x.p, X.p, nullptr) == FFT3D_OK);
+            for (int i = 0; i < 12; ++i) {
+                EXPECT(fft3d_forward(p, x.p, X.p, side) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, X.p, Y.p, side) == FFT3D_OK);
+            }
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    // 1024^3 R2C + C2R f32 on the 8x8 grid and on 1x1
+    {
+        const size_t real = (size_t)1024 * 1024 * 1024 * 4, half = (size_t)513 * 1024 * 1024 * 8;
+        Buf x(real), y(real);
+        for (int g : {8, 1}) {
+            step(g == 8 ? "1024^3 r2c 8x8" : "1024^3 r2c 1x1");
+            Buf H(half);
+            fft3d_plan_t p = nullptr;
+            EXPECT(fft3d_plan(&p, 1024, 1024, 1024, FFT3D_C64, g, g, 1) == FFT3D_OK);
+            if (!p) continue;
+            EXPECT(fft3d_forward(p, x.p, H.p, nullptr) == FFT3D_OK);
+            for (int i = 0; i < 7; ++i) {
+                EXPECT(fft3d_forward(p, x.p, H.p, side) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, H.p, y.p, side) == FFT3D_OK);
+            }
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    // 840^3 C2C complex64, one tile
+    {
+        step("840^3 c64");
+        const size_t b = (size_t)840 * 840 * 840 * 8;
+        Buf x(b), X(b), Y(b);
+        fft3d_plan_t p = nullptr;
+        EXPECT(fft3d_plan(&p, 840, 840, 840, FFT3D_C64, 1, 1, 0) == FFT3D_OK);
+        if (p) {
+            EXPECT(fft3d_forward(p, x.p, X.p, nullptr) == FFT3D_OK);
+            for (int i = 0; i < 7; ++i) {
+                EXPECT(fft3d_forward(p, x.p, X.p, side) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, X.p, Y.p, side) == FFT3D_OK);
+            }
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    // 64 uneven transforms: a probe batch for the fused shapes, then a batch
+    // whose launch shapes come from the autotuner's search on stand-alone
+    // plans (timing mode, every candidate shape), replayed on `side`; the
+    // same transforms one by one through plans of their own; a second batch
+    {
+        step("batch");
+        const std::vector<int64_t>& dims = g_batch_dims;
+        const int n = (int)dims.size() / 3;
+        std::vector<Buf*> bufs;
+        std::vector<const void*> in;
+        std::vector<void*> out;
+        for (int f = 0; f < n; ++f) {
+            const size_t b = (size_t)dims[3 * f] * dims[3 * f + 1] * dims[3 * f + 2] * 8;
+            bufs.push_back(new Buf(b));
+            in.push_back(bufs.back()->p);
+            bufs.push_back(new Buf(b));
+            out.push_back(bufs.back()->p);
+        }
+        std::vector<std::vector<int64_t>> shapes;
+        for (int f = 0; f < n; ++f) {
+            std::vector<int64_t> sh(dims.begin() + 3 * f, dims.begin() + 3 * f + 3);
+            if (std::find(shapes.begin(), shapes.end(), sh) == shapes.end()) shapes.push_back(sh);
+        }
+        fft3d_batch_t probe = nullptr;
+        EXPECT(fft3d_plan_batch(&probe, n, dims.data(), FFT3D_C64) == FFT3D_OK);
+        for (auto& sh : shapes) (void)fft3d_batch_set_staging(probe, sh[0], sh[1], sh[2], FFT3D_STAGING_FUSED_XY);
+        EXPECT(fft3d_batch_destroy(probe) == FFT3D_OK);
+        for (int round = 0; round < 2; ++round) {
+            fft3d_batch_t bp = nullptr;
+            EXPECT(fft3d_plan_batch(&bp, n, dims.data(), FFT3D_C64) == FFT3D_OK);
+            if (!bp) break;
+            for (auto& sh : shapes) {
+                const size_t b = (size_t)sh[0] * sh[1] * sh[2] * 8;
+                Buf x(b), o(b);
+                fft3d_plan_t p = nullptr;
+                EXPECT(fft3d_plan(&p, sh[0], sh[1], sh[2], FFT3D_C64, 1, 1, 0) == FFT3D_OK);
+                if (!p) continue;
+                EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, x.p, o.p, nullptr) == FFT3D_OK);
+                const int nst = fft3d_stage_times(p, ms, 8);
+                EXPECT(nst >= 2);
+                EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+                std::vector<int> axes = nst == 3 ? std::vector<int>{0, 1, 2} : std::vector<int>{2};
+                for (int axis : axes) {
+                    int best[4] = {0, 1, 0, 0};
+                    EXPECT(fft3d_set_stage_config(p, axis, 0, 1, 0, 0) == FFT3D_OK);
+                    for (int lw : {1, 2, 4, 8, 16, 32, 64})
+                        for (int td : {1, 2, 4})
+                            for (int sp : {0, 1})
+                                for (int pd : {0, 1}) {
+                                    if (fft3d_set_stage_config(p, axis, lw, td, sp, pd) != FFT3D_OK) continue;
+                                    EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+                                    for (int r = 0; r < 6; ++r) {
+                                        EXPECT(fft3d_forward(p, x.p, o.p, nullptr) == FFT3D_OK);
+                                        EXPECT(fft3d_stage_times(p, ms, 8) == nst);
+                                    }
+                                    EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+                                    best[0] = lw; best[1] = td; best[2] = sp; best[3] = pd;
+                                }
+                    EXPECT(fft3d_set_stage_config(p, axis, best[0], best[1], best[2], best[3]) == FFT3D_OK);
+                    EXPECT(fft3d_batch_set_stage_config(bp, sh[0], sh[1], sh[2], axis, best[0], best[1], best[2],
+                                                        best[3]) == FFT3D_OK);
+                }
+                EXPECT(fft3d_destroy(p) == FFT3D_OK);
+            }
+            for (int r = 0; r < 12; ++r) EXPECT(fft3d_forward_batch(bp, in.data(), out.data(), side) == FFT3D_OK);
+            EXPECT(fft3d_batch_destroy(bp) == FFT3D_OK);
+            if (round == 0) {
+                std::vector<fft3d_plan_t> plans;
+                for (auto& sh : shapes) {
+                    fft3d_plan_t p = nullptr;
+                    EXPECT(fft3d_plan(&p, sh[0], sh[1], sh[2], FFT3D_C64, 1, 1, 0) == FFT3D_OK);
+                    if (fft3d_set_staging(p, FFT3D_STAGING_FUSED_XY) != FFT3D_OK)
+                        EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
+                    plans.push_back(p);
+                }
+                for (int r = 0; r < 12; ++r)
+                    for (int f = 0; f < n; ++f) {
+                        std::vector<int64_t> sh(dims.begin() + 3 * f, dims.begin() + 3 * f + 3);
+                        const size_t k = std::find(shapes.begin(), shapes.end(), sh) - shapes.begin();
+                        EXPECT(fft3d_forward(plans[k], in[f], out[f], side) == FFT3D_OK);
+                    }
+                for (fft3d_plan_t p : plans) EXPECT(fft3d_destroy(p) == FFT3D_OK);
+            }
+        }
+        for (Buf* x : bufs) delete x;
+    }
+    // 256^3 Poisson solve + adjoint, float32, default stream
+    {
+        step("poisson 256^3");
+        const size_t real = (size_t)256 * 256 * 256 * 4;
+        Buf f(real), w(real), phi(real), g(real);
+        fft3d_plan_t p = nullptr;
+        EXPECT(fft3d_plan(&p, 256, 256, 256, FFT3D_C64, 1, 1, 1) == FFT3D_OK);
+        if (p) {
+            for (int r = 0; r < 13; ++r) {
+                EXPECT(fft3d_poisson(p, f.p, phi.p, nullptr) == FFT3D_OK);
+                EXPECT(fft3d_poisson_backward(p, w.p, g.p, nullptr) == FFT3D_OK);
+            }
+            EXPECT(fft3d_destroy(p) == FFT3D_OK);
+        }
+    }
+    (void)hipStreamDestroy(side);
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
 {
+    if (argc > 1 && strcmp(argv[1], "bench") == 0) {
+        const int nb = argc > 2 ? atoi(argv[2]) : 0;
+        for (int i = 0; i < 3 * nb && 3 + i < argc; ++i) g_batch_dims.push_back(atoll(argv[3 + i]));
+        if (g_batch_dims.empty()) g_batch_dims = {48, 48, 48, 64, 64, 64, 100, 120, 128, 160, 160, 80};
+        const size_t live = hostsim_live_allocations();
+        bench_sequence();
+        EXPECT(hostsim_live_allocations() == live);
+        printf("launches %ld, violations %d, failures %d\n", hostsim_launches(), hostsim_violations(), g_failures);
+        if (hostsim_violations() == 0 && g_failures == 0) {
+            printf("hostsim ok\n");
+            return 0;
+        }
+        return 1;
+    }
     std::vector<int64_t> dims;
     if (argc > 1) {
         const int n = atoi(argv[1]);

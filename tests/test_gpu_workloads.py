@@ -120,13 +120,26 @@ def _edges(bounds, n):
 
 
 def _check_lines(got, want, rms_all, tol, what):
-    """Sampled outputs: their RMS and largest error, both relative to the RMS of
-    all N outputs of the transform (the scale FFT rounding errors follow)."""
+    """Whole sampled z-lines (columns of got/want): the RMS error relative to the
+    RMS of all N outputs, and every output's error relative to the larger of
+    that RMS and the RMS of its own reference z-line.
+
+    The last stage transforms each z-line on its own, so its rounding errors
+    follow the norm of that line, while the earlier stages' errors spread over
+    the outputs at the scale of the whole spectrum.  For white inputs the two
+    scales agree; for the k^-5/3 turbulence spectrum a few lines hold most of
+    the energy and their outputs carry correspondingly larger absolute errors
+    (a mode of ~7000 x the spectral RMS has a one-ulp error of ~5e-4 x that
+    RMS), which the line scale accounts for."""
     d = np.abs(got - want)
     e_rms = float(np.sqrt(np.mean(d ** 2))) / rms_all
-    e_max = float(d.max()) / rms_all
-    print(f"{what}: {got.size} outputs, rms error {e_rms:.3e}, max error {e_max:.3e} "
-          f"(relative to the spectral RMS; bound {tol:.1e})", flush=True)
+    line_rms = np.sqrt(np.mean(np.abs(want) ** 2, axis=0))
+    scale = np.maximum(rms_all, line_rms)[None, :]
+    e_max = float((d / scale).max())
+    e_max_all = float(d.max()) / rms_all
+    print(f"{what}: {got.size} outputs, rms error {e_rms:.3e} (of the spectral RMS), max error "
+          f"{e_max:.3e} (of max(spectral RMS, line RMS); {e_max_all:.3e} of the spectral RMS), "
+          f"bound {tol:.1e}", flush=True)
     assert e_rms <= tol and e_max <= tol, what
 
 
