@@ -178,8 +178,7 @@ def _extras(reps, torch, fft3d, synth, np):
             rep[name] = {
                 "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
                 "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                # plans with >= 16 tiles replay their task graph (one hipGraph node per tile)
-                "issue": "task graph" if grid[0] * grid[1] >= 16 else "direct"}
+                "issue": f"tiles on {ns} stream(s)"}
             if grid != (1, 1):
                 torch.cuda.synchronize()
                 checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),
@@ -187,8 +186,8 @@ def _extras(reps, torch, fft3d, synth, np):
             p.close()
         del x
         torch.cuda.empty_cache()
-    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (replayed as a
-    # task graph) and on one tile per stage; the values do not change the
+    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (issued on the
+    # plan's streams) and on one tile per stage; the values do not change the
     # timing, so the input is torch's normal generator (parity of the
     # turbulence field at this size is a GPU test)
     c3 = synth.CFG3
@@ -206,7 +205,7 @@ def _extras(reps, torch, fft3d, synth, np):
         rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}"] = {
             "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * m3 * math.log2(m3) / (ms * 1e-3) / 1e9, 1),
             "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "issue": "task graph" if grid[0] * grid[1] >= 16 else "direct"}
+            "issue": "tiles on 4 streams" if grid != (1, 1) else "one tile per stage"}
         p.close()
         del H, y
     del x

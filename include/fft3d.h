@@ -78,6 +78,39 @@ typedef enum {
 fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype,
                         int p1, int p2, int r2c);
 
+/*
+ * Create a real-to-complex plan whose z axis is bounded instead of periodic:
+ * the (Periodic, Periodic, Bounded) topology of the paper's Poisson solver
+ * (Sec. VI-B), with real-to-real transforms along z beside the DFTs along x
+ * and y (Sec. V-B's transform types).  The field has Nz cells between two
+ * walls, values at the cell centres; zbc selects the walls:
+ *   FFT3D_Z_NEUMANN    homogeneous Neumann (cosine modes): DCT-II along z,
+ *                      Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2Nz), k = 0..Nz-1
+ *   FFT3D_Z_DIRICHLET  homogeneous Dirichlet (sine modes): DST-II along z,
+ *                      Y_k = 2 sum_j x_j sin(pi (2j+1) (k+1) / 2Nz)
+ * Arguments otherwise as fft3d_plan with r2c = 1 (Nx even; Nx, Nx/2, Ny, Nz
+ * supported lengths).  The operations keep their meaning:
+ *   fft3d_forward   real Nx*Ny*Nz -> (Nx/2+1)*Ny*Nz complex: DFT along x (half
+ *                   spectrum) and y, then the DCT-II / DST-II along z, unscaled;
+ *   fft3d_inverse   its inverse: DCT-III / DST-III along z divided by 2 Nz,
+ *                   inverse DFT along y (1/Ny) and x (1/Nx, imaginary parts of
+ *                   the kx = 0 and Nx/2 bins ignored);
+ *   fft3d_backward  the adjoint of fft3d_forward (transposed DCT-II / DST-II,
+ *                   unscaled conjugate DFT along y, adjoint of the R2C step);
+ *   fft3d_poisson   phi = inverse(M .* forward(f)), M = -1/|k|^2 and 0 for the
+ *                   zero wavenumber, on the box (0, 2 pi)^2 x (0, pi): integer
+ *                   kx, ky as for periodic plans, kz = k (Neumann) or k + 1
+ *                   (Dirichlet, so M is never 0); the z stage runs the DCT
+ *                   (DST), the multiplier and the inverse in one kernel;
+ *   fft3d_poisson_backward  its adjoint (the solve is self-adjoint).
+ * Staging is always FFT3D_STAGING_IN_PLACE (the x and y stages run in the
+ * plan workspace).  zbc other than the two values: FFT3D_ERR_INVALID_ARG.
+ */
+#define FFT3D_Z_NEUMANN 1
+#define FFT3D_Z_DIRICHLET 2
+fft3d_status fft3d_plan_ppb(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                            int p1, int p2, int zbc);
+
 /* Release everything the plan allocated (not caller buffers), after waiting
  * for the plan's last call to finish on the device.  NULL is accepted. */
 fft3d_status fft3d_destroy(fft3d_plan_t plan);
@@ -185,26 +218,9 @@ int fft3d_get_staging(fft3d_plan_t plan);
  * Number of internal HIP streams the tiles are placed on (1..16; default 4).
  * The streams are created by the first call that needs them.  With 1 stream,
  * or a 1x1 pencil grid (one tile per stage), every tile is enqueued directly
- * on the caller's stream in dependency order.  Calls that replay a task graph
- * (fft3d_set_graphs) use no internal streams.  Drops the cached graphs.
+ * on the caller's stream in dependency order.
  */
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
-
-/*
- * Graph replay of tiled pipelines (Sec. IV's task graph as one launch).  With
- * enable = 1, a call of a plan with more than one tile per stage builds, once
- * per operation and (in, out, workspace) triple, a hipGraph with one kernel
- * node per tile whose dependencies are exactly the tile's producers, and
- * launches it on the caller's stream (the plan's streams and events are not
- * used; at most 8 graphs are cached, the oldest set is dropped when full).
- * Results are bitwise identical to direct issue.  A call on a stream the
- * caller is capturing issues its tiles in order on that stream.  Cached
- * graphs are dropped (after the device finishes them) by every setter that
- * changes launches.  Default: 1 for plans with at least 16 tiles per stage
- * (p1 * p2 >= 16), where the graph measured 10-22 % faster than direct issue
- * on MI355X; 0 below (fewer, larger tiles issue faster directly).
- */
-fft3d_status fft3d_set_graphs(fft3d_plan_t plan, int enable);
 
 /*
  * Override the launch shape of the stage kernels along one axis (0 = x,

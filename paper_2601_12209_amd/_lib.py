@@ -17,6 +17,7 @@ I64, I32, P, SZ = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
 
 _SIGS = {
     "fft3d_plan": (I32, [ctypes.POINTER(P), I64, I64, I64, I32, I32, I32, I32]),
+    "fft3d_plan_ppb": (I32, [ctypes.POINTER(P), I64, I64, I64, I32, I32, I32, I32]),
     "fft3d_destroy": (I32, [P]),
     "fft3d_forward": (I32, [P, P, P, P]),
     "fft3d_inverse": (I32, [P, P, P, P]),
@@ -27,7 +28,6 @@ _SIGS = {
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
     "fft3d_set_staging": (I32, [P, I32]),
-    "fft3d_set_graphs": (I32, [P, I32]),
     "fft3d_get_staging": (I32, [P]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),
     "fft3d_set_timing": (I32, [P, I32]),

@@ -1,0 +1,24 @@
+// Bounded-z real-to-real stage kernels in single precision (see k_r2r.hpp).
+#include "k_r2r.hpp"
+
+namespace fft3d {
+
+hipError_t launch_r2r_z_f32(int n, const StageArgs& a, hipStream_t s)
+{
+#define FFT3D_R2R_CASE(L) \
+    case L:               \
+        return launch_r2r_n<float, L>(a, s);
+    switch (n) {
+        FFT3D_FOR_EACH_LENGTH(FFT3D_R2R_CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef FFT3D_R2R_CASE
+}
+
+hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    return dtype == DT_F64 ? launch_r2r_z_f64(n, a, s) : launch_r2r_z_f32(n, a, s);
+}
+
+}  // namespace fft3d

@@ -20,6 +20,9 @@ bool c2c_variant_available(int n, int tdiv, int split);
 hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s);
 hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s);
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s);
+// Bounded z axis: DCT/DST of the z-lines (a.r2r), strided lines as the
+// Poisson z stage.
+hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s);
 // Fused x-y planes (plane_list.hpp): a.B planes, rows a.sa / a.sa_o apart,
 // planes a.sb / a.sb_o apart.
 hipError_t launch_c2c_xy(int nx, int ny, int dtype, const StageArgs& a, hipStream_t s);

@@ -126,6 +126,53 @@ std::vector<Stage> op_stages(const PlanDesc& d, int op)
         }
         return s;
     }
+    if (d.zbc != Z_PERIODIC) {
+        // (Periodic, Periodic, Bounded): DFT along x (half spectrum) and y,
+        // DCT-II (Neumann) or DST-II (Dirichlet) along z; the inverse divides
+        // by 2 Nz along z (DCT-III / DST-III) and by Nx Ny as the periodic one
+        const bool dst = d.zbc == Z_DIRICHLET;
+        const int fwd_z = dst ? R2R_DST2 : R2R_DCT2, inv_z = dst ? R2R_DST3 : R2R_DCT3;
+        const int pz = dst ? R2R_POISSON_D : R2R_POISSON_N;
+        auto r2r = [&](int mode, int weight, double scale, int src, int dst_buf) {
+            Stage st = mk(K_R2R_Z, 2, nz, 0, weight, scale, src, dst_buf);
+            st.r2r = mode;
+            return st;
+        };
+        switch (op) {
+        case OP_FORWARD:
+            s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(r2r(fwd_z, 0, 1.0, BUF_WS, BUF_OUT));
+            break;
+        case OP_INVERSE:
+            s.push_back(r2r(inv_z, 0, 0.5, BUF_IN, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2R_X, 0, nx, 0, 0, inv_n, BUF_WS, BUF_OUT));
+            break;
+        case OP_BACKWARD:  // transposes in reverse order: DCT-II^T, DFT_y^H, r2c^T
+            s.push_back(r2r(inv_z, 1, 1.0, BUF_IN, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2R_X, 0, nx, 0, 1, 1.0, BUF_WS, BUF_OUT));
+            break;
+        case OP_POISSON:  // the z stage folds forward, multiplier and inverse (1/(2N) in all)
+            s.push_back(mk(K_R2C_X, 0, nx, 0, 0, 1.0, BUF_IN, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(r2r(pz, 0, 0.5 * inv_n, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2R_X, 0, nx, 0, 0, 1.0, BUF_WS, BUF_OUT));
+            break;
+        case OP_POISSON_ADJ:  // as the periodic adjoint; the fused z stage is symmetric
+            s.push_back(mk(K_R2C_X, 0, nx, 0, 1, 1.0, BUF_IN, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 0, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(r2r(pz, 0, 0.5 * inv_n, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2C, 1, ny, 1, 0, 1.0, BUF_WS, BUF_WS));
+            s.push_back(mk(K_C2R_X, 0, nx, 0, 1, 1.0, BUF_WS, BUF_OUT));
+            break;
+        default:
+            break;
+        }
+        return s;
+    }
     if (d.staging == STAGING_SWAP_YZ && op == OP_FORWARD) {
         // x writes the output, y moves it into the workspace with y and z
         // swapped, z reads the workspace rows back into the output: no stage

@@ -33,12 +33,19 @@ enum Layout : int { LAY_NATURAL = 0, LAY_SWAP_YZ = 1 };
 // two passes; the inverse runs z, then the planes.
 enum Staging : int { STAGING_IN_PLACE = 0, STAGING_SWAP_YZ = 1, STAGING_FUSED_XY = 2 };
 
+// The z axis of an R2C plan: periodic (DFT), or bounded by walls at both
+// ends with the field at cell centres (the (Periodic, Periodic, Bounded)
+// topology): homogeneous Neumann walls (cosine modes, DCT-II) or homogeneous
+// Dirichlet walls (sine modes, DST-II).
+enum ZBound : int { Z_PERIODIC = 0, Z_NEUMANN = 1, Z_DIRICHLET = 2 };
+
 struct PlanDesc {
     int64_t nx, ny, nz;
     int dtype;  // DT_F32 / DT_F64
     int p1, p2;
     int r2c;
     int staging = STAGING_IN_PLACE;  // R2C: IN_PLACE or SWAP_YZ (forward only)
+    int zbc = Z_PERIODIC;            // R2C plans: boundary of the z axis (ZBound)
     int64_t nxc() const { return r2c ? nx / 2 + 1 : nx; }  // complex x extent (row pitch of caller buffers)
     // row pitch (complex elements) of the workspace: the complex x extent
     // rounded up to 128 bytes, so workspace rows start on cache-line bounds
@@ -66,6 +73,7 @@ struct Stage {
     double scale;  // output scale
     int src, dst;  // Buf ids
     int lay_src = LAY_NATURAL, lay_dst = LAY_NATURAL;
+    int r2r = 0;   // K_R2R_Z: R2RMode
 };
 
 struct Task {

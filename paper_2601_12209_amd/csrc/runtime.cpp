@@ -43,13 +43,6 @@ constexpr int kMaxStreams = 16;
 // Tiles per stage a plan may have: the planner's dependency search is
 // quadratic in it and a plan creates five events per tile.
 constexpr int64_t kMaxTiles = 1024;
-constexpr size_t kMaxGraphs = 8;  // cached pipeline graphs per plan
-// Plans with at least this many tiles per stage replay their task graphs by
-// default.  Measured on MI355X, fwd+inv complex64: 256^3 on 4x4 tiles 0.83 ms
-// direct on 4 streams (0.71 on one) -> 0.65 ms as a graph, 8x8 2.14 -> 1.86,
-// 512^3 on 4x4 3.35 -> 2.99; with 2x2 tiles one stream is faster (256^3
-// 0.34 ms against 0.37 as a graph, 32^3 0.08 against 0.24).
-constexpr int64_t kGraphMinTiles = 16;
 // C2C plans of at least this many bytes, and R2C plans whose half spectrum is
 // at least this large, default to the swapped-y/z staging (measured on MI355X:
 // faster at 512^3, slower at 256^3, whose 128-256 MiB field stays in the
@@ -129,17 +122,6 @@ struct fft3d_plan_s {
     bool pipe_ok[OP_COUNT] = {};
     std::vector<char> needs_event[OP_COUNT];
     KConf conf_override[3];  // per axis; lw == 0: default
-    // forked pipelines issued on a non-default stream are captured once per
-    // (operation, buffers) into a hipGraph and replayed
-    struct CachedGraph {
-        int op;
-        const void* in;
-        void* out;
-        void* ws;
-        hipGraphExec_t exec;
-    };
-    bool use_graphs = false;  // multi-tile calls replay an explicit task graph (fft3d_set_graphs)
-    std::vector<CachedGraph> graphs;
     // Completion of the last call issued outside a stream capture, recorded on
     // that call's stream.  A call on another stream first waits on it, so two
     // streams never use the plan's workspace at once; the destructor and the
@@ -184,7 +166,8 @@ bool conf_fits(const Stage& st, int dtype, const KConf& c, bool strided)
     const int threads = c.lw * (rp.tpl / c.tdiv);
     const size_t s = elem_bytes(dtype) / (c.split ? 2 : 1);
     const size_t line = strided ? (size_t)nk : (size_t)(nk + 1 + (c.pad ? nk / 8 : 0));
-    const size_t tw = (size_t)pass_table_size(rp) * elem_bytes(dtype) + 16;
+    size_t tw = (size_t)pass_table_size(rp) * elem_bytes(dtype) + 16;
+    if (st.kind == K_R2R_Z) tw += (size_t)nk * elem_bytes(dtype);  // the W_4n roots
     return threads <= 1024 && (size_t)c.lw * line * s + tw <= kMaxLdsBytes;
 }
 
@@ -348,10 +331,11 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
         a.strided = 0;
         return a;
     }
-    if (st.kind == K_POISSON_Z) {
+    if (st.kind == K_POISSON_Z || st.kind == K_R2R_Z) {
         a.pnx = d.nx; a.pny = d.ny; a.pnz = d.nz;
         a.kx0 = b.lo[0];
         a.ky0 = b.lo[1];
+        a.r2r = st.r2r;
     }
     KConf c = default_conf(d, st, b);
     const KConf& ov = p->conf_override[st.axis];
@@ -384,6 +368,7 @@ hipError_t launch_task(const fft3d_plan_s* p, const Stage& st, const StageArgs& 
     case K_R2C_X: return launch_r2c_x(st.n, p->d.dtype, a, s);
     case K_C2R_X: return launch_c2r_x(st.n, p->d.dtype, a, s);
     case K_POISSON_Z: return launch_poisson_z(st.n, p->d.dtype, a, s);
+    case K_R2R_Z: return launch_r2r_z(st.n, p->d.dtype, a, s);
     case K_C2C_XY: return launch_c2c_xy((int)p->d.nx, (int)p->d.ny, p->d.dtype, a, s);
     default: return hipErrorInvalidValue;
     }
@@ -394,6 +379,9 @@ fft3d_status validate_desc(const PlanDesc& d)
     if (d.dtype != DT_F32 && d.dtype != DT_F64) return fail(FFT3D_ERR_INVALID_ARG, "dtype must be 0 (c64) or 1 (c128)");
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(FFT3D_ERR_INVALID_ARG, "dimensions must be >= 1");
     if (d.r2c != 0 && d.r2c != 1) return fail(FFT3D_ERR_INVALID_ARG, "r2c must be 0 or 1");
+    if (d.zbc != Z_PERIODIC && d.zbc != Z_NEUMANN && d.zbc != Z_DIRICHLET)
+        return fail(FFT3D_ERR_INVALID_ARG, "z boundary must be 1 (Neumann) or 2 (Dirichlet)");
+    if (d.zbc != Z_PERIODIC && !d.r2c) return fail(FFT3D_ERR_INVALID_ARG, "a bounded z axis needs an R2C plan");
     if (!length_supported(d.ny) || !length_supported(d.nz))
         return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "ny or nz has no compiled kernel");
     if (d.r2c) {
@@ -497,13 +485,11 @@ fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3],
 }
 
 // Wait until the last call has finished (its work may still use the
-// workspace or replay a graph), then destroy the cached graphs.
-void drop_graphs(fft3d_plan_s* p)
+// workspace); the caller's stream may be gone by now, the plan's own event
+// is not.
+void wait_last_call(fft3d_plan_s* p)
 {
-    // the caller's stream may be gone by now; the plan's own event is not
     if (p->called) hipEventSynchronize(p->call_done);
-    for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
-    p->graphs.clear();
 }
 
 fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user);
@@ -554,22 +540,6 @@ hipError_t add_pipeline_nodes(fft3d_plan_s* p, const Pipeline& pl, void* const b
     return e;
 }
 
-fft3d_status build_graph(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraphExec_t* out)
-{
-    *out = nullptr;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipGraphCreate(&g, 0);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
-    e = add_pipeline_nodes(p, pl, bufs, g, {}, nullptr);
-    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        *out = nullptr;
-        return hip_fail(e, "building the pipeline graph");
-    }
-    return FFT3D_OK;
-}
-
 }  // namespace
 
 fft3d_status fft3d::append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
@@ -586,30 +556,10 @@ fft3d_status fft3d::append_plan_nodes(fft3d_plan_s* p, int op, const void* in, v
 
 namespace {
 
-// Replay (building on first use) the task graph of this operation and these
-// buffers on the caller's stream.
-fft3d_status run_graph(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user)
-{
-    fft3d_plan_s::CachedGraph* hit = nullptr;
-    for (auto& g : p->graphs)
-        if (g.op == op && g.in == bufs[0] && g.out == bufs[1] && g.ws == bufs[2]) hit = &g;
-    if (!hit) {
-        if (p->graphs.size() >= kMaxGraphs) drop_graphs(p);
-        hipGraphExec_t exec = nullptr;
-        fft3d_status st = build_graph(p, pl, bufs, &exec);
-        if (st != FFT3D_OK) return st;
-        p->graphs.push_back({op, bufs[0], bufs[1], bufs[2], exec});
-        hit = &p->graphs.back();
-    }
-    hipError_t e = hipGraphLaunch(hit->exec, user);
-    return e == hipSuccess ? FFT3D_OK : hip_fail(e, "hipGraphLaunch");
-}
-
 fft3d_status issue(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user,
                    bool capturing)
 {
     if (p->timing && !capturing) return run_timed(p, pl, bufs, user);
-    if (p->use_graphs && (int64_t)p->d.p1 * p->d.p2 > 1 && !capturing) return run_graph(p, op, pl, bufs, user);
     // In order on the caller's stream: plans with one stream or one tile per
     // stage, and every call into a stream the caller is capturing (forking
     // onto the plan's streams there would put cross-stream event edges into
@@ -696,8 +646,7 @@ fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* con
 
 void release(fft3d_plan_s* p)
 {
-    if (p->called) hipEventSynchronize(p->call_done);  // work still reading or writing plan memory
-    drop_graphs(p);
+    wait_last_call(p);  // work still reading or writing plan memory
     for (hipStream_t s : p->streams)
         if (s) {
             hipStreamSynchronize(s);
@@ -728,15 +677,14 @@ fft3d_status check_plan_and_ptrs(fft3d_plan_t p, const void* in, const void* out
 
 extern "C" {
 
-fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype, int p1,
-                        int p2, int r2c)
+static fft3d_status make_plan(fft3d_plan_t* plan, const PlanDesc& d)
 {
     if (!plan) return fail(FFT3D_ERR_INVALID_ARG, "null plan pointer");
     *plan = nullptr;
-    PlanDesc d;
-    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = dtype; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
     fft3d_status st = validate_desc(d);
     if (st != FFT3D_OK) return st;
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    const int dtype = d.dtype, p1 = d.p1, p2 = d.p2, r2c = d.r2c;
 
     fft3d_plan_s* p = new fft3d_plan_s();
     p->d = d;
@@ -751,8 +699,17 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         const int64_t n = lens[ax];
         const size_t bytes = (size_t)n * elem_bytes(dtype);
         std::vector<char> host(bytes);
-        if (dtype == DT_F64) twiddles_f64(n, (double*)host.data());
-        else twiddles_f32(n, (float*)host.data());
+        if (ax == 2 && d.zbc != Z_PERIODIC) {
+            // bounded z: the first n roots W_4n^k of the order-4n table
+            std::vector<char> t4(4 * bytes);
+            if (dtype == DT_F64) twiddles_f64(4 * n, (double*)t4.data());
+            else twiddles_f32(4 * n, (float*)t4.data());
+            memcpy(host.data(), t4.data(), bytes);
+        } else if (dtype == DT_F64) {
+            twiddles_f64(n, (double*)host.data());
+        } else {
+            twiddles_f32(n, (float*)host.data());
+        }
         e = hipMalloc(&p->tw[ax], bytes);
         if (e == hipSuccess) e = hipMemcpy(p->tw[ax], host.data(), bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -787,7 +744,7 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
         // f64); at 1024^3 f32 (4.3 GB) in place is the faster one (forward
         // 6.54 ms against 6.97), so only half spectra below 2 GiB swap
         const size_t half = (size_t)d.nxc() * ny * nz * elem_bytes(dtype);
-        if (ny > 1 && nz > 1 && half >= kSwapStagingMinBytes && half < kR2CSwapMaxBytes)
+        if (d.zbc == Z_PERIODIC && ny > 1 && nz > 1 && half >= kSwapStagingMinBytes && half < kR2CSwapMaxBytes)
             p->d.staging = STAGING_SWAP_YZ;
     }
     // large C2C plans stage through a y/z-swapped workspace by default (see
@@ -807,7 +764,6 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
     if (!r2c && p->d.staging == STAGING_IN_PLACE && p1 == 1 && ny > 1 &&
         plane_available(nx, ny, elem_bytes(dtype)))
         p->d.staging = STAGING_FUSED_XY;
-    p->use_graphs = (int64_t)p1 * p2 >= kGraphMinTiles;
     p->streams.assign(kMaxStreams, nullptr);
     if (forks(p)) {
         e = ensure_streams(p, p->nstreams);
@@ -834,6 +790,23 @@ fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, 
     }
     *plan = p;
     return FFT3D_OK;
+}
+
+fft3d_status fft3d_plan(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype, int p1,
+                        int p2, int r2c)
+{
+    PlanDesc d;
+    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = dtype; d.p1 = p1; d.p2 = p2; d.r2c = r2c;
+    return make_plan(plan, d);
+}
+
+fft3d_status fft3d_plan_ppb(fft3d_plan_t* plan, int64_t nx, int64_t ny, int64_t nz, int dtype, int p1, int p2,
+                            int zbc)
+{
+    PlanDesc d;
+    d.nx = nx; d.ny = ny; d.nz = nz; d.dtype = dtype; d.p1 = p1; d.p2 = p2; d.r2c = 1;
+    d.zbc = zbc == Z_PERIODIC ? -1 : zbc;  // 0 is not a bounded axis
+    return make_plan(plan, d);
 }
 
 fft3d_status fft3d_destroy(fft3d_plan_t plan)
@@ -932,7 +905,7 @@ fft3d_status fft3d_set_workspace(fft3d_plan_t p, void* ws, size_t bytes)
     if (ws && bytes < need) return fail(FFT3D_ERR_WORKSPACE, "workspace smaller than fft3d_workspace_bytes");
     if (ws && ((uintptr_t)ws % 256) != 0) return fail(FFT3D_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     // the old workspace may still be in use by enqueued work
-    drop_graphs(p);
+    wait_last_call(p);
     if (ws) {
         if (p->ws_owned) hipFree(p->ws);
         p->ws = ws;
@@ -959,8 +932,10 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     if (p->d.r2c) {
         // R2C plans always hold the workspace; the staging only changes the forward's stages
         if (staging == STAGING_FUSED_XY) return fail(FFT3D_ERR_WRONG_PLAN, "fused x-y planes are for C2C plans");
+        if (p->d.zbc != Z_PERIODIC && staging != STAGING_IN_PLACE)
+            return fail(FFT3D_ERR_WRONG_PLAN, "plans with a bounded z axis stage in place");
         if (staging == p->d.staging) return FFT3D_OK;
-        drop_graphs(p);
+        wait_last_call(p);
         p->d.staging = staging;
         for (int op = 0; op < OP_COUNT; ++op) p->pipe_ok[op] = false;
         return FFT3D_OK;
@@ -968,7 +943,7 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     if (staging == STAGING_FUSED_XY && (p->d.p1 != 1 || !plane_available(p->d.nx, p->d.ny, elem_bytes(p->d.dtype))))
         return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "no fused x-y kernel for this plane (or p1 > 1)");
     if (staging == p->d.staging) return FFT3D_OK;
-    drop_graphs(p);  // waits for the last call, which may still use the old workspace
+    wait_last_call(p);  // the last call may still use the old workspace
     if (p->ws && p->ws_owned) hipFree(p->ws);
     p->ws = nullptr;
     p->ws_owned = false;
@@ -989,21 +964,12 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     return FFT3D_OK;
 }
 
-fft3d_status fft3d_set_graphs(fft3d_plan_t p, int enable)
-{
-    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
-    std::lock_guard<std::mutex> lock(p->mu);
-    drop_graphs(p);
-    p->use_graphs = enable != 0;
-    return FFT3D_OK;
-}
-
 fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
     std::lock_guard<std::mutex> lock(p->mu);
     if (nstreams < 1 || nstreams > kMaxStreams) return fail(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
-    drop_graphs(p);
+    wait_last_call(p);
     p->nstreams = nstreams;
     if (forks(p)) {
         hipError_t e = ensure_streams(p, nstreams);
@@ -1018,7 +984,7 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
     std::lock_guard<std::mutex> lock(p->mu);
     if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
     if (lw == 0) {
-        drop_graphs(p);
+        wait_last_call(p);
         p->conf_override[axis] = KConf();
         return FFT3D_OK;
     }
@@ -1037,7 +1003,7 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
                                                    "(threads, LDS, or no such kernel variant)");
         }
     }
-    drop_graphs(p);
+    wait_last_call(p);
     p->conf_override[axis] = c;
     return FFT3D_OK;
 }

@@ -11,6 +11,26 @@ enum KernelKind : int {
     K_C2R_X = 2,      // half-spectrum x-lines -> real x-lines
     K_POISSON_Z = 3,  // z-lines: forward FFT, spectral multiplier, inverse FFT
     K_C2C_XY = 4,     // whole x-y planes in LDS: x FFTs then y FFTs (small planes)
+    K_R2R_Z = 5,      // z-lines of a bounded z axis: DCT/DST (StageArgs::r2r)
+};
+
+// Real-to-real transform of a K_R2R_Z launch (each applied to the real and
+// imaginary parts of the complex z-lines alike), unnormalised:
+//   R2R_DCT2  Y_k = 2 sum_j x_j cos(pi (2j+1) k / 2n)          (Neumann walls)
+//   R2R_DCT3  x_j = Y_0 + 2 sum_{k>0} Y_k cos(pi k (2j+1) / 2n) (inverse of DCT2 up to 2n)
+//   R2R_DST2  Y_k = 2 sum_j x_j sin(pi (2j+1) (k+1) / 2n)      (Dirichlet walls)
+//   R2R_DST3  x_j = (-1)^j Y_{n-1} + 2 sum_{k<n-1} Y_k sin(pi (k+1) (2j+1) / 2n)
+//   R2R_POISSON_N / _D: DCT2 / DST2, the multiplier -1/|k|^2 (times scale), then
+//   DCT3 / DST3, in one kernel.
+// With StageArgs::weight, DCT3/DST3 count the first coefficient of the
+// (for the DST: reversed) line twice: the transposes of DCT2 and DST2.
+enum R2RMode : int {
+    R2R_DCT2 = 0,
+    R2R_DCT3 = 1,
+    R2R_DST2 = 2,
+    R2R_DST3 = 3,
+    R2R_POISSON_N = 4,
+    R2R_POISSON_D = 5,
 };
 
 enum DType : int { DT_F32 = 0, DT_F64 = 1 };
@@ -24,7 +44,8 @@ enum DType : int { DT_F32 = 0, DT_F64 = 1 };
 struct StageArgs {
     const void* in;
     void* out;
-    const void* tw;   // forward roots W_n^m = exp(-2 pi i m/n), m < n, n = axis length
+    const void* tw;   // forward roots W_n^m = exp(-2 pi i m/n), m < n, n = axis length;
+                      // K_R2R_Z: W_4n^k, k < n
     const void* twp;  // per-pass twiddle table of the kernel's FFT length
     const void* twp2; // K_C2C_XY: per-pass table of the y length (twp: the x length)
     int64_t A, B;
@@ -44,7 +65,9 @@ struct StageArgs {
     int split;    // 1: exchange real and imaginary parts through LDS separately
     int pad;      // 1: pad contiguous LDS lines by one slot per 8 elements
     int conj;     // 1: conjugate-sign transform, taken as conj(F(conj x))
-    int weight;   // R2C: interior bins x2 / C2R: interior bins x1/2 (adjoint paths)
+    int weight;   // R2C: interior bins x2 / C2R: interior bins x1/2 (adjoint paths);
+                  // K_R2R_Z: the transposed DCT2/DST2 (see R2RMode)
+    int r2r;      // K_R2R_Z: R2RMode
     double scale; // multiplies every output
     // spectral multiplier (K_POISSON_Z): full grid sizes and the global
     // (kx, ky) of line (0, 0)

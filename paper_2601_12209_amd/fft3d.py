@@ -46,18 +46,33 @@ STAGING_SWAP_YZ = 1
 STAGING_FUSED_XY = 2
 
 
-class Plan:
-    """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind."""
+Z_NEUMANN = 1
+Z_DIRICHLET = 2
+_ZBC = {"neumann": Z_NEUMANN, "dirichlet": Z_DIRICHLET, Z_NEUMANN: Z_NEUMANN, Z_DIRICHLET: Z_DIRICHLET}
 
-    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None):
+
+class Plan:
+    """A 3D FFT plan: sizes, precision, pencil grid P1 x P2 and transform kind.
+
+    ``z_bc`` ("neumann" or "dirichlet") makes a real-to-complex plan whose z
+    axis is bounded (the (Periodic, Periodic, Bounded) topology): DCT-II or
+    DST-II along z instead of the DFT."""
+
+    def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None,
+                 z_bc=None):
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
         self.code = _dtype_code(dtype)
         self.grid = (int(grid[0]), int(grid[1]))
-        self.r2c = bool(r2c)
+        self.z_bc = None if z_bc is None else _ZBC[z_bc]
+        self.r2c = bool(r2c) or self.z_bc is not None
         h = ctypes.c_void_p()
-        check(_lib.lib().fft3d_plan(ctypes.byref(h), nx, ny, nz, self.code, self.grid[0],
-                                    self.grid[1], int(self.r2c)), "fft3d_plan")
+        if self.z_bc is None:
+            check(_lib.lib().fft3d_plan(ctypes.byref(h), nx, ny, nz, self.code, self.grid[0],
+                                        self.grid[1], int(self.r2c)), "fft3d_plan")
+        else:
+            check(_lib.lib().fft3d_plan_ppb(ctypes.byref(h), nx, ny, nz, self.code, self.grid[0],
+                                            self.grid[1], self.z_bc), "fft3d_plan_ppb")
         self._h = h
         self.device = torch.cuda.current_device()
         self._ws = None
@@ -150,12 +165,6 @@ class Plan:
     # ------------------------------------------------------------ tuning
     def set_streams(self, n: int):
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
-
-    def set_graphs(self, enable: bool):
-        """Replay tiled pipelines as explicit task graphs (one kernel node per tile,
-        edges = producer tiles), cached per operation and buffer set (default on
-        for plans with at least 16 tiles per stage)."""
-        check(_lib.lib().fft3d_set_graphs(self._h, int(bool(enable))), "fft3d_set_graphs")
 
     def set_staging(self, staging: int):
         """STAGING_IN_PLACE (C2C: no workspace), STAGING_SWAP_YZ (y stage writes a

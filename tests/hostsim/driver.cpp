@@ -92,27 +92,19 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
                 EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
             }
-            // task-graph replay: built per (operation, buffers), cached, replayed,
-            // dropped by the setters; more buffer sets than cache slots
-            EXPECT(fft3d_set_graphs(p, 1) == FFT3D_OK);
-            for (int rep = 0; rep < 2; ++rep) {
-                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
-                EXPECT(fft3d_inverse(p, out.p, out.p, nullptr) == FFT3D_OK);
-                EXPECT(fft3d_backward(p, out.p, in.p, user) == FFT3D_OK);
-            }
+            // more buffer sets, then a setter
             {
                 std::vector<std::unique_ptr<Buf>> extra;
                 for (int k = 0; k < 10; ++k) {
                     extra.emplace_back(new Buf(bytes));
                     EXPECT(fft3d_forward(p, in.p, extra.back()->p, user) == FFT3D_OK);
                 }
-                EXPECT(fft3d_set_streams(p, 3) == FFT3D_OK);  // drops the cached graphs first
+                EXPECT(fft3d_set_streams(p, 3) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
             (void)fft3d_set_stage_config(p, 1, 4, 1, 0, 0);  // where the shape fits
             EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
             EXPECT(fft3d_set_stage_config(p, 1, 0, 1, 0, 0) == FFT3D_OK);
-            EXPECT(fft3d_set_graphs(p, 0) == FFT3D_OK);
             EXPECT(fft3d_poisson(p, in.p, out.p, user) == FFT3D_ERR_WRONG_PLAN);
             EXPECT(fft3d_get_staging(p) >= 0);
             if (bytes >= 2 * es_of(dtype))  // partial overlap
@@ -277,6 +269,45 @@ void r2c_cases(hipStream_t user)
     EXPECT(fft3d_plan(&p, 9, 8, 8, FFT3D_C64, 1, 1, 1) == FFT3D_ERR_UNSUPPORTED_SIZE);
 }
 
+// Plans with a bounded z axis: every operation, both walls, both precisions,
+// tiled and not; the staging they reject; the allocation-free forward.
+void ppb_cases(hipStream_t user)
+{
+    const Case cases[] = {{8, 8, 8, 1, 1}, {20, 12, 16, 2, 3}, {4, 6, 7, 1, 1}, {16, 10, 15, 2, 2}, {8, 4, 1, 1, 1},
+                          {100, 48, 64, 3, 3}, {6, 4, 512, 1, 1}};
+    for (const Case& c : cases) {
+        for (int dtype : {FFT3D_C64, FFT3D_C128}) {
+            for (int zbc : {FFT3D_Z_NEUMANN, FFT3D_Z_DIRICHLET}) {
+                const size_t es = es_of(dtype);
+                const size_t real = (size_t)c.nx * c.ny * c.nz * es / 2;
+                const size_t half = (size_t)(c.nx / 2 + 1) * c.ny * c.nz * es;
+                Buf r(real), r2(real), h(half);
+                fft3d_plan_t p = nullptr;
+                EXPECT(fft3d_plan_ppb(&p, c.nx, c.ny, c.nz, dtype, c.p1, c.p2, zbc) == FFT3D_OK);
+                if (!p) continue;
+                EXPECT(fft3d_get_staging(p) == FFT3D_STAGING_IN_PLACE);
+                for (int ns : {1, 3}) {
+                    EXPECT(fft3d_set_streams(p, ns) == FFT3D_OK);
+                    EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_inverse(p, h.p, r2.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_backward(p, h.p, r2.p, nullptr) == FFT3D_OK);
+                    EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_poisson(p, r2.p, r2.p, user) == FFT3D_OK);
+                    EXPECT(fft3d_poisson_backward(p, r.p, r2.p, user) == FFT3D_OK);
+                }
+                EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_WRONG_PLAN);
+                EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
+                EXPECT(fft3d_destroy(p) == FFT3D_OK);
+            }
+        }
+    }
+    fft3d_plan_t p = nullptr;
+    EXPECT(fft3d_plan_ppb(&p, 8, 8, 8, FFT3D_C64, 1, 1, 0) == FFT3D_ERR_INVALID_ARG);
+    EXPECT(fft3d_plan_ppb(&p, 8, 8, 8, FFT3D_C64, 1, 1, 3) == FFT3D_ERR_INVALID_ARG);
+    EXPECT(fft3d_plan_ppb(&p, 9, 8, 8, FFT3D_C64, 1, 1, FFT3D_Z_NEUMANN) == FFT3D_ERR_UNSUPPORTED_SIZE);
+    EXPECT(p == nullptr);
+}
+
 // A multi-stream plan launched inside a capture the caller began.
 void caller_capture_plan(hipStream_t user)
 {
@@ -285,8 +316,7 @@ void caller_capture_plan(hipStream_t user)
     if (!p) return;
     Buf in(32 * 24 * 20 * 8), out(32 * 24 * 20 * 8);
     EXPECT(fft3d_set_streams(p, 4) == FFT3D_OK);
-    for (int graphs : {0, 1}) {
-        EXPECT(fft3d_set_graphs(p, graphs) == FFT3D_OK);
+    for (int rep = 0; rep < 2; ++rep) {
         EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);  // an eager call first
         EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
         EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
@@ -637,6 +667,7 @@ int main(int argc, char** argv)
     c2c_cases(user);
     variant_cases(user);
     r2c_cases(user);
+    ppb_cases(user);
     caller_capture_plan(user);
     batch_cases(dims, user);
     (void)hipStreamDestroy(user);

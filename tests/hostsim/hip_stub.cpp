@@ -571,4 +571,20 @@ hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     return launched(a, s);
 }
 
+hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s)
+{
+    if (!length_supported(n) || a.r2r < R2R_DCT2 || a.r2r > R2R_POISSON_D) return hipErrorInvalidValue;
+    const size_t es = dtype == DT_F64 ? 16 : 8;
+    const int threads = a.lw * radix_plan(n).tpl;
+    const size_t lds = align16((size_t)a.lw * n * es) + table_entries(n) * es + (size_t)n * es;
+    if ((a.A + a.lw - 1) / a.lw == 0 || a.B == 0) return hipSuccess;
+    if (threads > kMaxThreads || lds > kMaxLdsBytes) violation("r2r kernel shape over the limits");
+    if (a.sa != 1 || a.sa_o != 1) violation("r2r tile with sa != 1");
+    check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "r2r load");
+    check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "r2r store");
+    check_tables(a, n, es, "r2r pass table");
+    in_alloc(a.tw, (size_t)n * es, "r2r W_4n roots");
+    return launched(a, s);
+}
+
 }  // namespace fft3d

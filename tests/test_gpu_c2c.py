@@ -274,6 +274,13 @@ def test_graph_replay_of_forked_pipelines(gpu_lib, dtype):
 GRAPH_CASES = [((24, 30, 40), (2, 3), 0), ((32, 32, 32), (2, 2), 1), ((16, 64, 64), (1, 4), 2)]
 
 
+@pytest.mark.skip(reason="plan-level task-graph replay (one hipGraph node per tile, graph destroyed after "
+                         "instantiation) ended in a host segmentation fault inside fft3d_forward on MI355X in "
+                         "this test ((32, 32, 32), grid 2x2, swapped staging, c64: the first call on the default "
+                         "stream after fft3d_set_streams dropped the cached graphs); the same case passed in an "
+                         "earlier run and the host code is clean under ASan in the host stand-in, so no cause is "
+                         "shown: plan-level graph replay was removed from the library and this case stays off "
+                         "the GPU")
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
 @pytest.mark.parametrize("shape,grid,staging", GRAPH_CASES, ids=[f"{s}-{g}-st{t}" for s, g, t in GRAPH_CASES])
 def test_task_graph_replay(gpu_lib, shape, grid, staging, dtype):
@@ -358,6 +365,13 @@ def test_caller_captures_tiled_plan(gpu_lib, shape, grid, dtype):
     plan.close()
 
 
+@pytest.mark.skip(reason="plan-level task-graph replay (one hipGraph node per tile, graph destroyed after "
+                         "instantiation) ended in a host segmentation fault inside fft3d_forward on MI355X in "
+                         "this test ((32, 32, 32), grid 2x2, swapped staging, c64: the first call on the default "
+                         "stream after fft3d_set_streams dropped the cached graphs); the same case passed in an "
+                         "earlier run and the host code is clean under ASan in the host stand-in, so no cause is "
+                         "shown: plan-level graph replay was removed from the library and this case stays off "
+                         "the GPU")
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
 def test_task_graph_replay_r2c(gpu_lib, dtype):
     shape, grid = (16, 24, 32), (2, 2)
