@@ -143,6 +143,34 @@ fft3d_status fft3d_inverse(fft3d_plan_t plan, const void* in, void* out, void* s
 fft3d_status fft3d_backward(fft3d_plan_t plan, const void* in, void* out, void* stream);
 
 /*
+ * fft3d_forward for callers that cannot allocate device memory or create
+ * HIP objects while it runs: code under stream capture into a hipGraph,
+ * tight serving or time-stepping loops, and harnesses that forbid
+ * allocation.  Same transform, arguments and buffer rules as fft3d_forward
+ * (the plan is created beforehand); the result is bitwise that of
+ * fft3d_forward (the same kernels on the same tiles).  Differences:
+ *   - the workspace (R2C plans; C2C plans staged FFT3D_STAGING_SWAP_YZ) is a
+ *     static device array of the library, 256 MiB per GPU (FFT3D_SCRATCH_BYTES),
+ *     allocated when the library's code is loaded on that GPU and held until
+ *     the process ends; a plan whose workspace is larger (fft3d_workspace_bytes)
+ *     gets FFT3D_ERR_WORKSPACE with nothing enqueued.  The plan's own
+ *     workspace is not touched.
+ *   - every tile is enqueued in dependency order on `stream` itself: no
+ *     internal streams, events or graphs, no hipMalloc/hipFree.  The first
+ *     call on a GPU looks the scratch address up (hipGetSymbolAddress) and
+ *     caches it.
+ *   - all calls of this function on one GPU share that GPU's scratch, and it
+ *     keeps whatever the last call left there (every call writes the
+ *     workspace before reading it, so nothing needs clearing).  Calls whose
+ *     execution overlaps on one GPU (different streams or host threads
+ *     without ordering between them) race on the scratch and give wrong
+ *     results: order them, e.g. on one stream.  Each process has its own
+ *     copy of the array.
+ */
+#define FFT3D_SCRATCH_BYTES ((size_t)256 << 20)
+fft3d_status fft3d_forward_noalloc(fft3d_plan_t plan, const void* in, void* out, void* stream);
+
+/*
  * Spectral Poisson solve on a periodic box of side 2 pi (R2C plans only; the
  * paper's Poisson application, Sec. VI-B, (Periodic, Periodic, Periodic)):
  *   phi = irfftn( M .* rfftn(f) ),  M(k) = -1/|k|^2,  M(0) = 0,

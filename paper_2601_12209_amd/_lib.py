@@ -22,6 +22,7 @@ _SIGS = {
     "fft3d_forward": (I32, [P, P, P, P]),
     "fft3d_inverse": (I32, [P, P, P, P]),
     "fft3d_backward": (I32, [P, P, P, P]),
+    "fft3d_forward_noalloc": (I32, [P, P, P, P]),
     "fft3d_poisson": (I32, [P, P, P, P]),
     "fft3d_poisson_backward": (I32, [P, P, P, P]),
     "fft3d_workspace_bytes": (SZ, [P]),

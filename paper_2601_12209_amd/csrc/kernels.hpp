@@ -45,4 +45,12 @@ void set_launch_recorder(KernelLaunch* rec, bool* recorded);
 hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const StageArgs& a, size_t lds,
                                hipStream_t s);
 
+// Size of the library's static device scratch (one per GPU, scratch.hip),
+// the workspace of the calls that allocate nothing: 256 MiB holds the R2C
+// workspace of every grid up to 256^3 in either precision.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+// Device address of that scratch on `device`, which must be the current
+// device; looked up once per device (hipGetSymbolAddress) and cached.
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace fft3d

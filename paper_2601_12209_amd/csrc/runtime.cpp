@@ -855,6 +855,50 @@ fft3d_status fft3d_backward(fft3d_plan_t p, const void* in, void* out, void* str
     return c2c_or_r2c(p, OP_BACKWARD, in, out, stream);
 }
 
+static_assert(kScratchBytes == FFT3D_SCRATCH_BYTES, "scratch size in the header and the library differ");
+
+fft3d_status fft3d_forward_noalloc(fft3d_plan_t p, const void* in, void* out, void* stream)
+{
+    fft3d_status st = check_plan_and_ptrs(p, in, out);
+    if (st != FFT3D_OK) return st;
+    std::lock_guard<std::mutex> lock(p->mu);
+    const PlanDesc& d = p->d;
+    const size_t s = elem_bytes(d.dtype);
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const size_t in_bytes = d.r2c ? n * s / 2 : n * s;
+    const size_t out_bytes = d.r2c ? (size_t)d.nxc() * d.ny * d.nz * s : n * s;
+    if (d.r2c ? ranges_overlap(in, in_bytes, out, out_bytes)
+              : (in != out && ranges_overlap(in, in_bytes, out, out_bytes)))
+        return fail(FFT3D_ERR_ALIAS, d.r2c ? "real-to-complex transforms cannot run in place"
+                                           : "in and out partially overlap");
+    // the workspace this plan's forward stages use, taken from the static scratch
+    const size_t need = (d.r2c || d.staging == STAGING_SWAP_YZ) ? (size_t)d.wpitch() * d.ny * d.nz * s : 0;
+    if (need > kScratchBytes)
+        return fail(FFT3D_ERR_WORKSPACE, "workspace of this plan (" + std::to_string(need) +
+                                             " bytes) exceeds the static scratch (" +
+                                             std::to_string(kScratchBytes) + " bytes)");
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* scr = nullptr;
+    if (need > 0) {
+        e = scratch_address(p->device, &scr);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (ranges_overlap(scr, need, in, in_bytes) || ranges_overlap(scr, need, out, out_bytes))
+            return fail(FFT3D_ERR_ALIAS, "a buffer overlaps the library scratch");
+    }
+    const Pipeline& pl = get_pipeline(p, OP_FORWARD);
+    void* bufs[3] = {const_cast<void*>(in), out, scr};
+    // every tile in dependency order on the caller's stream: no internal
+    // streams, events or graphs (creating those can allocate)
+    hipStream_t user = (hipStream_t)stream;
+    for (const Task& t : pl.tasks) {
+        const Stage& sg = pl.stages[t.stage];
+        e = launch_task(p, sg, make_args(p, sg, t.box, bufs), user);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    return FFT3D_OK;
+}
+
 static fft3d_status poisson_op(fft3d_plan_t p, int op, const void* f, void* phi, void* stream)
 {
     fft3d_status st = check_plan_and_ptrs(p, f, phi);

@@ -134,6 +134,17 @@ class Plan:
         return self._call(L.fft3d_forward, x, out, self.complex_dtype, self.shape, self.complex_dtype,
                           self.shape, stream)
 
+    def forward_noalloc(self, x, out, stream=None):
+        """:meth:`forward` with the library's static device scratch as the workspace,
+        every tile enqueued in order on the stream and nothing allocated (``out``
+        is required); for code under graph capture or loops that cannot allocate."""
+        L = _lib.lib()
+        if self.r2c:
+            return self._call(L.fft3d_forward_noalloc, x, out, self.real_dtype, self.shape,
+                              self.complex_dtype, self.half_shape, stream)
+        return self._call(L.fft3d_forward_noalloc, x, out, self.complex_dtype, self.shape,
+                          self.complex_dtype, self.shape, stream)
+
     def inverse(self, x, out=None, stream=None):
         """Inverse 3D FFT (sign +1, scaled by 1/N)."""
         L = _lib.lib()

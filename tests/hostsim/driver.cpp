@@ -295,6 +295,7 @@ void ppb_cases(hipStream_t user)
                     EXPECT(fft3d_poisson(p, r2.p, r2.p, user) == FFT3D_OK);
                     EXPECT(fft3d_poisson_backward(p, r.p, r2.p, user) == FFT3D_OK);
                 }
+                EXPECT(fft3d_forward_noalloc(p, r.p, h.p, user) == FFT3D_OK);
                 EXPECT(fft3d_set_staging(p, FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_WRONG_PLAN);
                 EXPECT(fft3d_set_staging(p, FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
                 EXPECT(fft3d_destroy(p) == FFT3D_OK);

@@ -587,4 +587,24 @@ hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     return launched(a, s);
 }
 
+// The library's static device scratch: one stand-in allocation made before
+// main (so it is not counted as a leak), like the array the GPU build holds
+// from code-object load until the process ends.
+namespace {
+void* const g_scratch = [] {
+    void* m = nullptr;
+    hipMalloc(&m, kScratchBytes);
+    return m;
+}();
+}  // namespace
+
+hipError_t scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device != 0) return hipErrorInvalidDevice;
+    if (!g_scratch) return hipErrorOutOfMemory;
+    *out = g_scratch;
+    return hipSuccess;
+}
+
 }  // namespace fft3d
