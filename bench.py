@@ -168,44 +168,51 @@ def _extras(reps, torch, fft3d, synth, np):
     for dt, tag, es in ((torch.complex64, "c64", 8), (torch.complex128, "c128", 16)):
         _progress(f"extras: 256^3 c2c {tag}")
         x = torch.from_numpy(a).to("cuda", dt)
-        for grid, ns in ((tuple(cfg["grid"]), 4), ((1, 1), 1)):
-            p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns)
+        g2 = tuple(cfg["grid"])
+        for grid, ns, issue, suffix in ((g2, 4, fft3d.ISSUE_STAGES, ""), (g2, 4, fft3d.ISSUE_TILES, "_tiles"),
+                                        ((1, 1), 1, fft3d.ISSUE_STAGES, "")):
+            p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns, issue=issue)
             X = p.forward(x)
             Y = torch.empty_like(X)
             with torch.cuda.stream(side):
                 ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), reps, torch)
-            name = f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}"
+            name = f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}{suffix}"
             rep[name] = {
                 "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
                 "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "issue": f"tiles on {ns} stream(s)"}
-            if grid != (1, 1):
+                "issue": (f"tiles on {ns} stream(s)" if issue == fft3d.ISSUE_TILES or grid == (1, 1)
+                          else "one grouped launch per stage")}
+            if grid != (1, 1) and issue == fft3d.ISSUE_STAGES:
                 torch.cuda.synchronize()
                 checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),
                                lambda: _oracle().fftn(a.astype(np.complex128))))
             p.close()
         del x
         torch.cuda.empty_cache()
-    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (issued on the
-    # plan's streams) and on one tile per stage; the values do not change the
+    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (one grouped
+    # launch per stage, and one launch per tile on the plan's streams) and on
+    # one tile per stage; the values do not change the
     # timing, so the input is torch's normal generator (parity of the
     # turbulence field at this size is a GPU test)
     c3 = synth.CFG3
     m3 = int(np.prod(c3["shape"]))
     nh3 = (c3["shape"][2] // 2 + 1) * c3["shape"][0] * c3["shape"][1]
     x = torch.randn(c3["shape"], dtype=torch.float32, device="cuda")
-    for grid in (tuple(c3["grid"]), (1, 1)):
-        _progress(f"extras: 1024^3 r2c grid {grid}")
-        p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True)
+    g3 = tuple(c3["grid"])
+    for grid, issue, suffix in ((g3, fft3d.ISSUE_STAGES, ""), (g3, fft3d.ISSUE_TILES, "_tiles"),
+                                ((1, 1), fft3d.ISSUE_STAGES, "")):
+        _progress(f"extras: 1024^3 r2c grid {grid}{suffix}")
+        p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True, issue=issue)
         H = p.forward(x)
         y = torch.empty_like(x)
         with torch.cuda.stream(side):
             ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), max(3, reps // 2), torch)
         bytes_moved = 2 * m3 * 4 + 10 * nh3 * 2 * 4
-        rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}"] = {
+        rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}{suffix}"] = {
             "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * m3 * math.log2(m3) / (ms * 1e-3) / 1e9, 1),
             "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "issue": "tiles on 4 streams" if grid != (1, 1) else "one tile per stage"}
+            "issue": ("one tile per stage" if grid == (1, 1) else
+                      "tiles on 4 streams" if issue == fft3d.ISSUE_TILES else "one grouped launch per stage")}
         p.close()
         del H, y
     del x
@@ -227,7 +234,8 @@ def _extras(reps, torch, fft3d, synth, np):
     p.close()
     del x, X, Y
     torch.cuda.empty_cache()
-    # 64 uneven transforms issued as one task graph, on a non-default stream
+    # 64 uneven transforms, one grouped launch per shape and stage, on a
+    # non-default stream
     _progress("extras: 64 uneven transforms")
     shapes = synth.batch_sizes()
     host = synth.batch_inputs(shapes, synth.CFG4["seed"])
@@ -263,7 +271,7 @@ def _extras(reps, torch, fft3d, synth, np):
     autotune.tune_batch(bp, reps=5)
     with torch.cuda.stream(side):
         ms = _time(lambda: bp.forward(xs, outs), reps, torch)
-    brep["task_graph"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+    brep["grouped"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
                           "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     bp.close()
     # for comparison: the same transforms one after another, each through its own

@@ -251,14 +251,41 @@ int fft3d_get_staging(fft3d_plan_t plan);
 fft3d_status fft3d_set_streams(fft3d_plan_t plan, int nstreams);
 
 /*
+ * How a plan with more than one tile per stage issues its tiles (the tasks
+ * of Alg. 1, Sec. IV-D):
+ *   FFT3D_ISSUE_TILES   one kernel launch per tile, placed on the plan's
+ *                       streams (Alg. 3 placement) with one event wait per
+ *                       producer tile on another stream, forked from and
+ *                       joined back to the caller's stream: a tile starts as
+ *                       soon as the tiles it reads are done;
+ *   FFT3D_ISSUE_STAGES  (default) the tiles of each stage as one launch on the
+ *                       caller's stream: every workgroup finds its tile in a
+ *                       table the plan keeps on the device, so all tiles of a
+ *                       stage are ready together (the task graph with every
+ *                       stage's tiles released at once).  Stages whose tiles
+ *                       need different kernels or launch shapes fall back to
+ *                       one launch per tile, in order.  The first call of an
+ *                       operation uploads its tables (a blocking copy).
+ * Results are bitwise identical.  A call into a stream the caller is
+ * capturing issues its tiles in order on that stream in either mode.
+ */
+#define FFT3D_ISSUE_TILES 0
+#define FFT3D_ISSUE_STAGES 1
+fft3d_status fft3d_set_issue(fft3d_plan_t plan, int mode);
+/* The plan's issue mode, or -1 for a NULL plan. */
+int fft3d_get_issue(fft3d_plan_t plan);
+
+/*
  * Override the launch shape of the stage kernels along one axis (0 = x,
  * 1 = y, 2 = z) of this plan: lw lines per workgroup (a power of two; 0
  * restores the default shape), tdiv divides the threads that cooperate on one
  * line (each then takes tdiv times more butterflies), split = 1 exchanges real
  * and imaginary parts through LDS one after the other (half the LDS), pad = 1
- * pads contiguous LDS lines against bank conflicts.  FFT3D_ERR_INVALID_ARG if
- * any stage kernel of that axis cannot run with it.  Used by the autotuner;
- * results do not depend on the shape beyond rounding order.
+ * pads contiguous LDS lines against bank conflicts.  Stage kernels of that
+ * axis that cannot run with the shape (thread or LDS limits, no such kernel
+ * variant, e.g. the fused Poisson z stage) keep their default shape;
+ * FFT3D_ERR_INVALID_ARG if none of them can.  Used by the autotuner; results
+ * do not depend on the shape (the same arithmetic, bitwise).
  */
 fft3d_status fft3d_set_stage_config(fft3d_plan_t plan, int axis, int lw, int tdiv, int split, int pad);
 

@@ -28,6 +28,8 @@ _SIGS = {
     "fft3d_workspace_bytes": (SZ, [P]),
     "fft3d_set_workspace": (I32, [P, P, SZ]),
     "fft3d_set_streams": (I32, [P, I32]),
+    "fft3d_set_issue": (I32, [P, I32]),
+    "fft3d_get_issue": (I32, [P]),
     "fft3d_set_staging": (I32, [P, I32]),
     "fft3d_get_staging": (I32, [P]),
     "fft3d_set_stage_config": (I32, [P, I32, I32, I32, I32, I32]),

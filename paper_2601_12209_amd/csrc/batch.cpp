@@ -1,12 +1,11 @@
-// C ABI of batched transforms: many independent, unevenly sized 3D FFTs
-// issued as one task graph.  Every transform runs the x, y, z stage kernels of
-// the single-transform plan of its shape; the transforms' stage kernels are
-// appended node by node to one hipGraph per operation and pointer set (a chain
-// of producer edges per transform, no edges between transforms), which is
-// replayed, so the runtime overlaps the stages of different transforms with
-// no barrier between them (the paper's dynamically scheduled FFT tasks,
-// Sec. III-C and IV-D).  Transforms are appended largest first (the order of
-// the paper's Alg. 3 placement).
+// C ABI of batched transforms: many independent, unevenly sized 3D FFTs.
+// Every transform runs the stage kernels of the single-transform plan of its
+// shape.  A call issues, stage by stage, one grouped launch per shape: the
+// stage-s tiles of every transform of that shape in one kernel launch whose
+// workgroups find their transform's buffers and tile in a device table (the
+// paper's FFT tasks over uneven work, Sec. III-C and IV-D, released a stage at
+// a time; shapes largest first, the order of Alg. 3's placement).  The tables
+// of a pointer set are built on its first call and cached.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -21,31 +20,34 @@
 
 #include "../../include/fft3d.h"
 #include "fft_lengths.hpp"
+#include "kernels.hpp"
 #include "plan.hpp"
 #include "stage_args.hpp"
 
 namespace fft3d {
 fft3d_status set_error(fft3d_status st, const std::string& msg);  // runtime.cpp
 fft3d_status set_hip_error(hipError_t e, const char* what);       // runtime.cpp
-fft3d_status append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
-                               const std::vector<hipGraphNode_t>& after,
-                               std::vector<hipGraphNode_t>* tail);  // runtime.cpp
+fft3d_status record_stage(fft3d_plan_s* p, int op, int stage, const void* in, void* out,
+                          std::vector<KernelLaunch>* launches);  // runtime.cpp
+int stage_count(fft3d_plan_s* p, int op);                        // runtime.cpp
 }  // namespace fft3d
 
 using namespace fft3d;
 
 namespace {
 
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxCached = 8;  // pointer sets with launch tables kept per batch
 
 using Shape = std::tuple<int64_t, int64_t, int64_t>;
 
-struct CachedGraph {
+// The launches of one operation on one pointer set, in issue order; grouped
+// launches point at the set's device table.
+struct CachedIssue {
     int op;
     std::vector<const void*> in;
     std::vector<void*> out;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<KernelLaunch> launches;
+    TileEntry* dev = nullptr;
 };
 
 }  // namespace
@@ -56,7 +58,7 @@ struct fft3d_batch_s {
     int device = 0;
     std::map<Shape, fft3d_plan_t> plans;  // one single-stream plan per distinct shape
     std::vector<int> order;               // transforms in decreasing cost (issue order)
-    std::vector<CachedGraph> graphs;
+    std::vector<CachedIssue> cache;
     hipEvent_t done = nullptr;  // recorded on the caller's stream after each call
 };
 
@@ -70,33 +72,17 @@ void wait_done(fft3d_batch_s* b)
     if (b->done) hipEventSynchronize(b->done);
 }
 
-void drop_graphs(fft3d_batch_s* b)
+void drop_cache(fft3d_batch_s* b)
 {
     wait_done(b);
-    for (auto& g : b->graphs) {
-        if (g.exec) hipGraphExecDestroy(g.exec);
-        if (g.graph) hipGraphDestroy(g.graph);
-    }
-    b->graphs.clear();
-}
-
-// After a call issued on `s` (not into a capture): mark its end.
-fft3d_status finish(fft3d_batch_s* b, hipStream_t s, bool capturing, fft3d_status st)
-{
-    if (st != FFT3D_OK || capturing) return st;
-    hipError_t e = hipSuccess;
-    if (!b->done) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        b->done = nullptr;
-        return set_hip_error(e, "hipEventCreate");
-    }
-    e = hipEventRecord(b->done, s);
-    return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipEventRecord");
+    for (auto& c : b->cache)
+        if (c.dev) hipFree(c.dev);
+    b->cache.clear();
 }
 
 void release(fft3d_batch_s* b)
 {
-    drop_graphs(b);
+    drop_cache(b);
     if (b->done) hipEventDestroy(b->done);
     for (auto& kv : b->plans) fft3d_destroy(kv.second);
     delete b;
@@ -107,6 +93,76 @@ bool overlap(const void* a, size_t na, const void* c, size_t nc)
     const char* pa = (const char*)a;
     const char* pc = (const char*)c;
     return pa < pc + nc && pc < pa + na;
+}
+
+// Build the launches of operation op on this pointer set: for each stage,
+// for each shape (largest first), the stage tiles of all its transforms as
+// one grouped launch (or one by one where they cannot be grouped).
+fft3d_status build_issue(fft3d_batch_t b, int op, const void* const* in, void* const* out, CachedIssue* c)
+{
+    const int pop = op == 0 ? OP_FORWARD : OP_INVERSE;
+    std::vector<Shape> shapes;
+    for (int f : b->order) {
+        const Shape sh = shape_of(b->ffts[f]);
+        if (std::find(shapes.begin(), shapes.end(), sh) == shapes.end()) shapes.push_back(sh);
+    }
+    int nst = 0;
+    for (const Shape& sh : shapes) nst = std::max(nst, stage_count(b->plans[sh], pop));
+    std::vector<std::vector<KernelLaunch>> groups;  // per launch group
+    std::vector<char> grouped;
+    for (int st = 0; st < nst; ++st) {
+        for (const Shape& sh : shapes) {
+            fft3d_plan_t p = b->plans[sh];
+            if (st >= stage_count(p, pop)) continue;
+            std::vector<KernelLaunch> v, one;
+            for (int f : b->order) {
+                if (shape_of(b->ffts[f]) != sh) continue;
+                const fft3d_status r = record_stage(p, pop, st, in[f], out[f], &one);
+                if (r != FFT3D_OK) return r;
+                v.insert(v.end(), one.begin(), one.end());
+            }
+            if (can_group(v.data(), v.size())) {
+                groups.push_back(v);
+                grouped.push_back(1);
+            } else {
+                for (const KernelLaunch& kl : v) {
+                    groups.push_back({kl});
+                    grouped.push_back(0);
+                }
+            }
+        }
+    }
+    size_t total = 0;
+    for (size_t g = 0; g < groups.size(); ++g)
+        if (grouped[g]) total += groups[g].size();
+    std::vector<TileEntry> host(total);
+    std::vector<size_t> at(groups.size(), 0);
+    size_t pos = 0;
+    c->launches.clear();
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (!grouped[g]) {
+            c->launches.push_back(groups[g][0]);
+            continue;
+        }
+        KernelLaunch kl;
+        make_group(groups[g].data(), groups[g].size(), true, host.data() + pos, &kl);
+        at[g] = pos;
+        pos += groups[g].size();
+        c->launches.push_back(kl);
+    }
+    c->dev = nullptr;
+    if (total > 0) {
+        hipError_t e = hipMalloc(&c->dev, total * sizeof(TileEntry));
+        if (e == hipSuccess) e = hipMemcpy(c->dev, host.data(), total * sizeof(TileEntry), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (c->dev) hipFree(c->dev);
+            c->dev = nullptr;
+            return set_hip_error(e, "batch tile table upload");
+        }
+    }
+    for (size_t g = 0; g < groups.size(); ++g)
+        if (grouped[g]) c->launches[g].args.tiles = c->dev + at[g];
+    return FFT3D_OK;
 }
 
 fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* const* out, void* stream)
@@ -136,7 +192,8 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
     }
     if (cap != hipStreamCaptureStatusNone) {
         // a stream the caller is capturing: every transform in order on it
-        // (each plan issues its stages in order on a capturing stream)
+        // (each plan issues its stages in order on a capturing stream; no
+        // launch of the capture refers to a table of this batch)
         for (int f : b->order) {
             fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
             fft3d_status st = op == 0 ? fft3d_forward(p, in[f], out[f], s) : fft3d_inverse(p, in[f], out[f], s);
@@ -144,42 +201,40 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         }
         return FFT3D_OK;
     }
-    CachedGraph* hit = nullptr;
-    for (auto& g : b->graphs) {
-        if (g.op != op) continue;
+    CachedIssue* hit = nullptr;
+    for (auto& c : b->cache) {
+        if (c.op != op) continue;
         bool same = true;
-        for (int f = 0; same && f < count; ++f) same = g.in[f] == in[f] && g.out[f] == out[f];
+        for (int f = 0; same && f < count; ++f) same = c.in[f] == in[f] && c.out[f] == out[f];
         if (same) {
-            hit = &g;
+            hit = &c;
             break;
         }
     }
     if (!hit) {
-        if (b->graphs.size() >= kMaxGraphs) drop_graphs(b);
-        CachedGraph g;
-        g.op = op;
-        g.in.assign(in, in + count);
-        g.out.assign(out, out + count);
-        e = hipGraphCreate(&g.graph, 0);
-        if (e != hipSuccess) return set_hip_error(e, "hipGraphCreate");
-        for (int f : b->order) {
-            fft3d_status st = append_plan_nodes(b->plans[shape_of(b->ffts[f])], op == 0 ? OP_FORWARD : OP_INVERSE,
-                                                in[f], out[f], g.graph, {}, nullptr);
-            if (st != FFT3D_OK) {
-                hipGraphDestroy(g.graph);
-                return st;
-            }
-        }
-        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipGraphDestroy(g.graph);
-            return set_hip_error(e, "hipGraphInstantiate");
-        }
-        b->graphs.push_back(g);
-        hit = &b->graphs.back();
+        if (b->cache.size() >= kMaxCached) drop_cache(b);
+        CachedIssue c;
+        c.op = op;
+        c.in.assign(in, in + count);
+        c.out.assign(out, out + count);
+        const fft3d_status st = build_issue(b, op, in, out, &c);
+        if (st != FFT3D_OK) return st;
+        b->cache.push_back(c);
+        hit = &b->cache.back();
     }
-    e = hipGraphLaunch(hit->exec, s);
-    return finish(b, s, false, e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipGraphLaunch"));
+    for (const KernelLaunch& kl : hit->launches) {
+        e = launch_stage_kernel(kl.func, kl.grid, kl.block, kl.args, kl.lds, s);
+        if (e != hipSuccess) return set_hip_error(e, "batch kernel launch");
+    }
+    if (!b->done) {
+        e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            b->done = nullptr;
+            return set_hip_error(e, "hipEventCreate");
+        }
+    }
+    e = hipEventRecord(b->done, s);
+    return e == hipSuccess ? FFT3D_OK : set_hip_error(e, "hipEventRecord");
 }
 
 std::vector<double> batch_costs(const std::vector<PlanDesc>& ffts)
@@ -251,7 +306,7 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
-    drop_graphs(b);  // launch shapes are baked into the graphs
+    drop_cache(b);  // launch shapes are baked into the cached launches
     return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
 }
 
@@ -262,7 +317,7 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     if (staging != FFT3D_STAGING_IN_PLACE && staging != FFT3D_STAGING_FUSED_XY)
         return set_error(FFT3D_ERR_INVALID_ARG, "a batch stages in place or in fused x-y planes (no workspace)");
-    drop_graphs(b);  // the stage lists are baked into the graphs
+    drop_cache(b);  // the stage lists are baked into the cached launches
     return fft3d_set_staging(it->second, staging);
 }
 

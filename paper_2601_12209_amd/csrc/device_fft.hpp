@@ -398,4 +398,49 @@ FD void fft_line(const LdsView<cpx<T>>& L, const LdsView<T>& Ls, int tj, const c
     }
 }
 
+// ------------------------------------------------------------ tile lookup
+
+// Workgroup coordinates within its tile and the tile's grid.
+struct TileCoord {
+    int64_t bx, by, gx, gy;
+};
+
+// A launch of one tile uses blockIdx and gridDim.  A grouped launch (a.tiles
+// set, a 1D grid) reserves gmax workgroups per tile: workgroup w belongs to
+// tile w / gmax, whose entry replaces the per-tile fields of `a`; workgroups
+// past the tile's own grid have no work (false: the whole workgroup returns
+// before any barrier).
+template <typename Args>
+FD bool tile_coord(Args& a, TileCoord& c)
+{
+    if (a.tiles == nullptr) {
+        c.bx = blockIdx.x;
+        c.by = blockIdx.y;
+        c.gx = gridDim.x;
+        c.gy = gridDim.y;
+        return true;
+    }
+    // 32-bit index arithmetic: a grid's workgroup counts fit in 32 bits (and
+    // a 64-bit division here costs the kernel a scratch stack frame)
+    const uint32_t w = blockIdx.x, gmax = (uint32_t)a.gmax;
+    const uint32_t t = w / gmax, local = w - t * gmax;
+    const auto& e = a.tiles[t];
+    const uint32_t gx = (uint32_t)e.gx;
+    if (local >= gx * (uint32_t)e.gy) return false;
+    if (e.in) a.in = e.in;  // else the launch's buffers (the tiles of one transform)
+    if (e.out) a.out = e.out;
+    a.off = e.off;
+    a.off_o = e.off_o;
+    a.A = e.A;
+    a.B = e.B;
+    a.kx0 = e.kx0;
+    a.ky0 = e.ky0;
+    c.gx = e.gx;
+    c.gy = e.gy;
+    const uint32_t by = local / gx;
+    c.by = by;
+    c.bx = local - by * gx;
+    return true;
+}
+
 }  // namespace fft3d

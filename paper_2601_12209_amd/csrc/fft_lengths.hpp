@@ -59,7 +59,7 @@ constexpr RadixPlan radix_plan(int n)
     case 5: p.r[p.np++] = 8; p.r[p.np++] = 4; break;
     case 6: p.r[p.np++] = 8; p.r[p.np++] = 8; break;
     case 7: p.r[p.np++] = 16; p.r[p.np++] = 8; break;
-    case 8: p.r[p.np++] = 16; p.r[p.np++] = 16; break;
+    case 8: p.r[p.np++] = 8; p.r[p.np++] = 8; p.r[p.np++] = 4; break;  // not 16 x 16: half the registers
     case 9: p.r[p.np++] = 8; p.r[p.np++] = 8; p.r[p.np++] = 8; break;
     case 10: p.r[p.np++] = 16; p.r[p.np++] = 8; p.r[p.np++] = 8; break;
     case 11: p.r[p.np++] = 16; p.r[p.np++] = 16; p.r[p.np++] = 8; break;

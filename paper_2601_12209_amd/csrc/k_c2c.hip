@@ -26,6 +26,8 @@ template <typename T, int N, int TDIV, bool SPLIT, int NT>
 __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
 {
     constexpr int TPL = radix_plan(N).tpl / TDIV;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     T* ldsr = reinterpret_cast<T*>(smem_raw);
@@ -40,12 +42,12 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     if (a.strided) {
         const int lw = t % a.lw;
         tj = t / a.lw;
-        int64_t bx = blockIdx.x, by = blockIdx.y;
-        if (a.xcd) {  // host guarantees gridDim.x * gridDim.y % 8 == 0
-            const int64_t lin = bx + by * gridDim.x, per = (int64_t)gridDim.x * gridDim.y / 8;
+        int64_t bx = tc.bx, by = tc.by;
+        if (a.xcd) {  // host guarantees the tile's gx * gy % 8 == 0
+            const int64_t lin = bx + by * tc.gx, per = tc.gx * tc.gy / 8;
             const int64_t tile = (lin % 8) * per + lin / 8;
-            bx = tile % gridDim.x;
-            by = tile / gridDim.x;
+            bx = tile % tc.gx;
+            by = tile / tc.gx;
         }
         // with a.align, the tiles of this row start `shift` lines early so that
         // every output segment covers whole cache lines
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     } else {
         tj = t % TPL;
         const int lw = t / TPL;
-        const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+        const int64_t l0 = tc.bx * a.lw + lw;
         ok = l0 < a.A * a.B;
         const int64_t l = ok ? l0 : a.A * a.B - 1;
         const int64_t aa = l % a.A, bb = l / a.A;

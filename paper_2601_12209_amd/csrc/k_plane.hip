@@ -54,11 +54,13 @@ __global__ __launch_bounds__(NT) void k_c2c_xy(StageArgs a)
     cpx<T>* twx = scratch + (NX > NY ? NX : NY);
     cpx<T>* twy = twx + SX;
     const int t = threadIdx.x;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
     stage_pass_twiddles<T, NX>(twx, reinterpret_cast<const cpx<T>*>(a.twp), t, NT);
     stage_pass_twiddles<T, NY>(twy, reinterpret_cast<const cpx<T>*>(a.twp2), t, NT);
     // plane b of the tile: rows of NX values a.sa apart, planes a.sb apart
-    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + a.off + (int64_t)blockIdx.x * a.sb;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + (int64_t)blockIdx.x * a.sb_o;
+    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + a.off + tc.bx * a.sb;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + tc.bx * a.sb_o;
     const bool cj = a.conj != 0;
     // every load of the thread in flight at once, then into LDS
     constexpr int E = (NX * NY + NT - 1) / NT;

@@ -29,11 +29,13 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int lw = t % a.lw, tj = t / a.lw;
-    const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
+    const int64_t aa = tc.bx * a.lw + lw;
     const bool ok = aa < a.A;
     const int64_t ac = ok ? aa : a.A - 1;  // see k_c2c
-    const int64_t base = a.off + ac + (int64_t)blockIdx.y * a.sb;
-    const int64_t base_o = a.off_o + ac + (int64_t)blockIdx.y * a.sb_o;
+    const int64_t base = a.off + ac + tc.by * a.sb;
+    const int64_t base_o = a.off_o + ac + tc.by * a.sb_o;
     const int64_t se = a.se, se_o = a.se_o;
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + base + tj * se;
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + base_o + tj * se_o;
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(1024) void k_poisson_z(StageArgs a)
 
     // wavenumbers of this line: kx from the half-spectrum column, ky from the row
     const T kx = (T)(a.kx0 + aa);
-    const T ky = wavenumber<T>(a.ky0 + (int64_t)blockIdx.y, a.pny);
+    const T ky = wavenumber<T>(a.ky0 + tc.by, a.pny);
     const T kxy2 = kx * kx + ky * ky;
     const T scale = (T)a.scale;
 

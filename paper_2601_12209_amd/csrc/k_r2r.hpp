@@ -48,12 +48,14 @@ __global__ __launch_bounds__(1024) void k_r2r_z(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int lw = t % a.lw, tj = t / a.lw;
-    const int64_t aa = (int64_t)blockIdx.x * a.lw + lw;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
+    const int64_t aa = tc.bx * a.lw + lw;
     const bool ok = aa < a.A;
     const int64_t ac = ok ? aa : a.A - 1;  // lanes past the last line load a valid one, store nothing
     const int64_t se = a.se, se_o = a.se_o;
-    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + a.off + ac + (int64_t)blockIdx.y * a.sb;
-    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + ac + (int64_t)blockIdx.y * a.sb_o;
+    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + a.off + ac + tc.by * a.sb;
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + a.off_o + ac + tc.by * a.sb_o;
     LdsView<cpx<T>> L{lds + lw, a.lw, 0};
     LdsView<T> Ls{nullptr, 0, 0};
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * N * sizeof(cpx<T>)));
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_r2r_z(StageArgs a)
             // from the row; along z the DCT index k (Neumann) or, for the
             // DST, index N-1-k with wavenumber N-k (Dirichlet)
             const T kx = (T)(a.kx0 + aa);
-            const T ky = wavenumber_r2r<T>(a.ky0 + (int64_t)blockIdx.y, a.pny);
+            const T ky = wavenumber_r2r<T>(a.ky0 + tc.by, a.pny);
             const T kxy2 = kx * kx + ky * ky;
             auto mult = [&](int k) -> T {
                 const T kz = DST ? (T)(N - k) : (T)k;

@@ -46,7 +46,9 @@ __global__ __launch_bounds__(1024) void k_r2c_x(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int tj = t % TPL, lw = t / TPL;
-    const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
+    const int64_t l0 = tc.bx * a.lw + lw;
     const bool ok = l0 < a.A * a.B;
     const int64_t l = ok ? l0 : a.A * a.B - 1;  // past the end: load the last line, store nothing
     const int64_t aa = l % a.A, bb = l / a.A;
@@ -91,7 +93,9 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
     const int t = threadIdx.x;
     const int tj = t % TPL, lw = t / TPL;
-    const int64_t l0 = (int64_t)blockIdx.x * a.lw + lw;
+    TileCoord tc;
+    if (!tile_coord(a, tc)) return;
+    const int64_t l0 = tc.bx * a.lw + lw;
     const bool ok = l0 < a.A * a.B;
     const int64_t l = ok ? l0 : a.A * a.B - 1;  // past the end: load the last line, store nothing
     const int64_t aa = l % a.A, bb = l / a.A;

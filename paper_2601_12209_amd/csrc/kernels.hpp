@@ -45,6 +45,17 @@ void set_launch_recorder(KernelLaunch* rec, bool* recorded);
 hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const StageArgs& a, size_t lds,
                                hipStream_t s);
 
+// Grouped launches: tile launches of one stage kernel that differ only in
+// their tile fields (buffers, origins, line grid, wavenumber origin) become
+// one launch whose workgroups look their tile up in a device table
+// (StageArgs::tiles, TileEntry).  can_group tells whether the launches
+// qualify; make_group fills the table entries (in/out left null when
+// own_buffers is false: the tiles of one transform share the launch's
+// buffers) and the common launch (grid = tiles x gmax workgroups, args with
+// gmax set; the caller sets args.tiles to the device copy of the entries).
+bool can_group(const KernelLaunch* v, size_t n);
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, TileEntry* entries, KernelLaunch* common);
+
 // Size of the library's static device scratch (one per GPU, scratch.hip),
 // the workspace of the calls that allocate nothing: 256 MiB holds the R2C
 // workspace of every grid up to 256^3 in either precision.

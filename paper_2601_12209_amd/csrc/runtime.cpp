@@ -81,12 +81,64 @@ hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const St
     return hipLaunchKernel(func, grid, block, args, lds, s);
 }
 
-// Appends the kernel nodes of one call of `p` (operation op, in -> out, the
-// plan's workspace) to graph g: one node per tile with its producer edges;
-// the first stage's nodes depend on `after`.  *tail receives the last stage's
-// nodes.  Used by the batch to put many transforms into one graph.
-fft3d_status append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
-                               const std::vector<hipGraphNode_t>& after, std::vector<hipGraphNode_t>* tail);
+// The tile launches of one stage of one call of `p` (operation op, in ->
+// out, the plan's workspace), recorded instead of issued; tiles with nothing
+// to launch are left out.  Used by the batch to group the stage launches of
+// its transforms.
+fft3d_status record_stage(fft3d_plan_s* p, int op, int stage, const void* in, void* out,
+                          std::vector<KernelLaunch>* launches);
+int stage_count(fft3d_plan_s* p, int op);
+
+namespace {
+// StageArgs with the per-tile fields cleared, for comparing launches.
+StageArgs without_tile_fields(StageArgs a)
+{
+    a.in = nullptr;
+    a.out = nullptr;
+    a.off = a.off_o = a.A = a.B = a.kx0 = a.ky0 = 0;
+    a.tiles = nullptr;
+    a.gmax = 0;
+    return a;
+}
+}  // namespace
+
+bool can_group(const KernelLaunch* v, size_t n)
+{
+    if (n < 2) return false;
+    const StageArgs a0 = without_tile_fields(v[0].args);
+    for (size_t i = 0; i < n; ++i) {
+        if (v[i].func != v[0].func || v[i].lds != v[0].lds || v[i].block.x != v[0].block.x ||
+            v[i].block.y != v[0].block.y || v[i].block.z != v[0].block.z || v[i].grid.z != 1 ||
+            v[i].args.tiles != nullptr)
+            return false;
+        const StageArgs ai = without_tile_fields(v[i].args);
+        if (memcmp(&ai, &a0, sizeof ai) != 0) return false;
+    }
+    return true;
+}
+
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, TileEntry* entries, KernelLaunch* common)
+{
+    int64_t gmax = 1;
+    for (size_t i = 0; i < n; ++i) {
+        const StageArgs& a = v[i].args;
+        TileEntry& e = entries[i];
+        e.in = own_buffers ? a.in : nullptr;
+        e.out = own_buffers ? a.out : nullptr;
+        e.off = a.off;
+        e.off_o = a.off_o;
+        e.A = a.A;
+        e.B = a.B;
+        e.kx0 = a.kx0;
+        e.ky0 = a.ky0;
+        e.gx = v[i].grid.x;
+        e.gy = v[i].grid.y;
+        gmax = std::max<int64_t>(gmax, e.gx * e.gy);
+    }
+    *common = v[0];
+    common->args.gmax = gmax;
+    common->grid = dim3((unsigned)(gmax * (int64_t)n), 1, 1);
+}
 
 // error reporting shared with the batch entry points (batch.cpp)
 fft3d_status set_error(fft3d_status st, const std::string& msg) { return fail(st, msg); }
@@ -134,6 +186,19 @@ struct fft3d_plan_s {
     bool timing = false;
     std::vector<hipEvent_t> tev;  // 6 timing events (up to 5 stages)
     int timed_stages = 0;
+    // issue of tiled plans (fft3d_set_issue): one launch per tile on the
+    // plan's streams, or one grouped launch per stage
+    int issue = FFT3D_ISSUE_STAGES;
+    struct StageGroup {
+        bool grouped = false;  // one launch for all tiles of the stage
+        KernelLaunch launch;   // that launch (args.in/out set per call)
+    };
+    struct OpGroups {
+        bool valid = false;
+        std::vector<StageGroup> stages;
+        TileEntry* dev = nullptr;  // the grouped stages' tile tables
+    };
+    OpGroups groups[OP_COUNT];
 };
 
 namespace {
@@ -207,13 +272,17 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         c.lw = lw;
         c.tdiv = tdiv;
         c.split = c2c && c2c_variant_available(nk, tdiv, 1) ? 1 : 0;
-        // complex64 lines of 512 in whole 32-line tiles: 32 lines per workgroup
-        // (256-byte row segments) with half the threads per line and a full
-        // complex LDS tile measured ~4 % faster than 16 lines (MI355X, 512^3)
-        if (c2c && d.dtype == DT_F32 && nk == 512 && a % 32 == 0 && c2c_variant_available(nk, 2, 0)) {
+        // complex64 lines of 512 with a full complex LDS tile (no split
+        // exchange).  In whole 32-line tiles: 32 lines per workgroup
+        // (256-byte row segments) with half the threads per line: fwd+inv
+        // 2.42 ms at 512^3 on MI355X against 2.43 for 16-line tiles and 2.46
+        // with the split exchange.  Otherwise (the R2C half spectrum's 257
+        // columns) 16 lines, one thread per butterfly.
+        if (c2c && d.dtype == DT_F32 && nk == 512 && a >= 16) {
             KConf w;
-            w.lw = 32;
-            w.tdiv = 2;
+            const bool whole32 = a % 32 == 0 && c2c_variant_available(nk, 2, 0);
+            w.lw = whole32 ? 32 : 16;
+            w.tdiv = whole32 ? 2 : 1;
             w.split = 0;
             if (conf_fits(st, d.dtype, w, true)) c = w;
         }
@@ -227,6 +296,12 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         // 1.46-1.49, 480^3 0.38 -> 0.33-0.34)
         if ((nk & (nk - 1)) != 0)
             while (lw * tpl < 256) lw *= 2;
+        // the complex64 real kernels at half length 256 (512^3) run fastest with
+        // more lines per workgroup on MI355X: R2C split 16 lines (512
+        // threads), 237 -> 195 us; C2R merge 8 lines, 241 -> 233 us (the
+        // complex128 ones are best at the default 4 lines)
+        if (st.kind == K_R2C_X && d.dtype == DT_F32 && nk == 256) lw = 16;
+        if (st.kind == K_C2R_X && d.dtype == DT_F32 && nk == 256) lw = 8;
         c.lw = lw;
         c.split = c2c && c2c_variant_available(nk, 1, 1) ? 1 : 0;
         c.pad = 1;
@@ -269,7 +344,10 @@ int c2c_cache_policy(const PlanDesc& d, const Stage& st, const StageArgs& a, int
     if (st.kind != K_C2C) return 0;
     if ((size_t)d.nxc() * d.ny * d.nz * elem_bytes(d.dtype) < kSwapStagingMinBytes) return 0;
     const bool in_place = st.src == st.dst;
-    if (d.dtype == DT_F32 && a.strided && !in_place) return 0;
+    // complex64 C2C plans' y/z stages writing another buffer keep plain stores
+    // (1-2 % slower with them at 512^3); the R2C half spectrum's gain (R2C y
+    // and z stages 252 -> 234 us mean at 512^3)
+    if (d.dtype == DT_F32 && a.strided && !in_place && !d.r2c) return 0;
     bool whole_lines;
     if (a.strided)  // row segments of lw lines at off + b*sb + e*se
         whole_lines = a.align <= 1 && a.lw % per_line == 0 && a.A % per_line == 0 && a.off % per_line == 0 &&
@@ -301,14 +379,16 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     a.A = b.hi[ax_a] - b.lo[ax_a];
     a.B = b.hi[ax_b] - b.lo[ax_b];
     if (st.kind == K_R2C_X || st.kind == K_C2R_X) {
-        // real rows: nx reals = nx/2 complex pairs per row (dense); complex
-        // rows: the buffer's row pitch
+        // real rows: nx reals = nx/2 complex pairs per row (dense, natural
+        // order); complex rows: the buffer's pitch and layout (row (y, z) at
+        // y*st[1] + z*st[2])
         const int64_t h = d.nx / 2;
-        const int64_t row = b.lo[1] + ny * b.lo[2];
-        const int64_t li = st.kind == K_R2C_X ? h : row_pitch(d, st.src);
-        const int64_t lo = st.kind == K_R2C_X ? row_pitch(d, st.dst) : h;
-        a.off = row * li; a.sa = li; a.sb = li * ny; a.se = 1;
-        a.off_o = row * lo; a.sa_o = lo; a.sb_o = lo * ny; a.se_o = 1;
+        int64_t sc[3];
+        layout_strides(d, st.kind == K_R2C_X ? st.dst : st.src, st.kind == K_R2C_X ? st.lay_dst : st.lay_src, sc);
+        const int64_t ry = st.kind == K_R2C_X ? h : sc[1], rz = st.kind == K_R2C_X ? h * ny : sc[2];
+        const int64_t wy = st.kind == K_R2C_X ? sc[1] : h, wz = st.kind == K_R2C_X ? sc[2] : h * ny;
+        a.off = b.lo[1] * ry + b.lo[2] * rz; a.sa = ry; a.sb = rz; a.se = 1;
+        a.off_o = b.lo[1] * wy + b.lo[2] * wz; a.sa_o = wy; a.sb_o = wz; a.se_o = 1;
         a.strided = 0;
     } else {
         int64_t si[3], so[3];
@@ -441,13 +521,31 @@ hipError_t ensure_streams(fft3d_plan_s* p, int count)
     return hipSuccess;
 }
 
-// Timed issue: every stage is its own fork/join region on the caller's stream,
+fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl);
+fft3d_status issue_stage(fft3d_plan_s* p, int op, const Pipeline& pl, int stage, void* const bufs[3],
+                         hipStream_t s, bool group);
+bool stage_groups(const fft3d_plan_s* p);
+
+// Timed issue: every stage is its own region on the caller's stream (its
+// grouped launch, or its tiles forked onto the plan's streams and joined),
 // with a timing event after it, so stage durations can be read back.
-fft3d_status run_timed(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipStream_t user)
+fft3d_status run_timed(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user)
 {
+    const bool grouped = stage_groups(p);
+    if (grouped && !p->groups[op].valid) {
+        const fft3d_status r = build_groups(p, op, pl);
+        if (r != FFT3D_OK) return r;
+    }
     hipError_t e = hipEventRecord(p->tev[0], user);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
     for (int st = 0; st < (int)pl.stages.size(); ++st) {
+        if (grouped) {
+            const fft3d_status r = issue_stage(p, op, pl, st, bufs, user, true);
+            if (r != FFT3D_OK) return r;
+            e = hipEventRecord(p->tev[st + 1], user);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord(timing)");
+            continue;
+        }
         const bool fork = forks(p);
         if (fork) {
             e = hipEventRecord(p->fork, user);
@@ -494,72 +592,143 @@ void wait_last_call(fft3d_plan_s* p)
 
 fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user);
 
-// The task graph of one operation on these buffers as a hipGraph built node
-// by node: one kernel node per tile, whose dependencies are exactly the
-// tile's producers (the overlap edges of the pipeline; no streams, events or
-// stream capture are involved).  A tile with nothing to launch becomes an
-// empty node so that its consumers still follow its producers.
-hipError_t add_pipeline_nodes(fft3d_plan_s* p, const Pipeline& pl, void* const bufs[3], hipGraph_t g,
-                              const std::vector<hipGraphNode_t>& after, std::vector<hipGraphNode_t>* tail)
+// Record the launch of every tile of stage `stage` (in task order) instead
+// of issuing it; tiles with nothing to launch are left out.
+hipError_t record_tiles(fft3d_plan_s* p, const Pipeline& pl, int stage, void* const bufs[3],
+                        std::vector<KernelLaunch>* launches)
 {
-    hipError_t e = hipSuccess;
-    std::vector<hipGraphNode_t> node(pl.tasks.size(), nullptr);
-    for (size_t i = 0; i < pl.tasks.size() && e == hipSuccess; ++i) {
-        const Task& t = pl.tasks[i];
+    launches->clear();
+    for (const Task& t : pl.tasks) {
+        if (t.stage != stage) continue;
         const Stage& st = pl.stages[t.stage];
-        std::vector<hipGraphNode_t> deps;
-        for (int d : t.deps) deps.push_back(node[d]);
-        if (t.stage == 0) deps = after;
         KernelLaunch kl;
         bool recorded = false;
         set_launch_recorder(&kl, &recorded);
-        e = launch_task(p, st, make_args(p, st, t.box, bufs), nullptr);
+        const hipError_t e = launch_task(p, st, make_args(p, st, t.box, bufs), nullptr);
         set_launch_recorder(nullptr, nullptr);
-        if (e != hipSuccess) break;
-        if (recorded) {
-            void* kargs[] = {&kl.args};
-            hipKernelNodeParams kp;
-            memset(&kp, 0, sizeof kp);
-            kp.func = const_cast<void*>(kl.func);
-            kp.gridDim = kl.grid;
-            kp.blockDim = kl.block;
-            kp.sharedMemBytes = (unsigned)kl.lds;
-            kp.kernelParams = kargs;
-            kp.extra = nullptr;
-            e = hipGraphAddKernelNode(&node[i], g, deps.data(), deps.size(), &kp);
-        } else {
-            e = hipGraphAddEmptyNode(&node[i], g, deps.data(), deps.size());
+        if (e != hipSuccess) return e;
+        if (recorded) launches->push_back(kl);
+    }
+    return hipSuccess;
+}
+
+// Free the grouped launches' tables after the last call has finished.
+void drop_groups(fft3d_plan_s* p)
+{
+    wait_last_call(p);
+    for (auto& g : p->groups) {
+        if (g.dev) hipFree(g.dev);
+        g = fft3d_plan_s::OpGroups();
+    }
+}
+
+// Decide, per stage of operation op, whether its tiles go out as one
+// grouped launch, and upload the tile tables of the grouped stages.
+fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
+{
+    fft3d_plan_s::OpGroups& G = p->groups[op];
+    G = fft3d_plan_s::OpGroups();
+    void* const none[3] = {nullptr, nullptr, nullptr};
+    std::vector<std::vector<KernelLaunch>> rec(pl.stages.size());
+    size_t total = 0;
+    for (size_t st = 0; st < pl.stages.size(); ++st) {
+        hipError_t e = record_tiles(p, pl, (int)st, none, &rec[st]);
+        if (e != hipSuccess) return hip_fail(e, "recording tile launches");
+        if (can_group(rec[st].data(), rec[st].size())) total += rec[st].size();
+    }
+    std::vector<TileEntry> host(total);
+    G.stages.resize(pl.stages.size());
+    size_t pos = 0;
+    for (size_t st = 0; st < pl.stages.size(); ++st) {
+        const std::vector<KernelLaunch>& v = rec[st];
+        if (!can_group(v.data(), v.size())) continue;
+        G.stages[st].grouped = true;
+        make_group(v.data(), v.size(), false, host.data() + pos, &G.stages[st].launch);
+        G.stages[st].launch.args.tiles = reinterpret_cast<const TileEntry*>(pos);  // offset until uploaded
+        pos += v.size();
+    }
+    if (total > 0) {
+        hipError_t e = hipMalloc(&G.dev, total * sizeof(TileEntry));
+        if (e == hipSuccess) e = hipMemcpy(G.dev, host.data(), total * sizeof(TileEntry), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (G.dev) hipFree(G.dev);
+            G = fft3d_plan_s::OpGroups();
+            return hip_fail(e, "tile table upload");
         }
+        for (auto& sg : G.stages)
+            if (sg.grouped) sg.launch.args.tiles = G.dev + reinterpret_cast<size_t>(sg.launch.args.tiles);
     }
-    if (tail && e == hipSuccess) {
-        tail->clear();
-        const int last = (int)pl.stages.size() - 1;
-        for (size_t i = 0; i < pl.tasks.size(); ++i)
-            if (pl.tasks[i].stage == last) tail->push_back(node[i]);
+    G.valid = true;
+    return FFT3D_OK;
+}
+
+// Issue stage `stage` of a call on `s`: its grouped launch, or its tiles in
+// task order.
+fft3d_status issue_stage(fft3d_plan_s* p, int op, const Pipeline& pl, int stage, void* const bufs[3],
+                         hipStream_t s, bool group)
+{
+    const fft3d_plan_s::OpGroups& G = p->groups[op];
+    if (group && G.valid && G.stages[stage].grouped) {
+        const KernelLaunch& kl = G.stages[stage].launch;
+        StageArgs a = kl.args;
+        a.in = bufs[pl.stages[stage].src];
+        a.out = bufs[pl.stages[stage].dst];
+        const hipError_t e = launch_stage_kernel(kl.func, kl.grid, kl.block, a, kl.lds, s);
+        return e == hipSuccess ? FFT3D_OK : hip_fail(e, "grouped kernel launch");
     }
-    return e;
+    for (const Task& t : pl.tasks) {
+        if (t.stage != stage) continue;
+        const Stage& st = pl.stages[t.stage];
+        const hipError_t e = launch_task(p, st, make_args(p, st, t.box, bufs), s);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    return FFT3D_OK;
 }
 
 }  // namespace
 
-fft3d_status fft3d::append_plan_nodes(fft3d_plan_s* p, int op, const void* in, void* out, hipGraph_t g,
-                                      const std::vector<hipGraphNode_t>& after,
-                                      std::vector<hipGraphNode_t>* tail)
+fft3d_status fft3d::record_stage(fft3d_plan_s* p, int op, int stage, const void* in, void* out,
+                                 std::vector<KernelLaunch>* launches)
 {
     if (!p || op < 0 || op >= OP_COUNT) return fail(FFT3D_ERR_INVALID_ARG, "invalid plan or operation");
     const Pipeline& pl = get_pipeline(p, op);
-    if (pl.stages.empty()) return fail(FFT3D_ERR_WRONG_PLAN, "operation not available for this plan kind");
+    if (stage < 0 || stage >= (int)pl.stages.size()) return fail(FFT3D_ERR_INVALID_ARG, "invalid stage");
     void* bufs[3] = {const_cast<void*>(in), out, p->ws};
-    hipError_t e = add_pipeline_nodes(p, pl, bufs, g, after, tail);
-    return e == hipSuccess ? FFT3D_OK : hip_fail(e, "adding pipeline nodes");
+    const hipError_t e = record_tiles(p, pl, stage, bufs, launches);
+    return e == hipSuccess ? FFT3D_OK : hip_fail(e, "recording tile launches");
+}
+
+int fft3d::stage_count(fft3d_plan_s* p, int op)
+{
+    if (!p || op < 0 || op >= OP_COUNT) return 0;
+    return (int)get_pipeline(p, op).stages.size();
 }
 
 namespace {
 
+// Whether tiled calls of this plan go out as one grouped launch per stage.
+bool stage_groups(const fft3d_plan_s* p)
+{
+    return p->issue == FFT3D_ISSUE_STAGES && (int64_t)p->d.p1 * p->d.p2 > 1;
+}
+
 fft3d_status issue(fft3d_plan_s* p, int op, const Pipeline& pl, void* const bufs[3], hipStream_t user,
                    bool capturing)
 {
-    if (p->timing && !capturing) return run_timed(p, pl, bufs, user);
+    if (p->timing && !capturing) return run_timed(p, op, pl, bufs, user);
+    // One grouped launch per stage, in order on the caller's stream (not into
+    // a capture: a captured launch would keep the plan's tile table in use)
+    if (stage_groups(p) && !capturing) {
+        if (!p->groups[op].valid) {
+            const fft3d_status st = build_groups(p, op, pl);
+            if (st != FFT3D_OK) return st;
+        }
+        for (int st = 0; st < (int)pl.stages.size(); ++st) {
+            const fft3d_status r = issue_stage(p, op, pl, st, bufs, user, true);
+            if (r != FFT3D_OK) return r;
+        }
+        return FFT3D_OK;
+    }
     // In order on the caller's stream: plans with one stream or one tile per
     // stage, and every call into a stream the caller is capturing (forking
     // onto the plan's streams there would put cross-stream event edges into
@@ -646,7 +815,7 @@ fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* con
 
 void release(fft3d_plan_s* p)
 {
-    wait_last_call(p);  // work still reading or writing plan memory
+    drop_groups(p);  // waits for the last call (work still reading or writing plan memory)
     for (hipStream_t s : p->streams)
         if (s) {
             hipStreamSynchronize(s);
@@ -979,7 +1148,7 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
         if (p->d.zbc != Z_PERIODIC && staging != STAGING_IN_PLACE)
             return fail(FFT3D_ERR_WRONG_PLAN, "plans with a bounded z axis stage in place");
         if (staging == p->d.staging) return FFT3D_OK;
-        wait_last_call(p);
+        drop_groups(p);
         p->d.staging = staging;
         for (int op = 0; op < OP_COUNT; ++op) p->pipe_ok[op] = false;
         return FFT3D_OK;
@@ -987,7 +1156,7 @@ fft3d_status fft3d_set_staging(fft3d_plan_t p, int staging)
     if (staging == STAGING_FUSED_XY && (p->d.p1 != 1 || !plane_available(p->d.nx, p->d.ny, elem_bytes(p->d.dtype))))
         return fail(FFT3D_ERR_UNSUPPORTED_SIZE, "no fused x-y kernel for this plane (or p1 > 1)");
     if (staging == p->d.staging) return FFT3D_OK;
-    wait_last_call(p);  // the last call may still use the old workspace
+    drop_groups(p);  // waits for the last call, which may still use the old workspace
     if (p->ws && p->ws_owned) hipFree(p->ws);
     p->ws = nullptr;
     p->ws_owned = false;
@@ -1022,13 +1191,33 @@ fft3d_status fft3d_set_streams(fft3d_plan_t p, int nstreams)
     return FFT3D_OK;
 }
 
+fft3d_status fft3d_set_issue(fft3d_plan_t p, int mode)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (mode != FFT3D_ISSUE_TILES && mode != FFT3D_ISSUE_STAGES)
+        return fail(FFT3D_ERR_INVALID_ARG, "issue mode must be 0 (tiles) or 1 (stages)");
+    p->issue = mode;
+    return FFT3D_OK;
+}
+
+int fft3d_get_issue(fft3d_plan_t p)
+{
+    if (!p) {
+        fail(FFT3D_ERR_INVALID_ARG, "null plan");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    return p->issue;
+}
+
 fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, int split, int pad)
 {
     if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
     std::lock_guard<std::mutex> lock(p->mu);
     if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
     if (lw == 0) {
-        wait_last_call(p);
+        drop_groups(p);
         p->conf_override[axis] = KConf();
         return FFT3D_OK;
     }
@@ -1039,15 +1228,19 @@ fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, 
     c.pad = pad;
     if (lw < 1 || lw > 1024 || (lw & (lw - 1)) != 0 || tdiv < 1 || split < 0 || split > 1 || pad < 0 || pad > 1)
         return fail(FFT3D_ERR_INVALID_ARG, "lw a power of two <= 1024, tdiv >= 1, split and pad 0 or 1");
-    // every stage kernel of this axis in every operation must accept the shape
-    for (int op = 0; op < OP_COUNT; ++op) {
+    // some stage kernel of this axis must accept the shape (the others keep
+    // their default shape)
+    bool fits = false, any = false;
+    for (int op = 0; op < OP_COUNT; ++op)
         for (const Stage& st : op_stages(p->d, op)) {
-            if (st.axis == axis && !conf_fits(st, p->d.dtype, c, axis != 0))
-                return fail(FFT3D_ERR_INVALID_ARG, "shape does not fit a stage kernel of this axis "
-                                                   "(threads, LDS, or no such kernel variant)");
+            if (st.axis != axis || st.kind == K_C2C_XY) continue;
+            any = true;
+            fits = fits || conf_fits(st, p->d.dtype, c, axis != 0);
         }
-    }
-    wait_last_call(p);
+    if (any && !fits)
+        return fail(FFT3D_ERR_INVALID_ARG, "shape does not fit a stage kernel of this axis "
+                                           "(threads, LDS, or no such kernel variant)");
+    drop_groups(p);
     p->conf_override[axis] = c;
     return FFT3D_OK;
 }

@@ -35,6 +35,18 @@ enum R2RMode : int {
 
 enum DType : int { DT_F32 = 0, DT_F64 = 1 };
 
+// One tile of a grouped launch (one launch covering several tiles, of one
+// transform or of several transforms of one shape): the fields of StageArgs
+// that differ between those tiles, and the tile's own grid of workgroups.
+struct TileEntry {
+    const void* in;  // nullptr: the launch's own in/out (tiles of one transform)
+    void* out;
+    int64_t off, off_o;
+    int64_t A, B;
+    int64_t kx0, ky0;
+    int64_t gx, gy;
+};
+
 // The tile's lines form an A x B grid; line (a, b) starts at element
 // off + a*sa + b*sb of the input and its elements are se apart; in the output
 // it starts at off_o + a*sa_o + b*sb_o with elements se_o apart.  Elements are
@@ -73,6 +85,10 @@ struct StageArgs {
     // (kx, ky) of line (0, 0)
     int64_t pnx, pny, pnz;
     int64_t kx0, ky0;
+    // grouped launch: tiles[w / gmax] is the tile of workgroup w (nullptr: a
+    // launch of this one tile on its own grid)
+    const TileEntry* tiles;
+    int64_t gmax;
 };
 
 }  // namespace fft3d

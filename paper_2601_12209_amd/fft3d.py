@@ -44,6 +44,8 @@ def _stream_handle(stream=None) -> int:
 STAGING_IN_PLACE = 0
 STAGING_SWAP_YZ = 1
 STAGING_FUSED_XY = 2
+ISSUE_TILES = 0
+ISSUE_STAGES = 1
 
 
 Z_NEUMANN = 1
@@ -59,7 +61,7 @@ class Plan:
     DST-II along z instead of the DFT."""
 
     def __init__(self, shape, dtype=torch.complex64, grid=(1, 1), r2c=False, streams=None, staging=None,
-                 z_bc=None):
+                 z_bc=None, issue=None):
         nz, ny, nx = (int(v) for v in shape)
         self.shape = (nz, ny, nx)
         self.code = _dtype_code(dtype)
@@ -80,6 +82,8 @@ class Plan:
             self.set_streams(streams)
         if staging is not None:
             self.set_staging(staging)
+        if issue is not None:
+            self.set_issue(issue)
 
     # ------------------------------------------------------------ helpers
     @property
@@ -177,6 +181,15 @@ class Plan:
     def set_streams(self, n: int):
         check(_lib.lib().fft3d_set_streams(self._h, int(n)), "fft3d_set_streams")
 
+    def set_issue(self, mode: int):
+        """ISSUE_TILES (one launch per tile on the plan's streams, event edges per
+        producer tile) or ISSUE_STAGES (one grouped launch per stage)."""
+        check(_lib.lib().fft3d_set_issue(self._h, int(mode)), "fft3d_set_issue")
+
+    @property
+    def issue(self) -> int:
+        return int(_lib.lib().fft3d_get_issue(self._h))
+
     def set_staging(self, staging: int):
         """STAGING_IN_PLACE (C2C: no workspace), STAGING_SWAP_YZ (y stage writes a
         y/z-swapped workspace that the z stage reads back; R2C: forward only) or
@@ -226,8 +239,8 @@ class Plan:
 
 
 class BatchPlan:
-    """Many 3D FFTs of different shapes issued as one task graph (one hipGraph
-    of every transform's stage kernels, replayed)."""
+    """Many 3D FFTs of different shapes: each stage of every shape's transforms
+    goes out as one grouped launch (tile tables cached per pointer set)."""
 
     def __init__(self, shapes, dtype=torch.complex64):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]

@@ -1,9 +1,9 @@
 // Drives the library's C ABI through every host path the GPU tests take —
 // plans of all test shapes and pencil grids, every stream count, every launch
 // shape the library accepts, real-to-complex plans with the Poisson
-// operations and caller workspaces, timing mode, and batches in all three
-// issue modes including graph caching, pointer changes and capture by the
-// caller — against the host-only HIP stand-in, so AddressSanitizer and the
+// operations and caller workspaces, timing mode, both issue modes (a launch
+// per tile, a grouped launch per stage), and batches with their cached launch
+// tables, pointer changes and capture by the caller — against the host-only HIP stand-in, so AddressSanitizer and the
 // stand-in's launch checks see all of it.  Prints "hostsim ok" and exits 0
 // when nothing was flagged.
 //
@@ -92,6 +92,17 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
                 EXPECT(fft3d_backward(p, out.p, in.p, nullptr) == FFT3D_OK);
             }
+            // both issue modes, timed and not
+            for (int issue : {FFT3D_ISSUE_TILES, FFT3D_ISSUE_STAGES}) {
+                EXPECT(fft3d_set_issue(p, issue) == FFT3D_OK);
+                EXPECT(fft3d_get_issue(p) == issue);
+                EXPECT(fft3d_set_timing(p, 1) == FFT3D_OK);
+                EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+                EXPECT(fft3d_set_timing(p, 0) == FFT3D_OK);
+                EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+            }
+            EXPECT(fft3d_set_issue(p, 2) == FFT3D_ERR_INVALID_ARG);
+            EXPECT(fft3d_get_issue(nullptr) == -1);
             // more buffer sets, then a setter
             {
                 std::vector<std::unique_ptr<Buf>> extra;
@@ -362,7 +373,7 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
             EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), user) == FFT3D_OK);
             EXPECT(fft3d_forward_batch(b, in.data(), out.data(), nullptr) == FFT3D_OK);
         }
-        // more pointer sets than cached graphs (one graph each)
+        // more pointer sets than cached launch tables (one table set each)
         for (int rep = 0; rep < 12; ++rep) {
             std::vector<Buf*> fresh;
             std::vector<void*> o2;
@@ -375,7 +386,7 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
             EXPECT(hipStreamSynchronize(user) == hipSuccess);
             for (Buf* x : fresh) delete x;
         }
-        // stage configs of each distinct shape drop the cached graphs
+        // stage configs of each distinct shape drop the cached launch tables
         for (int f = 0; f < n; ++f) {
             EXPECT(fft3d_batch_set_stage_config(b, dims[3 * f], dims[3 * f + 1], dims[3 * f + 2], 1, 4, 1, 0, 0) ==
                    FFT3D_OK);

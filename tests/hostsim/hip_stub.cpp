@@ -386,10 +386,19 @@ hipError_t hipGraphAddEmptyNode(hipGraphNode_t* n, hipGraph_t g, const hipGraphN
     return add_node(n, g, deps, nd, "hipGraphAddEmptyNode");
 }
 
-hipError_t hipLaunchKernel(const void* f, dim3, dim3, void** args, size_t, hipStream_t s)
+namespace fft3d {
+void check_grouped(const void* f, dim3 grid, const StageArgs& a);  // below, with the kernel stand-ins
+}
+
+hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3, void** args, size_t, hipStream_t s)
 {
     if (!f || !args || !args[0]) violation("kernel launch without a function or arguments");
     if (!stream_ok(s, "kernel launch")) return hipErrorInvalidHandle;
+    if (args && args[0]) {
+        const fft3d::StageArgs& a = *static_cast<const fft3d::StageArgs*>(args[0]);
+        if (!a.in || !a.out) violation("kernel launch without its buffers");
+        fft3d::check_grouped(f, grid, a);
+    }
     enqueue(s);
     ++g_launches;
     return hipSuccess;
@@ -457,6 +466,10 @@ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 void check_range(const void* base, size_t es, int64_t off, int64_t A, int64_t sa, int64_t B, int64_t sb, int64_t len,
                  int64_t se, const char* what)
 {
+    // no buffer yet: a launch recorded for a grouped launch, whose buffers
+    // come at issue (hipLaunchKernel rejects a launch without them, and
+    // check_grouped checks every tile against them)
+    if (!base) return;
     const int64_t lo = off;
     const int64_t hi = off + (A - 1) * sa + (B - 1) * sb + (len - 1) * se;
     if (lo < 0) {
@@ -472,12 +485,23 @@ void check_tables(const StageArgs& a, int n, size_t es, const char* what)
     if (s) in_alloc(a.twp, s * es, what);
 }
 
+// Stand-in kernel functions: one per kernel kind, length(s) and precision,
+// as the GPU build has one instantiation per such set.  A grouped launch
+// (StageArgs::tiles) names one of them; check_grouped re-runs its checks on
+// every tile of the table.
+struct StubKernel {
+    int kind, n, n2, dtype;
+};
+std::map<std::vector<int>, StubKernel> g_kernels;  // node addresses stay put
+bool g_checking = false;  // re-checking a tile of a grouped launch: launch nothing
+
 // The checked launch goes through the library's launch hook, which launches
-// (hipLaunchKernel below) or records a graph node description.
-const int g_stub_kernel = 0;
-hipError_t launched(const fft3d::StageArgs& a, hipStream_t s)
+// (hipLaunchKernel above) or records the launch for a grouped one.
+hipError_t launched(const fft3d::StageArgs& a, hipStream_t s, int kind, int n, int n2, int dtype)
 {
-    return fft3d::launch_stage_kernel(&g_stub_kernel, dim3(1), dim3(64), a, 0, s);
+    if (g_checking) return hipSuccess;
+    const StubKernel& k = g_kernels.emplace(std::vector<int>{kind, n, n2, dtype}, StubKernel{kind, n, n2, dtype}).first->second;
+    return fft3d::launch_stage_kernel(&k, dim3(1), dim3(64), a, 0, s);
 }
 
 }  // namespace
@@ -516,7 +540,7 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
         check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, n, 1, "c2c store");
     }
     check_tables(a, n, es, "c2c pass table");
-    return launched(a, s);
+    return launched(a, s, K_C2C, n, 0, dtype);
 }
 
 static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -534,7 +558,7 @@ static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hi
     check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, lout, 1, r2c ? "r2c store" : "c2r store");
     in_alloc(a.tw, (size_t)(h + 1) * es, "real kernel root table");
     check_tables(a, h, es, "real kernel pass table");
-    return launched(a, s);
+    return launched(a, s, r2c ? K_R2C_X : K_C2R_X, n, 0, dtype);
 }
 
 hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s) { return launch_real(true, n, dtype, a, s); }
@@ -553,7 +577,7 @@ hipError_t launch_c2c_xy(int nx, int ny, int dtype, const StageArgs& a, hipStrea
     if (a.twp) check_tables(a, nx, es, "plane x pass table");
     const size_t sy = table_entries(ny);
     if (sy) in_alloc(a.twp2, sy * es, "plane y pass table");
-    return launched(a, s);
+    return launched(a, s, K_C2C_XY, nx, ny, dtype);
 }
 
 hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -568,7 +592,7 @@ hipError_t launch_poisson_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     check_range(a.in, es, a.off, a.A, 1, a.B, a.sb, n, a.se, "poisson load");
     check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "poisson store");
     check_tables(a, n, es, "poisson pass table");
-    return launched(a, s);
+    return launched(a, s, K_POISSON_Z, n, 0, dtype);
 }
 
 hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s)
@@ -584,7 +608,57 @@ hipError_t launch_r2r_z(int n, int dtype, const StageArgs& a, hipStream_t s)
     check_range(a.out, es, a.off_o, a.A, 1, a.B, a.sb_o, n, a.se_o, "r2r store");
     check_tables(a, n, es, "r2r pass table");
     in_alloc(a.tw, (size_t)n * es, "r2r W_4n roots");
-    return launched(a, s);
+    return launched(a, s, K_R2R_Z, n, 0, dtype);
+}
+
+// A grouped launch: the table lies in one allocation and holds grid.x / gmax
+// tiles, each with no more workgroups than gmax, and every tile passes the
+// checks of a launch of its own (the launch's buffers where the entry has
+// none).
+void check_grouped(const void* f, dim3 grid, const StageArgs& a)
+{
+    if (!a.tiles) return;
+    const StubKernel* k = nullptr;
+    for (const auto& kv : g_kernels)
+        if (&kv.second == f) k = &kv.second;
+    if (!k) {
+        violation("grouped launch of an unknown kernel");
+        return;
+    }
+    if (a.gmax < 1 || grid.x % a.gmax != 0 || grid.y != 1 || grid.z != 1) {
+        violation("grouped launch grid %u x %u x %u with gmax %lld", grid.x, grid.y, grid.z, (long long)a.gmax);
+        return;
+    }
+    const int64_t count = grid.x / a.gmax;
+    if (!in_alloc(a.tiles, (size_t)count * sizeof(TileEntry), "tile table")) return;
+    g_checking = true;
+    for (int64_t i = 0; i < count; ++i) {
+        const TileEntry& e = a.tiles[i];
+        if (e.gx < 1 || e.gy < 1 || e.gx * e.gy > a.gmax) violation("tile %lld of a grouped launch has %lld x %lld workgroups, gmax %lld", (long long)i, (long long)e.gx, (long long)e.gy, (long long)a.gmax);
+        StageArgs b = a;
+        b.tiles = nullptr;
+        b.gmax = 0;
+        if (e.in) b.in = e.in;
+        if (e.out) b.out = e.out;
+        b.off = e.off;
+        b.off_o = e.off_o;
+        b.A = e.A;
+        b.B = e.B;
+        b.kx0 = e.kx0;
+        b.ky0 = e.ky0;
+        hipError_t r = hipSuccess;
+        switch (k->kind) {
+        case K_C2C: r = launch_c2c(k->n, k->dtype, b, nullptr); break;
+        case K_R2C_X: r = launch_r2c_x(k->n, k->dtype, b, nullptr); break;
+        case K_C2R_X: r = launch_c2r_x(k->n, k->dtype, b, nullptr); break;
+        case K_C2C_XY: r = launch_c2c_xy(k->n, k->n2, k->dtype, b, nullptr); break;
+        case K_POISSON_Z: r = launch_poisson_z(k->n, k->dtype, b, nullptr); break;
+        case K_R2R_Z: r = launch_r2r_z(k->n, k->dtype, b, nullptr); break;
+        default: violation("grouped launch of kernel kind %d", k->kind);
+        }
+        if (r != hipSuccess) violation("tile %lld of a grouped launch fails its own launch checks", (long long)i);
+    }
+    g_checking = false;
 }
 
 // The library's static device scratch: one stand-in allocation made before

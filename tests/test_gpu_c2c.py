@@ -12,6 +12,7 @@ import torch
 import oracle
 import synth
 from _util import assert_parity, bound, promoted, rel, to_dev, to_host
+from paper_2601_12209_amd._lib import Fft3dError
 
 pytestmark = pytest.mark.gpu
 
@@ -119,6 +120,58 @@ def test_grid_and_stream_invariance_bitwise(gpu_lib):
                 ref = y.clone()
             assert torch.equal(y, ref), (grid, ns)
             plan.close()
+
+
+ISSUE_CASES = [((64, 64, 64), (4, 4), 0), ((128, 120, 100), (3, 3), 0), ((32, 32, 32), (2, 2), 1),
+               ((25, 30, 24), (4, 5), 0), ((16, 64, 64), (1, 4), 2)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid,staging", ISSUE_CASES, ids=[f"{s}-{g}-st{t}" for s, g, t in ISSUE_CASES])
+def test_issue_modes_bitwise(gpu_lib, shape, grid, staging, dtype):
+    """One grouped launch per stage (the tiles found in a device table) gives
+    the same bits as one launch per tile on the plan's streams: forward,
+    inverse and backward, over several buffer sets, in place, on a side
+    stream with eager work in between, with stage timing on, and after
+    setters that rebuild the tables."""
+    print(f"case issue modes shape={shape} grid={grid} staging={staging} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 46)
+    x = to_dev(a, dtype)
+    tiles = gpu_lib.Plan(shape, dtype, grid, streams=3, staging=staging, issue=gpu_lib.ISSUE_TILES)
+    ref_f, ref_i, ref_b = tiles.forward(x), tiles.inverse(x), tiles.backward(x)
+    torch.cuda.synchronize()
+    tiles.close()
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=3, staging=staging)
+    assert plan.issue == gpu_lib.ISSUE_STAGES
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            X, Y = plan.forward(x), plan.inverse(x)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            B = plan.backward(x)
+        side.synchronize()
+        assert torch.equal(X, ref_f) and torch.equal(Y, ref_i) and torch.equal(B, ref_b), rep
+        del junk
+    for _ in range(4):  # other buffers, in place
+        z = x.clone()
+        plan.forward(z, out=z)
+    torch.cuda.synchronize()
+    assert torch.equal(z, ref_f)
+    plan.set_timing(True)
+    X = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref_f) and len(plan.stage_times()) > 0
+    plan.set_timing(False)
+    plan.set_streams(2)
+    try:
+        plan.set_stage_config(1, 4)
+    except Fft3dError:  # no y kernel of that shape for this plan
+        pass
+    X = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref_f)
+    assert_parity(to_host(X), oracle.fftn(promoted(a, dtype)), bound(dtype, a.size))
+    plan.close()
 
 
 def test_alias_and_argument_errors(gpu_lib):

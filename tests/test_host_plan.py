@@ -450,7 +450,7 @@ def test_cache_policy_large_c2c(fft3d):
                 assert L["align"] <= 1
                 want = 0 if (dtype == "c64" and st["axis"] != 0) else 2
                 assert L["nt"] == want, (dtype, op, st, L)
-    # the complex64 strided stages take 32 lines, two threads per line fewer, full LDS tile
+    # the complex64 strided stages take 32 lines, half the threads per line, full LDS tile
     _, L = _by_stage(fft3d, (512, 512, 512), "c64", staging=1)[1]
     assert (L["lw"], L["tdiv"], L["split"]) == (32, 2, 0)
 
@@ -475,15 +475,17 @@ def test_r2c_launches(fft3d):
         assert x["kind"] == 1 and Lx["pad"] == 1 and Lx["nt"] == 0 and Lx["strided"] == 0
         per_line = 16 if dtype == "f32" else 8
         assert Lz["align"] == per_line and Ly["align"] <= 1  # z writes the 257-value rows of the output
-        if dtype == "f32":
-            assert Ly["nt"] == 0 and Lz["nt"] == 0
-        else:  # rows of 257 values are read misaligned: stores only
-            assert Ly["nt"] == 1 and Lz["nt"] == 1 and Ly["xcd"] == 1 and Lz["xcd"] == 1
+        # rows of 257 values are read misaligned: non-temporal stores only
+        assert Ly["nt"] == 1 and Lz["nt"] == 1
+        if dtype == "f32":  # 257 columns: 16-line tiles, full complex LDS tile
+            assert (Ly["lw"], Ly["tdiv"], Ly["split"]) == (16, 1, 0)
+        if dtype == "f64":
+            assert Ly["xcd"] == 1 and Lz["xcd"] == 1
         inv = _by_stage(fft3d, (512, 512, 512), dtype, r2c=True, op=1)
         (z, Lz), (y, Ly), (x, Lx) = inv
         assert x["kind"] == 2 and Lx["pad"] == 1 and Lx["nt"] == 0
         assert y["src"] == y["dst"] == 2 and Ly["nt"] == 1  # in place in the workspace
-        assert Lz["nt"] == (0 if dtype == "f32" else 1)
+        assert Lz["nt"] == 1
     # small R2C plans: plain accesses, padded real kernels
     for st, L in _by_stage(fft3d, (32, 32, 32), "f32", r2c=True, op=3):
         assert L["nt"] == 0

@@ -1,11 +1,11 @@
 """Host code of the library under AddressSanitizer / UndefinedBehaviorSanitizer.
 
-The C++ sources of the planner, executor, batch task graphs and C ABI are
+The C++ sources of the planner, executor, batch issue and C ABI are
 built with g++ against a host-only stand-in for the HIP runtime
 (tests/hostsim/hip_stub.cpp) and driven through every host path the GPU
 tests take (tests/hostsim/driver.cpp).  The stand-in checks every stage-kernel
-launch's tile address range against its allocations, the thread and LDS
-limits, and the stream / event / graph-capture rules (fork-join closure,
+launch's tile address range against its allocations (every tile of a
+grouped launch's device table included), the thread and LDS limits, and the stream / event / graph-capture rules (fork-join closure,
 no synchronisation inside a capture, no use of destroyed handles).  Any
 sanitizer report, flagged launch, failed expectation or leaked allocation
 fails the test.
