@@ -134,202 +134,216 @@ def _progress(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-def _extras(reps, torch, fft3d, synth, np):
-    """The other workloads, timed on the GPU.  Returns (report, checks) where
-    checks holds (name, GPU result on the host, function giving the FP64 oracle
-    result) for the CPU-baseline leg."""
+EXTRAS = ("r2c512", "grid256", "r2c1024", "c840", "batch", "poisson")
+
+
+def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
+    """The other workloads (those named in `only`), timed on the GPU.  Returns
+    (report, checks) where checks holds (name, GPU result on the host, function
+    giving the FP64 oracle result) for the CPU-baseline leg."""
     rep, checks = {}, []
+
+    def want(name):
+        return name in only
+
     n = 512
     N = n ** 3
     nh = (n // 2 + 1) * n * n
-    for dt, tag, sr, npdt in ((torch.float32, "f32", 4, np.float32), (torch.float64, "f64", 8, np.float64)):
-        _progress(f"extras: 512^3 r2c {tag}")
-        f = synth.real_normal((n, n, n), 10, npdt)
-        x = torch.from_numpy(f).cuda()
-        p = fft3d.Plan((n, n, n), dt, r2c=True)
-        H = p.forward(x)
-        y = p.inverse(H)
-        ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), reps, torch)
-        bytes_moved = 2 * N * sr + 10 * nh * 2 * sr  # x stage real in/out, 5 half-spectrum passes each way
-        rep[f"r2c_512cubed_fwd_inv_{tag}"] = {
-            "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        Hh, yh = H.cpu().numpy(), y.cpu().numpy()
-        checks.append((f"r2c_512cubed_{tag}_forward", Hh, lambda f=f: _oracle().rfftn(f.astype(np.float64))))
-        checks.append((f"r2c_512cubed_{tag}_roundtrip", yh, lambda f=f: f.astype(np.float64)))
-        p.close()
-        del x, H, y
-        torch.cuda.empty_cache()
-    # 256^3 C2C on the 4x4 pencil grid of tiles, and 1x1 for comparison
-    cfg = synth.CFG2
-    m = cfg["shape"][0] ** 3
-    a = synth.complex_normal(cfg["shape"], cfg["seed"], np.complex64)
     side = torch.cuda.Stream()
-    for dt, tag, es in ((torch.complex64, "c64", 8), (torch.complex128, "c128", 16)):
-        _progress(f"extras: 256^3 c2c {tag}")
-        x = torch.from_numpy(a).to("cuda", dt)
-        g2 = tuple(cfg["grid"])
-        for grid, ns, issue, suffix in ((g2, 4, fft3d.ISSUE_STAGES, ""), (g2, 4, fft3d.ISSUE_TILES, "_tiles"),
-                                        ((1, 1), 1, fft3d.ISSUE_STAGES, "")):
-            p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns, issue=issue)
-            X = p.forward(x)
-            Y = torch.empty_like(X)
-            with torch.cuda.stream(side):
-                ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), reps, torch)
-            name = f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}{suffix}"
-            rep[name] = {
-                "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "issue": (f"tiles on {ns} stream(s)" if issue == fft3d.ISSUE_TILES or grid == (1, 1)
-                          else "one grouped launch per stage")}
-            if grid != (1, 1) and issue == fft3d.ISSUE_STAGES:
-                torch.cuda.synchronize()
-                checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),
-                               lambda: _oracle().fftn(a.astype(np.complex128))))
+    if want("r2c512"):
+        for dt, tag, sr, npdt in ((torch.float32, "f32", 4, np.float32), (torch.float64, "f64", 8, np.float64)):
+            _progress(f"extras: 512^3 r2c {tag}")
+            f = synth.real_normal((n, n, n), 10, npdt)
+            x = torch.from_numpy(f).cuda()
+            p = fft3d.Plan((n, n, n), dt, r2c=True)
+            H = p.forward(x)
+            y = p.inverse(H)
+            ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), reps, torch)
+            bytes_moved = 2 * N * sr + 10 * nh * 2 * sr  # x stage real in/out, 5 half-spectrum passes each way
+            rep[f"r2c_512cubed_fwd_inv_{tag}"] = {
+                "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            Hh, yh = H.cpu().numpy(), y.cpu().numpy()
+            checks.append((f"r2c_512cubed_{tag}_forward", Hh, lambda f=f: _oracle().rfftn(f.astype(np.float64))))
+            checks.append((f"r2c_512cubed_{tag}_roundtrip", yh, lambda f=f: f.astype(np.float64)))
             p.close()
+            del x, H, y
+            torch.cuda.empty_cache()
+    if want("grid256"):
+        # 256^3 C2C on the 4x4 pencil grid of tiles, and 1x1 for comparison
+        cfg = synth.CFG2
+        m = cfg["shape"][0] ** 3
+        a = synth.complex_normal(cfg["shape"], cfg["seed"], np.complex64)
+        side = torch.cuda.Stream()
+        for dt, tag, es in ((torch.complex64, "c64", 8), (torch.complex128, "c128", 16)):
+            _progress(f"extras: 256^3 c2c {tag}")
+            x = torch.from_numpy(a).to("cuda", dt)
+            g2 = tuple(cfg["grid"])
+            for grid, ns, issue, suffix in ((g2, 4, fft3d.ISSUE_STAGES, ""), (g2, 4, fft3d.ISSUE_TILES, "_tiles"),
+                                            ((1, 1), 1, fft3d.ISSUE_STAGES, "")):
+                p = fft3d.Plan(cfg["shape"], dt, grid, streams=ns, issue=issue)
+                X = p.forward(x)
+                Y = torch.empty_like(X)
+                with torch.cuda.stream(side):
+                    ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), reps, torch)
+                name = f"c2c_256cubed_{tag}_grid{grid[0]}x{grid[1]}{suffix}"
+                rep[name] = {
+                    "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m * math.log2(m) / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(12 * es * m / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "issue": (f"tiles on {ns} stream(s)" if issue == fft3d.ISSUE_TILES or grid == (1, 1)
+                              else "one grouped launch per stage")}
+                if grid != (1, 1) and issue == fft3d.ISSUE_STAGES:
+                    torch.cuda.synchronize()
+                    checks.append((f"c2c_256cubed_{tag}_forward", X.cpu().numpy(),
+                                   lambda: _oracle().fftn(a.astype(np.complex128))))
+                p.close()
+            del x
+            torch.cuda.empty_cache()
+    if want("r2c1024"):
+        # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (one grouped
+        # launch per stage, and one launch per tile on the plan's streams) and on
+        # one tile per stage; the values do not change the
+        # timing, so the input is torch's normal generator (parity of the
+        # turbulence field at this size is a GPU test)
+        c3 = synth.CFG3
+        m3 = int(np.prod(c3["shape"]))
+        nh3 = (c3["shape"][2] // 2 + 1) * c3["shape"][0] * c3["shape"][1]
+        x = torch.randn(c3["shape"], dtype=torch.float32, device="cuda")
+        g3 = tuple(c3["grid"])
+        for grid, issue, suffix in ((g3, fft3d.ISSUE_STAGES, ""), (g3, fft3d.ISSUE_TILES, "_tiles"),
+                                    ((1, 1), fft3d.ISSUE_STAGES, "")):
+            _progress(f"extras: 1024^3 r2c grid {grid}{suffix}")
+            p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True, issue=issue)
+            H = p.forward(x)
+            y = torch.empty_like(x)
+            with torch.cuda.stream(side):
+                ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), max(3, reps // 2), torch)
+            bytes_moved = 2 * m3 * 4 + 10 * nh3 * 2 * 4
+            rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}{suffix}"] = {
+                "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * m3 * math.log2(m3) / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "issue": ("one tile per stage" if grid == (1, 1) else
+                          "tiles on 4 streams" if issue == fft3d.ISSUE_TILES else "one grouped launch per stage")}
+            p.close()
+            del H, y
         del x
         torch.cuda.empty_cache()
-    # 1024^3 float32 R2C + C2R on the 8x8 pencil grid of tiles (one grouped
-    # launch per stage, and one launch per tile on the plan's streams) and on
-    # one tile per stage; the values do not change the
-    # timing, so the input is torch's normal generator (parity of the
-    # turbulence field at this size is a GPU test)
-    c3 = synth.CFG3
-    m3 = int(np.prod(c3["shape"]))
-    nh3 = (c3["shape"][2] // 2 + 1) * c3["shape"][0] * c3["shape"][1]
-    x = torch.randn(c3["shape"], dtype=torch.float32, device="cuda")
-    g3 = tuple(c3["grid"])
-    for grid, issue, suffix in ((g3, fft3d.ISSUE_STAGES, ""), (g3, fft3d.ISSUE_TILES, "_tiles"),
-                                ((1, 1), fft3d.ISSUE_STAGES, "")):
-        _progress(f"extras: 1024^3 r2c grid {grid}{suffix}")
-        p = fft3d.Plan(c3["shape"], torch.float32, grid, r2c=True, issue=issue)
-        H = p.forward(x)
-        y = torch.empty_like(x)
+    if want("c840"):
+        # 840^3 complex64: the largest grid of the paper's GPU runs (lengths with a
+        # factor 7), whole on one GPU; parity is covered by the GPU tests
+        _progress("extras: 840^3 c2c")
+        n8 = 840
+        m8 = n8 ** 3
+        x = torch.randn((n8, n8, n8), dtype=torch.complex64, device="cuda")
+        p = fft3d.Plan((n8, n8, n8), torch.complex64)
+        X = p.forward(x)
+        Y = torch.empty_like(X)
         with torch.cuda.stream(side):
-            ms = _time(lambda: (p.forward(x, out=H), p.inverse(H, out=y)), max(3, reps // 2), torch)
-        bytes_moved = 2 * m3 * 4 + 10 * nh3 * 2 * 4
-        rep[f"r2c_1024cubed_f32_grid{grid[0]}x{grid[1]}{suffix}"] = {
-            "ms": round(ms, 4), "GFLOP/s (2.5 N log2 N per transform)": round(2 * 2.5 * m3 * math.log2(m3) / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(bytes_moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "issue": ("one tile per stage" if grid == (1, 1) else
-                      "tiles on 4 streams" if issue == fft3d.ISSUE_TILES else "one grouped launch per stage")}
+            ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), max(3, reps // 2), torch)
+        rep["c2c_840cubed_c64_grid1x1"] = {
+            "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m8 * math.log2(m8) / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(12 * 8 * m8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         p.close()
-        del H, y
-    del x
-    torch.cuda.empty_cache()
-    # 840^3 complex64: the largest grid of the paper's GPU runs (lengths with a
-    # factor 7), whole on one GPU; parity is covered by the GPU tests
-    _progress("extras: 840^3 c2c")
-    n8 = 840
-    m8 = n8 ** 3
-    x = torch.randn((n8, n8, n8), dtype=torch.complex64, device="cuda")
-    p = fft3d.Plan((n8, n8, n8), torch.complex64)
-    X = p.forward(x)
-    Y = torch.empty_like(X)
-    with torch.cuda.stream(side):
-        ms = _time(lambda: (p.forward(x, out=X), p.inverse(X, out=Y)), max(3, reps // 2), torch)
-    rep["c2c_840cubed_c64_grid1x1"] = {
-        "ms": round(ms, 4), "GFLOP/s": round(2 * 5 * m8 * math.log2(m8) / (ms * 1e-3) / 1e9, 1),
-        "hbm_frac": round(12 * 8 * m8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    p.close()
-    del x, X, Y
-    torch.cuda.empty_cache()
-    # 64 uneven transforms, one grouped launch per shape and stage, on a
-    # non-default stream
-    _progress("extras: 64 uneven transforms")
-    shapes = synth.batch_sizes()
-    host = synth.batch_inputs(shapes, synth.CFG4["seed"])
-    xs = [torch.from_numpy(h).cuda() for h in host]
-    outs = [torch.empty_like(t) for t in xs]
-    pts = sum(int(np.prod(sh)) for sh in shapes)
-    flops = sum(5 * np.prod(sh) * math.log2(np.prod(sh)) for sh in shapes)
-    # shapes whose planes fit the fused x-y kernel take two passes over HBM
-    # (the batch's default there), the others three
-    probe = fft3d.BatchPlan(shapes)
-    fused = set()
-    for sh in set(shapes):
-        try:
-            probe.set_staging(sh, fft3d.STAGING_FUSED_XY)
-            fused.add(sh)
-        except RuntimeError:
-            pass
-    probe.close()
-    bbytes = sum((2 if sh in fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
-    brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
-            "hbm_bytes_per_call": bbytes}
-    side = torch.cuda.Stream()
-    # launch shapes per transform shape from the autotuner (untimed; measured
-    # once, then taken from its cache file, a temporary one here)
-    from paper_2601_12209_amd import autotune
-    import tempfile
-    tune_path = os.path.join(tempfile.gettempdir(), f"fft3d_tune_{os.getpid()}.json")
-    own_cache = "FFT3D_TUNE_CACHE" not in os.environ
-    if own_cache:
-        os.environ["FFT3D_TUNE_CACHE"] = tune_path
-    brep["launch_shapes"] = "autotuned"
-    bp = fft3d.BatchPlan(shapes)
-    autotune.tune_batch(bp, reps=5)
-    with torch.cuda.stream(side):
-        ms = _time(lambda: bp.forward(xs, outs), reps, torch)
-    brep["grouped"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
-                          "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    bp.close()
-    # for comparison: the same transforms one after another, each through its own
-    # plan (same staging per shape, default launch shapes) on one stream
-    plans = {}
-    for sh in set(shapes):
-        pl = fft3d.Plan(sh, torch.complex64)
-        if sh in fused:
-            pl.set_staging(fft3d.STAGING_FUSED_XY)
-        else:
-            pl.set_staging(fft3d.STAGING_IN_PLACE)
-        plans[sh] = pl
+        del x, X, Y
+        torch.cuda.empty_cache()
+    if want("batch"):
+        # 64 uneven transforms, one grouped launch per shape and stage, on a
+        # non-default stream
+        _progress("extras: 64 uneven transforms")
+        shapes = synth.batch_sizes()
+        host = synth.batch_inputs(shapes, synth.CFG4["seed"])
+        xs = [torch.from_numpy(h).cuda() for h in host]
+        outs = [torch.empty_like(t) for t in xs]
+        pts = sum(int(np.prod(sh)) for sh in shapes)
+        flops = sum(5 * np.prod(sh) * math.log2(np.prod(sh)) for sh in shapes)
+        # shapes whose planes fit the fused x-y kernel take two passes over HBM
+        # (the batch's default there), the others three
+        probe = fft3d.BatchPlan(shapes)
+        fused = set()
+        for sh in set(shapes):
+            try:
+                probe.set_staging(sh, fft3d.STAGING_FUSED_XY)
+                fused.add(sh)
+            except RuntimeError:
+                pass
+        probe.close()
+        bbytes = sum((2 if sh in fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
+        brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
+                "hbm_bytes_per_call": bbytes}
+        side = torch.cuda.Stream()
+        # launch shapes per transform shape from the autotuner (untimed; measured
+        # once, then taken from its cache file, a temporary one here)
+        from paper_2601_12209_amd import autotune
+        import tempfile
+        tune_path = os.path.join(tempfile.gettempdir(), f"fft3d_tune_{os.getpid()}.json")
+        own_cache = "FFT3D_TUNE_CACHE" not in os.environ
+        if own_cache:
+            os.environ["FFT3D_TUNE_CACHE"] = tune_path
+        brep["launch_shapes"] = "autotuned"
+        bp = fft3d.BatchPlan(shapes)
+        autotune.tune_batch(bp, reps=5)
+        with torch.cuda.stream(side):
+            ms = _time(lambda: bp.forward(xs, outs), reps, torch)
+        brep["grouped"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        bp.close()
+        # for comparison: the same transforms one after another, each through its own
+        # plan (same staging per shape, default launch shapes) on one stream
+        plans = {}
+        for sh in set(shapes):
+            pl = fft3d.Plan(sh, torch.complex64)
+            if sh in fused:
+                pl.set_staging(fft3d.STAGING_FUSED_XY)
+            else:
+                pl.set_staging(fft3d.STAGING_IN_PLACE)
+            plans[sh] = pl
 
-    def serial():
-        for sh, x_, o_ in zip(shapes, xs, outs):
-            plans[sh].forward(x_, out=o_)
+        def serial():
+            for sh, x_, o_ in zip(shapes, xs, outs):
+                plans[sh].forward(x_, out=o_)
 
-    with torch.cuda.stream(side):
-        ms = _time(serial, reps, torch)
-    brep["serial_one_stream"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
-                                 "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    for pl in plans.values():
-        pl.close()
-    bp = fft3d.BatchPlan(shapes)
-    autotune.tune_batch(bp, reps=5)
-    with torch.cuda.stream(side):
-        bp.forward(xs, outs)
-    torch.cuda.synchronize()
-    bp.close()
-    if own_cache:
-        del os.environ["FFT3D_TUNE_CACHE"]
-        try:
-            os.remove(tune_path)
-        except OSError:
-            pass
-    rep["batched_64_uneven_c64"] = brep
-    checks.append(("batched_64_uneven_forward_worst", [o.cpu().numpy() for o in outs],
-                   lambda: [_oracle().fftn(h.astype(np.complex128)) for h in host]))
-    del xs, outs
-    torch.cuda.empty_cache()
-    # differentiable Poisson solve, 256^3 float32: forward solve + adjoint (one gradient step)
-    _progress("extras: 256^3 Poisson")
-    c5 = synth.CFG5
-    f = synth.smooth_field(c5["shape"], c5["seed_f"], c5["sigma"], np.float32)
-    w = synth.real_normal(c5["shape"], c5["seed_w"], np.float32)
-    fd, wd = torch.from_numpy(f).cuda(), torch.from_numpy(w).cuda()
-    p = fft3d.Plan(c5["shape"], torch.float32, r2c=True)
-    phi = p.poisson(fd)
-    g = p.poisson_backward(wd)
-    ms = _time(lambda: (p.poisson(fd, out=phi), p.poisson_backward(wd, out=g)), reps, torch)
-    m = int(np.prod(c5["shape"]))
-    mh = (c5["shape"][2] // 2 + 1) * c5["shape"][0] * c5["shape"][1]
-    pbytes = 2 * (2 * m * 4 + 8 * mh * 8)  # per solve: real in/out + 4 half-spectrum passes
-    rep["poisson_256cubed_f32_solve_plus_adjoint"] = {
-        "ms": round(ms, 4), "hbm_frac": round(pbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    checks.append(("poisson_256cubed_solution", phi.cpu().numpy(), lambda: _oracle().poisson(f.astype(np.float64))))
-    checks.append(("poisson_256cubed_gradient", g.cpu().numpy(), lambda: _oracle().poisson_grad(w.astype(np.float64))))
-    p.close()
+        with torch.cuda.stream(side):
+            ms = _time(serial, reps, torch)
+        brep["serial_one_stream"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
+                                     "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        for pl in plans.values():
+            pl.close()
+        bp = fft3d.BatchPlan(shapes)
+        autotune.tune_batch(bp, reps=5)
+        with torch.cuda.stream(side):
+            bp.forward(xs, outs)
+        torch.cuda.synchronize()
+        bp.close()
+        if own_cache:
+            del os.environ["FFT3D_TUNE_CACHE"]
+            try:
+                os.remove(tune_path)
+            except OSError:
+                pass
+        rep["batched_64_uneven_c64"] = brep
+        checks.append(("batched_64_uneven_forward_worst", [o.cpu().numpy() for o in outs],
+                       lambda: [_oracle().fftn(h.astype(np.complex128)) for h in host]))
+        del xs, outs
+        torch.cuda.empty_cache()
+    if want("poisson"):
+        # differentiable Poisson solve, 256^3 float32: forward solve + adjoint (one gradient step)
+        _progress("extras: 256^3 Poisson")
+        c5 = synth.CFG5
+        f = synth.smooth_field(c5["shape"], c5["seed_f"], c5["sigma"], np.float32)
+        w = synth.real_normal(c5["shape"], c5["seed_w"], np.float32)
+        fd, wd = torch.from_numpy(f).cuda(), torch.from_numpy(w).cuda()
+        p = fft3d.Plan(c5["shape"], torch.float32, r2c=True)
+        phi = p.poisson(fd)
+        g = p.poisson_backward(wd)
+        ms = _time(lambda: (p.poisson(fd, out=phi), p.poisson_backward(wd, out=g)), reps, torch)
+        m = int(np.prod(c5["shape"]))
+        mh = (c5["shape"][2] // 2 + 1) * c5["shape"][0] * c5["shape"][1]
+        pbytes = 2 * (2 * m * 4 + 8 * mh * 8)  # per solve: real in/out + 4 half-spectrum passes
+        rep["poisson_256cubed_f32_solve_plus_adjoint"] = {
+            "ms": round(ms, 4), "hbm_frac": round(pbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        checks.append(("poisson_256cubed_solution", phi.cpu().numpy(), lambda: _oracle().poisson(f.astype(np.float64))))
+        checks.append(("poisson_256cubed_gradient", g.cpu().numpy(), lambda: _oracle().poisson_grad(w.astype(np.float64))))
+        p.close()
     return rep, checks
 
 
@@ -350,6 +364,16 @@ def _oracle():
     return oracle
 
 
+def _extras_names(spec):
+    if spec == "all":
+        return EXTRAS
+    names = tuple(v for v in spec.split(",") if v)
+    bad = [v for v in names if v not in EXTRAS]
+    if bad:
+        raise SystemExit(f"unknown extras {bad}; choose from {EXTRAS}")
+    return names
+
+
 def _run_extras_child(args):
     """The other workloads in a child process (its own HIP context), so that a
     failure there cannot take the headline record with it.  Returns (report,
@@ -359,7 +383,8 @@ def _run_extras_child(args):
 
     fd, path = tempfile.mkstemp(prefix="fft3d_extras_", suffix=".json")
     os.close(fd)
-    cmd = [sys.executable, os.path.abspath(__file__), "--extras-child", path, "--steps", str(args.steps)]
+    cmd = [sys.executable, os.path.abspath(__file__), "--extras-child", path, "--steps", str(args.steps),
+           "--extras", args.extras]
     if args.no_cpu_baseline:
         cmd.append("--no-cpu-baseline")
     try:
@@ -385,7 +410,7 @@ def _extras_child(args):
     from paper_2601_12209_amd import fft3d
 
     fft3d.load()
-    rep, checks = _extras(max(3, min(args.steps, 10)), torch, fft3d, synth, np)
+    rep, checks = _extras(max(3, min(args.steps, 10)), torch, fft3d, synth, np, _extras_names(args.extras))
     errs = {}
     if not args.no_cpu_baseline:
         oracle = _oracle()
@@ -415,6 +440,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle on the host")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (R2C 512^3, 256^3 grid, batch, Poisson)")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of the other workloads: " + ",".join(EXTRAS) + " (default all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy the complex64 field once with a plain device copy "
                          "(a known-size reference for HBM byte counters)")
