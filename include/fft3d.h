@@ -306,15 +306,15 @@ const char* fft3d_status_string(int status);
 const char* fft3d_last_error(void);
 
 /* --------------------------------------------------------- batches
- * Many independent 3D transforms of (possibly) different sizes issued as one
- * task graph (the paper's dynamically scheduled FFT tasks over uneven work,
- * Sec. III-C and IV-D): the stage kernels of every transform are appended,
- * node by node, to one hipGraph per operation and pointer set, a chain of
- * producer edges per transform and no edge between transforms, largest
- * transform first (the order of Alg. 3's placement); the graph is built on
- * first use and replayed afterwards (at most 8 cached), and the runtime
- * overlaps the stages of different transforms.  A call into a stream the
- * caller is capturing issues the transforms one after another on it. */
+ * Many independent 3D transforms of (possibly) different sizes (the paper's
+ * dynamically scheduled FFT tasks over uneven work, Sec. III-C and IV-D).  A
+ * call issues, stage by stage, one grouped launch per distinct shape, largest
+ * shape first (the order of Alg. 3's placement): the tiles of that stage of
+ * every transform of the shape in one kernel launch, each workgroup finding
+ * its transform's buffers and tile in a device table.  The tables of a
+ * pointer set are built on its first call (a blocking upload) and cached (at
+ * most 8 sets).  A call into a stream the caller is capturing issues the
+ * transforms one after another on it instead. */
 typedef struct fft3d_batch_s* fft3d_batch_t;
 
 /* dims holds count triples (nx, ny, nz), each a shape fft3d_plan accepts;
@@ -330,7 +330,7 @@ fft3d_status fft3d_inverse_batch(fft3d_batch_t plan, const void* const* in, void
 
 /* Launch shape of one stage of the transforms of one shape (arguments as
  * fft3d_set_stage_config); waits for the last call and drops the cached
- * graphs.  Used by the autotuner; results do not depend on it. */
+ * launch tables.  Used by the autotuner; results do not depend on it. */
 fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
                                           int lw, int tdiv, int split, int pad);
 
@@ -338,9 +338,12 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_
  * FFT3D_STAGING_FUSED_XY (the default where a fused kernel fits the plane;
  * UNSUPPORTED_SIZE where none does); a workspace staging is
  * FFT3D_ERR_INVALID_ARG, since transforms of one shape share their plan.
- * Waits for the last call and drops the cached graphs; results are bitwise
- * the same in both stagings. */
+ * Waits for the last call and drops the cached launch tables; results are
+ * bitwise the same in both stagings. */
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int staging);
+/* Staging of the transforms of one shape, or -1 (NULL plan, or no transform
+ * of that shape). */
+int fft3d_batch_get_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz);
 
 fft3d_status fft3d_batch_destroy(fft3d_batch_t plan);
 

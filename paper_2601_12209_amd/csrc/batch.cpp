@@ -321,6 +321,20 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
     return fft3d_set_staging(it->second, staging);
 }
 
+int fft3d_batch_get_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz)
+{
+    if (!b) {
+        set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+        return -1;
+    }
+    auto it = b->plans.find(Shape(nx, ny, nz));
+    if (it == b->plans.end()) {
+        set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
+        return -1;
+    }
+    return fft3d_get_staging(it->second);
+}
+
 fft3d_status fft3d_batch_destroy(fft3d_batch_t b)
 {
     if (b) release(b);

@@ -263,6 +263,14 @@ class BatchPlan:
         nz, ny, nx = shape
         check(_lib.lib().fft3d_batch_set_staging(self._h, nx, ny, nz, int(staging)), "fft3d_batch_set_staging")
 
+    def staging(self, shape) -> int:
+        """The staging of the transforms of one (nz, ny, nx) shape."""
+        nz, ny, nx = shape
+        v = int(_lib.lib().fft3d_batch_get_staging(self._h, nx, ny, nz))
+        if v < 0:
+            raise _lib.Fft3dError(-1, "fft3d_batch_get_staging")
+        return v
+
     def _run(self, fn, xs, outs, stream):
         dt = _COMPLEX[self.code]
         if len(xs) != len(self.shapes):

@@ -400,11 +400,14 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_FUSED_XY) ==
                    (planes ? FFT3D_OK : FFT3D_ERR_UNSUPPORTED_SIZE));
             EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
+            if (planes) EXPECT(fft3d_batch_get_staging(b, d[0], d[1], d[2]) == FFT3D_STAGING_FUSED_XY);
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_IN_PLACE) == FFT3D_OK);
             EXPECT(fft3d_batch_set_staging(b, d[0], d[1], d[2], FFT3D_STAGING_SWAP_YZ) == FFT3D_ERR_INVALID_ARG);
         }
         EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_staging(b, 3, 3, 3, FFT3D_STAGING_IN_PLACE) == FFT3D_ERR_INVALID_ARG);
+        EXPECT(fft3d_batch_get_staging(b, 3, 3, 3) == -1);
+        EXPECT(fft3d_batch_get_staging(nullptr, 3, 3, 3) == -1);
         // the caller captures the batch into its own graph (twice: replays of
         // the plans' direct issue)
         for (int rep = 0; rep < 2; ++rep) {
