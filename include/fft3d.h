@@ -311,10 +311,14 @@ const char* fft3d_last_error(void);
  * call issues, stage by stage, one grouped launch per distinct shape, largest
  * shape first (the order of Alg. 3's placement): the tiles of that stage of
  * every transform of the shape in one kernel launch, each workgroup finding
- * its transform's buffers and tile in a device table.  The tables of a
- * pointer set are built on its first call (a blocking upload) and cached (at
- * most 8 sets).  A call into a stream the caller is capturing issues the
- * transforms one after another on it instead. */
+ * its transform's buffers and tile in a device table.  Each shape's chain of
+ * stage launches runs on one of the batch's own streams (4 by default,
+ * fft3d_batch_set_streams), shapes placed by Alg. 3's rule on their total
+ * cost, forked from and joined back to the caller's stream, so transforms of
+ * different shapes overlap.  The tables of a pointer set are built on its
+ * first call (a blocking upload) and cached (at most 8 sets).  A call into a
+ * stream the caller is capturing issues the transforms one after another on
+ * it instead. */
 typedef struct fft3d_batch_s* fft3d_batch_t;
 
 /* dims holds count triples (nx, ny, nz), each a shape fft3d_plan accepts;
@@ -341,6 +345,11 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_
  * Waits for the last call and drops the cached launch tables; results are
  * bitwise the same in both stagings. */
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int staging);
+/* Streams the batch's shapes run on concurrently (1..16, default 4; 1 runs
+ * every shape's launches in order on the caller's stream).  Waits for the last
+ * call and drops the cached launch tables; results are bitwise the same. */
+fft3d_status fft3d_batch_set_streams(fft3d_batch_t plan, int nstreams);
+
 /* Staging of the transforms of one shape, or -1 (NULL plan, or no transform
  * of that shape). */
 int fft3d_batch_get_staging(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz);

@@ -40,13 +40,16 @@ constexpr size_t kMaxCached = 8;  // pointer sets with launch tables kept per ba
 
 using Shape = std::tuple<int64_t, int64_t, int64_t>;
 
-// The launches of one operation on one pointer set, in issue order; grouped
-// launches point at the set's device table.
+constexpr int kDefaultStreams = 4;
+
+// The launches of one operation on one pointer set: one chain per stream
+// (the shapes placed on it, each shape's stages in order); grouped launches
+// point at the set's device table.
 struct CachedIssue {
     int op;
     std::vector<const void*> in;
     std::vector<void*> out;
-    std::vector<KernelLaunch> launches;
+    std::vector<std::vector<KernelLaunch>> chains;
     TileEntry* dev = nullptr;
 };
 
@@ -59,12 +62,18 @@ struct fft3d_batch_s {
     std::map<Shape, fft3d_plan_t> plans;  // one single-stream plan per distinct shape
     std::vector<int> order;               // transforms in decreasing cost (issue order)
     std::vector<CachedIssue> cache;
+    int nstreams = kDefaultStreams;  // shapes run concurrently on this many streams
+    std::vector<hipStream_t> streams;  // created on the first call that forks
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
     hipEvent_t done = nullptr;  // recorded on the caller's stream after each call
 };
 
 namespace {
 
 Shape shape_of(const PlanDesc& d) { return Shape(d.nx, d.ny, d.nz); }
+
+std::vector<double> batch_costs(const std::vector<PlanDesc>& ffts);
 
 // Wait for the work of the last call (the caller's stream itself may be gone).
 void wait_done(fft3d_batch_s* b)
@@ -83,6 +92,11 @@ void drop_cache(fft3d_batch_s* b)
 void release(fft3d_batch_s* b)
 {
     drop_cache(b);
+    for (hipStream_t st : b->streams)
+        if (st) hipStreamDestroy(st);
+    for (hipEvent_t ev : b->joins)
+        if (ev) hipEventDestroy(ev);
+    if (b->fork) hipEventDestroy(b->fork);
     if (b->done) hipEventDestroy(b->done);
     for (auto& kv : b->plans) fft3d_destroy(kv.second);
     delete b;
@@ -95,9 +109,12 @@ bool overlap(const void* a, size_t na, const void* c, size_t nc)
     return pa < pc + nc && pc < pa + na;
 }
 
-// Build the launches of operation op on this pointer set: for each stage,
-// for each shape (largest first), the stage tiles of all its transforms as
-// one grouped launch (or one by one where they cannot be grouped).
+// Build the launches of operation op on this pointer set.  Each distinct
+// shape gets one chain: per stage, the stage tiles of all its transforms as
+// one grouped launch (or one by one where they cannot be grouped).  Shapes
+// are placed on the batch's streams by Alg. 3's rule on their total cost
+// (count x N log2 N), largest first; with one stream every chain runs in
+// order on the caller's stream.
 fft3d_status build_issue(fft3d_batch_t b, int op, const void* const* in, void* const* out, CachedIssue* c)
 {
     const int pop = op == 0 ? OP_FORWARD : OP_INVERSE;
@@ -106,50 +123,54 @@ fft3d_status build_issue(fft3d_batch_t b, int op, const void* const* in, void* c
         const Shape sh = shape_of(b->ffts[f]);
         if (std::find(shapes.begin(), shapes.end(), sh) == shapes.end()) shapes.push_back(sh);
     }
-    int nst = 0;
-    for (const Shape& sh : shapes) nst = std::max(nst, stage_count(b->plans[sh], pop));
-    std::vector<std::vector<KernelLaunch>> groups;  // per launch group
-    std::vector<char> grouped;
-    for (int st = 0; st < nst; ++st) {
-        for (const Shape& sh : shapes) {
-            fft3d_plan_t p = b->plans[sh];
-            if (st >= stage_count(p, pop)) continue;
+    const std::vector<double> fcost = batch_costs(b->ffts);
+    std::vector<double> scost(shapes.size(), 0.0);
+    for (size_t f = 0; f < b->ffts.size(); ++f)
+        scost[std::find(shapes.begin(), shapes.end(), shape_of(b->ffts[f])) - shapes.begin()] += fcost[f];
+    const int ns = std::max(1, std::min<int>(b->nstreams, (int)shapes.size()));
+    const std::vector<std::vector<int>> placed = place_batch(scost, ns);
+    // launch groups of each shape's chain, in stage order
+    std::vector<std::vector<std::vector<KernelLaunch>>> groups(shapes.size());
+    std::vector<std::vector<char>> grouped(shapes.size());
+    size_t total = 0;
+    for (size_t k = 0; k < shapes.size(); ++k) {
+        fft3d_plan_t p = b->plans[shapes[k]];
+        for (int st = 0; st < stage_count(p, pop); ++st) {
             std::vector<KernelLaunch> v, one;
             for (int f : b->order) {
-                if (shape_of(b->ffts[f]) != sh) continue;
+                if (shape_of(b->ffts[f]) != shapes[k]) continue;
                 const fft3d_status r = record_stage(p, pop, st, in[f], out[f], &one);
                 if (r != FFT3D_OK) return r;
                 v.insert(v.end(), one.begin(), one.end());
             }
             if (can_group(v.data(), v.size())) {
-                groups.push_back(v);
-                grouped.push_back(1);
+                total += v.size();
+                groups[k].push_back(v);
+                grouped[k].push_back(1);
             } else {
                 for (const KernelLaunch& kl : v) {
-                    groups.push_back({kl});
-                    grouped.push_back(0);
+                    groups[k].push_back({kl});
+                    grouped[k].push_back(0);
                 }
             }
         }
     }
-    size_t total = 0;
-    for (size_t g = 0; g < groups.size(); ++g)
-        if (grouped[g]) total += groups[g].size();
     std::vector<TileEntry> host(total);
-    std::vector<size_t> at(groups.size(), 0);
+    std::vector<std::vector<size_t>> at(shapes.size());  // table offset of each launch of a chain
+    std::vector<std::vector<KernelLaunch>> launches(shapes.size());
     size_t pos = 0;
-    c->launches.clear();
-    for (size_t g = 0; g < groups.size(); ++g) {
-        if (!grouped[g]) {
-            c->launches.push_back(groups[g][0]);
-            continue;
+    for (size_t k = 0; k < shapes.size(); ++k)
+        for (size_t g = 0; g < groups[k].size(); ++g) {
+            at[k].push_back(pos);
+            if (!grouped[k][g]) {
+                launches[k].push_back(groups[k][g][0]);
+                continue;
+            }
+            KernelLaunch kl;
+            make_group(groups[k][g].data(), groups[k][g].size(), true, host.data() + pos, &kl);
+            pos += groups[k][g].size();
+            launches[k].push_back(kl);
         }
-        KernelLaunch kl;
-        make_group(groups[g].data(), groups[g].size(), true, host.data() + pos, &kl);
-        at[g] = pos;
-        pos += groups[g].size();
-        c->launches.push_back(kl);
-    }
     c->dev = nullptr;
     if (total > 0) {
         hipError_t e = hipMalloc(&c->dev, total * sizeof(TileEntry));
@@ -160,9 +181,43 @@ fft3d_status build_issue(fft3d_batch_t b, int op, const void* const* in, void* c
             return set_hip_error(e, "batch tile table upload");
         }
     }
-    for (size_t g = 0; g < groups.size(); ++g)
-        if (grouped[g]) c->launches[g].args.tiles = c->dev + at[g];
+    c->chains.assign(ns, {});
+    for (int q = 0; q < ns; ++q)
+        for (int k : placed[q])
+            for (size_t g = 0; g < launches[k].size(); ++g) {
+                KernelLaunch kl = launches[k][g];
+                if (grouped[k][g]) kl.args.tiles = c->dev + at[k][g];
+                c->chains[q].push_back(kl);
+            }
     return FFT3D_OK;
+}
+
+// The batch's streams and events, created on the first call that forks.
+hipError_t ensure_streams(fft3d_batch_t b, int ns)
+{
+    if ((int)b->streams.size() >= ns) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (!b->fork) {
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            b->fork = nullptr;
+            return e;
+        }
+    }
+    while ((int)b->streams.size() < ns) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            hipStreamDestroy(st);
+            return e;
+        }
+        b->streams.push_back(st);
+        b->joins.push_back(ev);
+    }
+    return hipSuccess;
 }
 
 fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* const* out, void* stream)
@@ -222,9 +277,30 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         b->cache.push_back(c);
         hit = &b->cache.back();
     }
-    for (const KernelLaunch& kl : hit->launches) {
-        e = launch_stage_kernel(kl.func, kl.grid, kl.block, kl.args, kl.lds, s);
-        if (e != hipSuccess) return set_hip_error(e, "batch kernel launch");
+    const int ns = (int)hit->chains.size();
+    if (ns == 1) {
+        for (const KernelLaunch& kl : hit->chains[0]) {
+            e = launch_stage_kernel(kl.func, kl.grid, kl.block, kl.args, kl.lds, s);
+            if (e != hipSuccess) return set_hip_error(e, "batch kernel launch");
+        }
+    } else {
+        // fork the chains from the caller's stream onto the batch's streams
+        // and join them back
+        e = ensure_streams(b, ns);
+        if (e != hipSuccess) return set_hip_error(e, "batch streams");
+        e = hipEventRecord(b->fork, s);
+        if (e != hipSuccess) return set_hip_error(e, "hipEventRecord(fork)");
+        for (int q = 0; q < ns; ++q) {
+            e = hipStreamWaitEvent(b->streams[q], b->fork, 0);
+            if (e != hipSuccess) return set_hip_error(e, "hipStreamWaitEvent(fork)");
+            for (const KernelLaunch& kl : hit->chains[q]) {
+                e = launch_stage_kernel(kl.func, kl.grid, kl.block, kl.args, kl.lds, b->streams[q]);
+                if (e != hipSuccess) return set_hip_error(e, "batch kernel launch");
+            }
+            e = hipEventRecord(b->joins[q], b->streams[q]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[q], 0);
+            if (e != hipSuccess) return set_hip_error(e, "batch join");
+        }
     }
     if (!b->done) {
         e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
@@ -319,6 +395,15 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
         return set_error(FFT3D_ERR_INVALID_ARG, "a batch stages in place or in fused x-y planes (no workspace)");
     drop_cache(b);  // the stage lists are baked into the cached launches
     return fft3d_set_staging(it->second, staging);
+}
+
+fft3d_status fft3d_batch_set_streams(fft3d_batch_t b, int nstreams)
+{
+    if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    if (nstreams < 1 || nstreams > 16) return set_error(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
+    drop_cache(b);  // the chains are placed per stream count
+    b->nstreams = nstreams;
+    return FFT3D_OK;
 }
 
 int fft3d_batch_get_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz)

@@ -263,6 +263,10 @@ class BatchPlan:
         nz, ny, nx = shape
         check(_lib.lib().fft3d_batch_set_staging(self._h, nx, ny, nz, int(staging)), "fft3d_batch_set_staging")
 
+    def set_streams(self, n: int):
+        """Streams the batch's shapes run on concurrently (1: all on the caller's stream)."""
+        check(_lib.lib().fft3d_batch_set_streams(self._h, int(n)), "fft3d_batch_set_streams")
+
     def staging(self, shape) -> int:
         """The staging of the transforms of one (nz, ny, nx) shape."""
         nz, ny, nx = shape

@@ -407,6 +407,13 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), user) == FFT3D_OK);
         EXPECT(fft3d_batch_set_staging(b, 3, 3, 3, FFT3D_STAGING_IN_PLACE) == FFT3D_ERR_INVALID_ARG);
         EXPECT(fft3d_batch_get_staging(b, 3, 3, 3) == -1);
+        for (int ns : {1, 2, 16}) {  // shapes on other stream counts
+            EXPECT(fft3d_batch_set_streams(b, ns) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_inverse_batch(b, out.data(), out.data(), nullptr) == FFT3D_OK);
+        }
+        EXPECT(fft3d_batch_set_streams(b, 0) == FFT3D_ERR_INVALID_ARG);
+        EXPECT(fft3d_batch_set_streams(b, 4) == FFT3D_OK);
         EXPECT(fft3d_batch_get_staging(nullptr, 3, 3, 3) == -1);
         // the caller captures the batch into its own graph (twice: replays of
         // the plans' direct issue)

@@ -165,6 +165,29 @@ def test_stage_configs_do_not_change_bits(gpu_lib, workload):
     bp.close()
 
 
+def test_batch_stream_counts_bitwise(gpu_lib, workload):
+    """Shapes on 1, 2, 4 or 8 of the batch's streams (forked from and joined
+    back to the caller's stream) give the same bits, forward and inverse."""
+    shapes, host, xs = workload
+    bp = gpu_lib.BatchPlan(shapes)
+    bp.set_streams(1)
+    ref = [o.clone() for o in bp.forward(xs)]
+    ref_i = [o.clone() for o in bp.inverse(ref)]
+    side = torch.cuda.Stream()
+    for ns in (2, 4, 8):
+        print(f"case batch on {ns} streams", flush=True)
+        bp.set_streams(ns)
+        with torch.cuda.stream(side):
+            outs = bp.forward(xs)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            back = bp.inverse(outs)
+        side.synchronize()
+        for i in range(len(xs)):
+            assert torch.equal(outs[i], ref[i]) and torch.equal(back[i], ref_i[i]), (ns, i)
+        del junk
+    bp.close()
+
+
 def test_batch_errors(gpu_lib):
     from paper_2601_12209_amd._lib import Fft3dError
 
