@@ -317,8 +317,10 @@ const char* fft3d_last_error(void);
  * cost, forked from and joined back to the caller's stream, so transforms of
  * different shapes overlap.  The tables of a pointer set are built on its
  * first call (a blocking upload) and cached (at most 8 sets).  A call into a
- * stream the caller is capturing issues the transforms one after another on
- * it instead. */
+ * stream the caller is capturing issues, in order on that stream, the grouped
+ * launches of a pointer set that an earlier call has built (their tables are
+ * then kept until the batch is destroyed, since the caller's graph refers to
+ * them), and otherwise the transforms one after another. */
 typedef struct fft3d_batch_s* fft3d_batch_t;
 
 /* dims holds count triples (nx, ny, nz), each a shape fft3d_plan accepts;

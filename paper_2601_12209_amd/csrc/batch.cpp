@@ -51,6 +51,7 @@ struct CachedIssue {
     std::vector<void*> out;
     std::vector<std::vector<KernelLaunch>> chains;
     TileEntry* dev = nullptr;
+    bool captured = false;  // issued into a caller's capture: its graph refers to dev
 };
 
 }  // namespace
@@ -62,6 +63,7 @@ struct fft3d_batch_s {
     std::map<Shape, fft3d_plan_t> plans;  // one single-stream plan per distinct shape
     std::vector<int> order;               // transforms in decreasing cost (issue order)
     std::vector<CachedIssue> cache;
+    std::vector<TileEntry*> retired;  // tables of captured issues, kept until the batch is destroyed
     int nstreams = kDefaultStreams;  // shapes run concurrently on this many streams
     std::vector<hipStream_t> streams;  // created on the first call that forks
     std::vector<hipEvent_t> joins;
@@ -81,17 +83,24 @@ void wait_done(fft3d_batch_s* b)
     if (b->done) hipEventSynchronize(b->done);
 }
 
+// Drop the cached launch tables (after the last call); tables that a
+// caller's captured graph may still use stay allocated until the batch is
+// destroyed.
 void drop_cache(fft3d_batch_s* b)
 {
     wait_done(b);
-    for (auto& c : b->cache)
-        if (c.dev) hipFree(c.dev);
+    for (auto& c : b->cache) {
+        if (!c.dev) continue;
+        if (c.captured) b->retired.push_back(c.dev);
+        else hipFree(c.dev);
+    }
     b->cache.clear();
 }
 
 void release(fft3d_batch_s* b)
 {
     drop_cache(b);
+    for (TileEntry* t : b->retired) hipFree(t);
     for (hipStream_t st : b->streams)
         if (st) hipStreamDestroy(st);
     for (hipEvent_t ev : b->joins)
@@ -245,17 +254,6 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
         e = hipStreamIsCapturing(s, &cap);
         if (e != hipSuccess) return set_hip_error(e, "hipStreamIsCapturing");
     }
-    if (cap != hipStreamCaptureStatusNone) {
-        // a stream the caller is capturing: every transform in order on it
-        // (each plan issues its stages in order on a capturing stream; no
-        // launch of the capture refers to a table of this batch)
-        for (int f : b->order) {
-            fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
-            fft3d_status st = op == 0 ? fft3d_forward(p, in[f], out[f], s) : fft3d_inverse(p, in[f], out[f], s);
-            if (st != FFT3D_OK) return st;
-        }
-        return FFT3D_OK;
-    }
     CachedIssue* hit = nullptr;
     for (auto& c : b->cache) {
         if (c.op != op) continue;
@@ -265,6 +263,30 @@ fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* con
             hit = &c;
             break;
         }
+    }
+    if (cap != hipStreamCaptureStatusNone) {
+        // a stream the caller is capturing.  With launch tables already built
+        // for this pointer set (an earlier call), their grouped launches go in
+        // order onto the capturing stream, and the tables are kept until the
+        // batch is destroyed (the caller's graph refers to them).  Otherwise
+        // (building tables would allocate and copy during the capture) every
+        // transform goes in order onto it, each plan issuing its stages in
+        // order.
+        if (hit) {
+            hit->captured = true;
+            for (const auto& chain : hit->chains)
+                for (const KernelLaunch& kl : chain) {
+                    e = launch_stage_kernel(kl.func, kl.grid, kl.block, kl.args, kl.lds, s);
+                    if (e != hipSuccess) return set_hip_error(e, "batch kernel launch");
+                }
+            return FFT3D_OK;
+        }
+        for (int f : b->order) {
+            fft3d_plan_t p = b->plans[shape_of(b->ffts[f])];
+            fft3d_status st = op == 0 ? fft3d_forward(p, in[f], out[f], s) : fft3d_inverse(p, in[f], out[f], s);
+            if (st != FFT3D_OK) return st;
+        }
+        return FFT3D_OK;
     }
     if (!hit) {
         if (b->cache.size() >= kMaxCached) drop_cache(b);

@@ -415,15 +415,27 @@ void batch_cases(const std::vector<int64_t>& dims, hipStream_t user)
         EXPECT(fft3d_batch_set_streams(b, 0) == FFT3D_ERR_INVALID_ARG);
         EXPECT(fft3d_batch_set_streams(b, 4) == FFT3D_OK);
         EXPECT(fft3d_batch_get_staging(nullptr, 3, 3, 3) == -1);
-        // the caller captures the batch into its own graph (twice: replays of
-        // the plans' direct issue)
-        for (int rep = 0; rep < 2; ++rep) {
+        // the caller captures the batch into its own graph: twice with a
+        // pointer set an earlier call built tables for (grouped launches),
+        // then with a fresh set (each plan's direct issue); then a setter
+        // retires the captured tables
+        for (int rep = 0; rep < 3; ++rep) {
+            std::vector<Buf*> fresh;
+            std::vector<void*> o2(out.begin(), out.end());
+            if (rep == 2)
+                for (int f = 0; f < n; ++f) {
+                    fresh.push_back(new Buf(bufs2[f]->bytes));
+                    o2[f] = fresh.back()->p;
+                }
             EXPECT(hipStreamBeginCapture(user, hipStreamCaptureModeThreadLocal) == hipSuccess);
-            EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
+            EXPECT(fft3d_forward_batch(b, in.data(), o2.data(), user) == FFT3D_OK);
             hipGraph_t g = nullptr;
             EXPECT(hipStreamEndCapture(user, &g) == hipSuccess);
             if (g) (void)hipGraphDestroy(g);
+            for (Buf* x : fresh) delete x;
         }
+        EXPECT(fft3d_batch_set_streams(b, 2) == FFT3D_OK);
+        EXPECT(fft3d_forward_batch(b, in.data(), out.data(), user) == FFT3D_OK);
         // a partial overlap of one transform's input and output
         if (bufs[0]->bytes >= 2 * es_of(dtype)) {
             std::vector<void*> shifted(out.begin(), out.end());

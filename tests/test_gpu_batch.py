@@ -106,6 +106,36 @@ def test_caller_captures_batch(gpu_lib, workload):
     bp.close()
 
 
+def test_caller_captures_grouped_batch(gpu_lib, workload):
+    """A pointer set the batch has run once is captured as its grouped launches
+    (about ten kernel nodes); replays with eager work between them, and after a
+    setter dropped the batch's cache, equal the eager result bit for bit."""
+    shapes, host, xs = workload
+    bp = gpu_lib.BatchPlan(shapes)
+    outs = [torch.empty_like(x) for x in xs]
+    bp.forward(xs, outs)  # builds the launch tables of this pointer set
+    ref = [o.clone() for o in outs]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bp.forward(xs, outs)
+    for rep in range(3):
+        print(f"case grouped capture replay {rep}", flush=True)
+        for o in outs:
+            o.zero_()
+        y = bp.inverse(ref)  # eager work of the same batch between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for r, o in zip(ref, outs):
+            assert torch.equal(r, o), rep
+        if rep == 1:
+            bp.set_streams(2)  # drops the cache; the captured tables stay alive
+        del y
+    del g
+    bp.close()
+
+
 def test_complex128_batch(gpu_lib):
     shapes = [(12, 20, 16), (8, 8, 8), (30, 6, 10), (16, 48, 5)]
     host = synth.batch_inputs(shapes, 17)
