@@ -1,4 +1,4 @@
-// Device-side building blocks: complex arithmetic, radix-2/3/4/5/8/16
+// Device-side building blocks: complex arithmetic, radix-2/3/4/5/7/8/15/16
 // butterflies and the Stockham pass driver used by every stage kernel.
 //
 // A length-N line is transformed by the passes of radix_plan(N).  Pass p
@@ -195,6 +195,32 @@ template <typename T> FD void dft16(cpx<T>* x)
     }
 }
 
+// radix 15 by the prime-factor map (3 and 5 are coprime): with the inputs
+// indexed n = (5 n1 + 3 n2) mod 15 and the outputs k = (10 k1 + 6 k2) mod 15,
+// W15^(nk) = W3^(n1 k1) W5^(n2 k2), so the DFT is five DFT3s over n1 followed
+// by three DFT5s over n2, with no twiddles in between.
+template <typename T> FD void dft15(cpx<T>* x)
+{
+    cpx<T> a[5][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 5; ++n2)
+#pragma unroll
+        for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = x[(5 * n1 + 3 * n2) % 15];
+#pragma unroll
+    for (int n2 = 0; n2 < 5; ++n2) dft3(a[n2]);
+    cpx<T> b[3][5];
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+        for (int n2 = 0; n2 < 5; ++n2) b[k1][n2] = a[n2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) dft5(b[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 5; ++k2) x[(10 * k1 + 6 * k2) % 15] = b[k1][k2];
+}
+
 template <int R, typename T> FD void dft_radix(cpx<T>* v)
 {
     if constexpr (R == 2) dft2(v);
@@ -203,6 +229,7 @@ template <int R, typename T> FD void dft_radix(cpx<T>* v)
     else if constexpr (R == 5) dft5(v);
     else if constexpr (R == 7) dft7(v);
     else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 15) dft15(v);
     else if constexpr (R == 16) dft16(v);
     else static_assert(R == 2, "unsupported radix");
 }

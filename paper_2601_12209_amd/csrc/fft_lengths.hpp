@@ -66,8 +66,18 @@ constexpr RadixPlan radix_plan(int n)
     case 12: p.r[p.np++] = 16; p.r[p.np++] = 16; p.r[p.np++] = 16; break;
     default: break;
     }
-    for (int i = 0; i < b; ++i) p.r[p.np++] = 3;
-    for (int i = 0; i < c; ++i) p.r[p.np++] = 5;
+    // a factor 3 and a factor 5 together as one radix-15 pass (the
+    // prime-factor butterfly) where no radix-16 pass sets the threads per
+    // line: one pass fewer, and the larger largest radix means fewer threads
+    // per line (840: 56 instead of 105, so strided tiles hold 16 lines
+    // instead of 8).  With a radix-16 pass the threads per line stay n/16 and
+    // a radix-15 pass would give each thread two butterflies (more registers).
+    bool has16 = false;
+    for (int i = 0; i < p.np; ++i) has16 = has16 || p.r[i] == 16;
+    const int p15 = has16 ? 0 : (b < c ? b : c);
+    for (int i = 0; i < p15; ++i) p.r[p.np++] = 15;
+    for (int i = p15; i < b; ++i) p.r[p.np++] = 3;
+    for (int i = p15; i < c; ++i) p.r[p.np++] = 5;
     for (int i = 0; i < d; ++i) p.r[p.np++] = 7;
     int rmax = 1;
     for (int i = 0; i < p.np; ++i) rmax = p.r[i] > rmax ? p.r[i] : rmax;

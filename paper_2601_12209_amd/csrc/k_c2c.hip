@@ -118,13 +118,15 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
                                arg, lds, s);
 }
 
-// Lengths that also get the TDIV = 2, 4 and SPLIT variants.  (A TDIV 3
-// variant for 840's odd 105 threads per line spilled and ran slower than
-// 8-line tiles at 840^3, as did the split exchange there.)
+// Lengths that also get the TDIV = 2, 4 and SPLIT variants: the powers of
+// two, and 840 (the paper's largest GPU grid), whose radix-15 plan has 56
+// threads per line.  (With the earlier 105 threads per line a TDIV 3 variant
+// for 840 spilled and ran slower than 8-line tiles, as did the split
+// exchange.)
 template <int N>
 constexpr bool has_variants()
 {
-    return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096;
+    return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096 || N == 840;
 }
 
 template <typename T, int N>
@@ -167,7 +169,7 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
 
 bool c2c_variant_available(int n, int tdiv, int split)
 {
-    const bool var = n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096;
+    const bool var = n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 840;
     if (tdiv == 1 && !split) return length_supported(n);
     if (!var) return false;
     const int tpl = radix_plan(n).tpl;

@@ -248,8 +248,14 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
     const int tpl = radix_plan(nk).tpl;
     KConf c;
     const bool c2c = st.kind == K_C2C;
+    const bool pow2_tpl = (tpl & (tpl - 1)) == 0;
     if (st.axis != 0) {
-        int lw = 16;
+        // threads per line that are not a power of two leave the lines'
+        // wavefronts partly idle; there 8-line tiles (more workgroups per CU)
+        // measured fastest on MI355X: complex64 840^3 y/z 2.51-2.57 ms against
+        // 2.97-3.15 for 16 lines, 720^3 1.63-1.66 against 1.95, complex128
+        // 840^3 3.76-3.79 against 4.63-4.68
+        int lw = pow2_tpl ? 16 : 8;
         while (lw * tpl < 256 && lw < 64) lw *= 2;
         const int64_t a = b.hi[0] - b.lo[0];
         lw = (int)std::min<int64_t>(lw, next_pow2(a));
@@ -289,13 +295,15 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
     } else {
         int lw = 1;
         while (2 * lw * tpl <= 128) lw *= 2;
-        // lengths with factors 3, 5, 7 have thread counts per line (105 for
-        // 840, 45 for 720, 60 for 480) that leave 128-thread workgroups with
-        // partial wavefronts and too many workgroups: take >= 256 threads
-        // (measured x stage, complex64: 840^3 2.92 -> 2.09 ms, 720^3 1.64 ->
-        // 1.46-1.49, 480^3 0.38 -> 0.33-0.34)
-        if ((nk & (nk - 1)) != 0)
-            while (lw * tpl < 256) lw *= 2;
+        // thread counts per line that are not a power of two leave the lines'
+        // wavefronts partly idle, so take more lines: below 32 threads per
+        // line >= 256 threads (the rule for all such lengths before the
+        // radix-15 pass: 480^3 complex64 with 60 threads per line went from
+        // 0.38 ms on 2 lines to 0.33 on 8), from 32 up >= 128 (840^3 with 56
+        // threads per line: 1.85 ms on 4 lines against 1.98 on 8; 720^3, 45
+        // per line: 1.43 against 1.48; MI355X)
+        if (!pow2_tpl)
+            while (lw * tpl < (tpl >= 32 ? 128 : 256)) lw *= 2;
         // the complex64 real kernels at half length 256 (512^3) run fastest with
         // more lines per workgroup on MI355X: R2C split 16 lines (512
         // threads), 237 -> 195 us; C2R merge 8 lines, 241 -> 233 us (the

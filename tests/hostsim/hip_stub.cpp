@@ -455,7 +455,10 @@ namespace {
 
 constexpr int kMaxThreads = 1024;
 
-bool has_variants(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096; }
+bool has_variants(int n)
+{
+    return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 840;
+}
 
 size_t table_entries(int n) { return (size_t)pass_table_size(radix_plan(n)); }
 

@@ -55,8 +55,11 @@ def test_supported_lengths_and_radix_plans(fft3d):
     for n in SUPPORTED:
         radices, tpl = fft3d.query_radix_plan(n)
         assert int(np.prod(radices)) == n
-        assert set(radices) <= {2, 3, 4, 5, 7, 8, 16}
+        assert set(radices) <= {2, 3, 4, 5, 7, 8, 15, 16}
+        if n % 15 == 0:  # a factor 3 and a factor 5 form one radix-15 pass unless a radix 16 sets the threads
+            assert (15 in radices) != (16 in radices), (n, radices)
         assert tpl == (n // max(radices) if radices else 1)
+    assert fft3d.query_radix_plan(840) == ([8, 15, 7], 56)
 
 
 @pytest.mark.parametrize("n", [2, 3, 5, 7, 8, 12, 100, 120, 512, 840, 1000, 1024, 4096])
