@@ -134,7 +134,7 @@ def _progress(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-EXTRAS = ("r2c512", "grid256", "r2c1024", "c840", "batch", "poisson")
+EXTRAS = ("r2c512", "grid256", "r2c1024", "c840", "batch", "poisson", "ppb")
 
 
 def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
@@ -344,6 +344,30 @@ def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
         checks.append(("poisson_256cubed_solution", phi.cpu().numpy(), lambda: _oracle().poisson(f.astype(np.float64))))
         checks.append(("poisson_256cubed_gradient", g.cpu().numpy(), lambda: _oracle().poisson_grad(w.astype(np.float64))))
         p.close()
+    if want("ppb"):
+        # (Periodic, Periodic, Bounded) topology, 256^3 float32: Poisson solve
+        # and forward + inverse with a DCT (Neumann) or DST (Dirichlet) z axis
+        c5 = synth.CFG5
+        f = synth.smooth_field(c5["shape"], c5["seed_f"], c5["sigma"], np.float32)
+        fd = torch.from_numpy(f).cuda()
+        m = int(np.prod(c5["shape"]))
+        mh = (c5["shape"][2] // 2 + 1) * c5["shape"][0] * c5["shape"][1]
+        for wall, bc in (("neumann", 0), ("dirichlet", 1)):
+            _progress(f"extras: 256^3 (P,P,B) {wall}")
+            p = fft3d.Plan(c5["shape"], torch.float32, z_bc=wall)
+            phi = p.poisson(fd)
+            H = p.forward(fd)
+            y = torch.empty_like(fd)
+            ms_s = _time(lambda: p.poisson(fd, out=phi), reps, torch)
+            ms_t = _time(lambda: (p.forward(fd, out=H), p.inverse(H, out=y)), reps, torch)
+            sbytes = 2 * m * 4 + 8 * mh * 8  # real in/out + x, y, fused z, y, x half-spectrum passes
+            tbytes = 2 * m * 4 + 10 * mh * 8  # real side once each way + 5 half-spectrum transfers each way
+            rep[f"ppb_256cubed_f32_{wall}"] = {
+                "poisson_ms": round(ms_s, 4), "poisson_hbm_frac": round(sbytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "fwd_inv_ms": round(ms_t, 4), "fwd_inv_hbm_frac": round(tbytes / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            checks.append((f"ppb_256cubed_{wall}_solution", phi.cpu().numpy(),
+                           lambda bc=bc: _oracle().poisson_ppb(f.astype(np.float64), bc)))
+            p.close()
     return rep, checks
 
 
