@@ -267,9 +267,7 @@ def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
             except RuntimeError:
                 pass
         probe.close()
-        bbytes = sum((2 if sh in fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
-        brep = {"transforms": len(shapes), "points": pts, "fused_xy_shapes": sorted(fused),
-                "hbm_bytes_per_call": bbytes}
+        brep = {"transforms": len(shapes), "points": pts}
         side = torch.cuda.Stream()
         # launch shapes per transform shape from the autotuner (untimed; measured
         # once, then taken from its cache file, a temporary one here)
@@ -279,16 +277,22 @@ def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
         own_cache = "FFT3D_TUNE_CACHE" not in os.environ
         if own_cache:
             os.environ["FFT3D_TUNE_CACHE"] = tune_path
-        brep["launch_shapes"] = "autotuned"
+        brep["launch_shapes"] = "autotuned (launch shapes per stage, staging per shape)"
         bp = fft3d.BatchPlan(shapes)
         autotune.tune_batch(bp, reps=5)
+        # bytes of the passes made: two for shapes in fused x-y planes, three otherwise
+        tuned_fused = sorted(sh for sh in set(shapes) if bp.staging(sh) == fft3d.STAGING_FUSED_XY)
+        bbytes = sum((2 if sh in tuned_fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
+        brep["fused_xy_shapes"] = tuned_fused
+        brep["hbm_bytes_per_call"] = bbytes
         with torch.cuda.stream(side):
             ms = _time(lambda: bp.forward(xs, outs), reps, torch)
         brep["grouped"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
                               "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bp.close()
         # for comparison: the same transforms one after another, each through its own
-        # plan (same staging per shape, default launch shapes) on one stream
+        # plan (the batch's default staging per shape, default launch shapes) on one
+        # stream
         plans = {}
         for sh in set(shapes):
             pl = fft3d.Plan(sh, torch.complex64)
@@ -304,8 +308,9 @@ def _extras(reps, torch, fft3d, synth, np, only=EXTRAS):
 
         with torch.cuda.stream(side):
             ms = _time(serial, reps, torch)
+        sbytes = sum((2 if sh in fused else 3) * 2 * 8 * int(np.prod(sh)) for sh in shapes)
         brep["serial_one_stream"] = {"ms": round(ms, 4), "GFLOP/s": round(flops / (ms * 1e-3) / 1e9, 1),
-                                     "hbm_frac": round(bbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                                     "hbm_frac": round(sbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         for pl in plans.values():
             pl.close()
         bp = fft3d.BatchPlan(shapes)

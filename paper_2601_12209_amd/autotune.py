@@ -3,7 +3,9 @@
 For every axis of a plan it times the candidate shapes (lines per workgroup,
 threads-per-line divisor, split exchange, padding) that the library accepts
 for that stage, using the per-stage timing events, and keeps the fastest; a
-batch is tuned shape by shape the same way.  The shapes only change how work
+batch is tuned shape by shape the same way, and for shapes that fit the
+fused x-y kernel the staging (fused planes or three line stages) is picked
+by timing the whole batch.  The shapes only change how work
 is mapped onto threads, never the arithmetic, so results are bitwise
 identical whatever is chosen.
 
@@ -140,15 +142,79 @@ def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: 
     return chosen
 
 
+def _time_batch(bp, xs, outs, reps):
+    bp.forward(xs, outs)  # builds the launch tables of this pointer set
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        start.record()
+        bp.forward(xs, outs)
+        end.record()
+        end.synchronize()
+        ts.append(start.elapsed_time(end))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def tune_batch(bp: fft3d.BatchPlan, reps: int = 5, use_cache: bool = True, verbose: bool = False):
-    """Tune the stage launch shapes of every distinct shape of the batch (on a
-    stand-alone plan of that shape) and apply them to the batch."""
-    chosen = {}
-    for shape in sorted(set(bp.shapes)):
-        p = fft3d.Plan(shape, fft3d._COMPLEX[bp.code])
-        got = tune_plan(p, reps=reps, use_cache=use_cache, verbose=verbose)
-        p.close()
-        for axis, cfg in got.items():
-            bp.set_stage_config(shape, axis, *cfg)
-        chosen[shape] = got
-    return chosen
+    """Tune every distinct shape of the batch and apply the result: the stage
+    launch shapes on a stand-alone plan of that shape, for each staging the
+    shape can take, and then, for shapes that fit the fused x-y kernel, the
+    staging itself (fused planes or three line stages) by timing the whole
+    batch, largest shapes first (the shapes share the GPU, so the better
+    staging depends on the rest of the batch).  Returns {shape: (staging,
+    {axis: shape})}."""
+    dt = fft3d._COMPLEX[bp.code]
+    shapes = sorted(set(bp.shapes))
+    counts = {sh: bp.shapes.count(sh) for sh in shapes}
+    fusable = [sh for sh in shapes if bp.staging(sh) == fft3d.STAGING_FUSED_XY]
+    tuned = {}
+    for sh in shapes:
+        for st in ((fft3d.STAGING_FUSED_XY, fft3d.STAGING_IN_PLACE) if sh in fusable else (fft3d.STAGING_IN_PLACE,)):
+            p = fft3d.Plan(sh, dt, staging=st)
+            tuned[(sh, st)] = tune_plan(p, reps=reps, use_cache=use_cache, verbose=verbose)
+            p.close()
+
+    def apply(sh, st):
+        bp.set_staging(sh, st)
+        for axis in range(3):
+            bp.set_stage_config(sh, axis, 0)
+        for axis, cfg in tuned[(sh, st)].items():
+            bp.set_stage_config(sh, axis, *cfg)
+
+    choice = {sh: (fft3d.STAGING_FUSED_XY if sh in fusable else fft3d.STAGING_IN_PLACE) for sh in shapes}
+    for sh in shapes:
+        apply(sh, choice[sh])
+    if fusable:
+        with _lock:
+            cache = _load() if use_cache else {}
+        comp = ",".join(f"{a}x{b}x{c}:{counts[(a, b, c)]}" for (a, b, c) in shapes)
+        key = f"{_arch()}|{'c64' if bp.code == fft3d.C64 else 'c128'}|batch-staging|{comp}"
+        if key in cache:
+            picked = {tuple(json.loads(k)): v for k, v in cache[key].items()}
+        else:
+            xs = [torch.randn(sh, dtype=dt, device="cuda") for sh in bp.shapes]
+            outs = [torch.empty_like(t) for t in xs]
+            picked = {}
+            for sh in sorted(fusable, key=lambda v: -counts[v] * v[0] * v[1] * v[2]):
+                best = None
+                for st in (fft3d.STAGING_FUSED_XY, fft3d.STAGING_IN_PLACE):
+                    apply(sh, st)
+                    t = _time_batch(bp, xs, outs, reps)
+                    if verbose:
+                        print(f"batch staging {sh} {st}: {t:.4f} ms")
+                    if best is None or t < best[0]:
+                        best = (t, st)
+                picked[sh] = best[1]
+                apply(sh, best[1])
+            del xs, outs
+            cache[key] = {json.dumps(list(k)): v for k, v in picked.items()}
+            if use_cache:
+                with _lock:
+                    merged = _load()
+                    merged.update(cache)
+                    _save(merged)
+        for sh, st in picked.items():
+            choice[sh] = st
+            apply(sh, st)
+    return {sh: (choice[sh], tuned[(sh, choice[sh])]) for sh in shapes}
