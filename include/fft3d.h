@@ -290,6 +290,23 @@ int fft3d_get_issue(fft3d_plan_t plan);
 fft3d_status fft3d_set_stage_config(fft3d_plan_t plan, int axis, int lw, int tdiv, int split, int pad);
 
 /*
+ * Radix order of the complex line kernels along one axis (0 = x, 1 = y,
+ * 2 = z): 0 the default plan of the length (fft3d_query_radix_plan), 1 the
+ * same radices in the reverse pass order.  The reverse-order kernels take
+ * one thread per butterfly, the plain exchange and plain accesses, so on an
+ * axis in order 1 the launch shape drops its threads-per-line divisor and
+ * split exchange (and halves its lines until the threads fit).  The
+ * autotuner's third dimension besides the launch shape and the staging.
+ * Unlike the launch shape, the order changes the arithmetic: results agree
+ * with order 0 to rounding, not bitwise.  FFT3D_ERR_INVALID_ARG for order
+ * 1 when no C2C line kernel of that axis has a distinct reverse order (a
+ * single pass, a palindrome of radices, or real-to-complex x kernels).
+ * fft3d_get_radix_order returns the axis's order, or -1.
+ */
+fft3d_status fft3d_set_radix_order(fft3d_plan_t plan, int axis, int order);
+int fft3d_get_radix_order(fft3d_plan_t plan, int axis);
+
+/*
  * Per-stage timing (tracing).  While enabled, every call on the plan records
  * a timing event on the caller's stream before its first stage and after each
  * stage; the tiles of a stage are forked from and joined back onto the
@@ -339,6 +356,12 @@ fft3d_status fft3d_inverse_batch(fft3d_batch_t plan, const void* const* in, void
  * launch tables.  Used by the autotuner; results do not depend on it. */
 fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
                                           int lw, int tdiv, int split, int pad);
+
+/* Radix order of one axis of the transforms of one shape (arguments as
+ * fft3d_set_radix_order); waits for the last call and drops the cached
+ * launch tables. */
+fft3d_status fft3d_batch_set_radix_order(fft3d_batch_t plan, int64_t nx, int64_t ny, int64_t nz, int axis,
+                                         int order);
 
 /* Staging of the transforms of one shape: FFT3D_STAGING_IN_PLACE or
  * FFT3D_STAGING_FUSED_XY (the default where a fused kernel fits the plane;

@@ -41,6 +41,9 @@ _SIGS = {
     "fft3d_batch_set_stage_config": (I32, [P, I64, I64, I64, I32, I32, I32, I32, I32]),
     "fft3d_batch_set_staging": (I32, [P, I64, I64, I64, I32]),
     "fft3d_batch_get_staging": (I32, [P, I64, I64, I64]),
+    "fft3d_batch_set_radix_order": (I32, [P, I64, I64, I64, I32, I32]),
+    "fft3d_set_radix_order": (I32, [P, I32, I32]),
+    "fft3d_get_radix_order": (I32, [P, I32]),
     "fft3d_batch_set_streams": (I32, [P, I32]),
     "fft3d_batch_destroy": (I32, [P]),
     "fft3d_query_batch_placement": (I64, [I32, ctypes.POINTER(I64), I32, ctypes.POINTER(I64), I64]),

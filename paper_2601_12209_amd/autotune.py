@@ -7,7 +7,9 @@ batch is tuned shape by shape the same way, and for shapes that fit the
 fused x-y kernel the staging (fused planes or three line stages) is picked
 by timing the whole batch.  The shapes only change how work
 is mapped onto threads, never the arithmetic, so results are bitwise
-identical whatever is chosen.
+identical whatever shape is chosen; for the complex line kernels it also
+tries the reverse radix order (fft3d_set_radix_order), which changes the
+rounding of the results but not their accuracy class.
 
 Choices are cached in a JSON file (``FFT3D_TUNE_CACHE``, default
 ``~/.cache/fft3d_tune.json``) keyed by GPU architecture, precision, length,
@@ -88,8 +90,18 @@ def _time_stage(plan, x, out, index, reps):
     return ts[len(ts) // 2]
 
 
+def _apply(plan, axis, shape):
+    """Set a tuned (lw, tdiv, split, pad[, radix order]) on one axis of a plan or batch shape."""
+    plan.set_stage_config(axis, *shape[:4])
+    if len(shape) > 4:
+        plan.set_radix_order(axis, shape[4])
+
+
 def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: bool = False):
-    """Pick the fastest launch shape of every forward stage of `plan`; returns {axis: shape}."""
+    """Pick the fastest launch shape, and radix order of the line kernels, of
+    every forward stage of `plan`; returns {axis: (lw, tdiv, split, pad,
+    order)}.  The launch shape never changes the results; the reverse radix
+    order changes their rounding."""
     with _lock:
         cache = _load() if use_cache else {}
     chosen = {}
@@ -109,29 +121,39 @@ def tune_plan(plan: fft3d.Plan, reps: int = 5, use_cache: bool = True, verbose: 
         if key in cache:
             shape = tuple(cache[key])
             try:
-                plan.set_stage_config(axis, *shape)
+                _apply(plan, axis, shape)
                 chosen[axis] = shape
                 continue
             except RuntimeError:
-                pass
-        best = None
+                plan.set_stage_config(axis, 0)
+                plan.set_radix_order(axis, 0)
         plan.set_stage_config(axis, 0)
+        plan.set_radix_order(axis, 0)
         t0 = _time_stage(plan, x, out, index, reps)
         best = (t0, None)
+        # the reverse radix order runs with one thread per butterfly and the
+        # plain exchange; the real x kernels have no such choice
+        line_kernels = not (plan.r2c and axis == 0)
         for cand in stage_candidates(axis):
             try:
                 plan.set_stage_config(axis, *cand)
             except RuntimeError:
                 continue
-            t = _time_stage(plan, x, out, index, reps)
-            if verbose:
-                print(f"axis {axis} {cand}: {t:.4f} ms")
-            if t < best[0]:
-                best = (t, cand)
+            for order in ((0, 1) if line_kernels and cand[1] == 1 and cand[2] == 0 else (0,)):
+                try:
+                    plan.set_radix_order(axis, order)
+                except RuntimeError:
+                    break
+                t = _time_stage(plan, x, out, index, reps)
+                if verbose:
+                    print(f"axis {axis} {cand} order {order}: {t:.4f} ms")
+                if t < best[0]:
+                    best = (t, tuple(cand) + (order,))
+            plan.set_radix_order(axis, 0)
         if best[1] is None:
             plan.set_stage_config(axis, 0)
         else:
-            plan.set_stage_config(axis, *best[1])
+            _apply(plan, axis, best[1])
             chosen[axis] = best[1]
             cache[key] = list(best[1])
     if use_cache:
@@ -175,12 +197,23 @@ def tune_batch(bp: fft3d.BatchPlan, reps: int = 5, use_cache: bool = True, verbo
             tuned[(sh, st)] = tune_plan(p, reps=reps, use_cache=use_cache, verbose=verbose)
             p.close()
 
+    class _Shape:  # one shape of the batch, with a plan's setter names
+        def __init__(self, sh):
+            self.sh = sh
+
+        def set_stage_config(self, axis, *cfg):
+            bp.set_stage_config(self.sh, axis, *cfg)
+
+        def set_radix_order(self, axis, order):
+            bp.set_radix_order(self.sh, axis, order)
+
     def apply(sh, st):
         bp.set_staging(sh, st)
         for axis in range(3):
             bp.set_stage_config(sh, axis, 0)
+            bp.set_radix_order(sh, axis, 0)
         for axis, cfg in tuned[(sh, st)].items():
-            bp.set_stage_config(sh, axis, *cfg)
+            _apply(_Shape(sh), axis, cfg)
 
     choice = {sh: (fft3d.STAGING_FUSED_XY if sh in fusable else fft3d.STAGING_IN_PLACE) for sh in shapes}
     for sh in shapes:

@@ -408,6 +408,15 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
     return fft3d_set_stage_config(it->second, axis, lw, tdiv, split, pad);
 }
 
+fft3d_status fft3d_batch_set_radix_order(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int axis, int order)
+{
+    if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    auto it = b->plans.find(Shape(nx, ny, nz));
+    if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
+    drop_cache(b);  // the radix order is baked into the cached launches
+    return fft3d_set_radix_order(it->second, axis, order);
+}
+
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int staging)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");

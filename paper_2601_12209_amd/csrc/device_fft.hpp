@@ -244,9 +244,9 @@ template <int R, typename T> FD void dft_radix(cpx<T>* v)
 // values, or (SPLIT) real parts first and imaginary parts second through a
 // real-valued buffer of half the size.
 
-template <int N, int TPL_, int P>
+template <int N, int TPL_, int P, int ORD = 0>
 struct PassInfo {
-    static constexpr RadixPlan PL = radix_plan(N);
+    static constexpr RadixPlan PL = radix_plan(N, ORD);
     static constexpr int R = PL.r[P];
     static constexpr int BF = N / R;             // butterflies in this pass
     static constexpr int NS = radix_ns(PL, P);   // sub-transform length before it
@@ -257,10 +257,10 @@ struct PassInfo {
     static constexpr bool LAST = (P + 1 == PL.np);
 };
 
-template <int N, int TPL>
+template <int N, int TPL, int ORD = 0>
 constexpr int driver_ept()
 {
-    constexpr RadixPlan PL = radix_plan(N);
+    constexpr RadixPlan PL = radix_plan(N, ORD);
     int e = 1;
     for (int i = 0; i < PL.np; ++i) {
         const int bf = N / PL.r[i];
@@ -282,10 +282,10 @@ struct LdsView {
 };
 
 // Pass-0 inputs through the loader.
-template <typename T, int N, int TPL, class Load>
+template <typename T, int N, int TPL, int ORD, class Load>
 FD void load_first(cpx<T>* v, int tj, Load& load)
 {
-    using PI = PassInfo<N, TPL, 0>;
+    using PI = PassInfo<N, TPL, 0, ORD>;
 #pragma unroll
     for (int i = 0; i < PI::NB; ++i) {
         const int j = tj + i * TPL;
@@ -299,10 +299,10 @@ FD void load_first(cpx<T>* v, int tj, Load& load)
 // Twiddles and the radix-R DFTs of pass P, in registers.  twl is the
 // per-pass twiddle table staged in LDS (layout in fft_lengths.hpp): the roots
 // of butterfly k are R contiguous entries, so they load as wide LDS reads.
-template <typename T, int N, int TPL, int P>
+template <typename T, int N, int TPL, int P, int ORD>
 FD void compute_pass(cpx<T>* v, int tj, const cpx<T>* twl)
 {
-    using PI = PassInfo<N, TPL, P>;
+    using PI = PassInfo<N, TPL, P, ORD>;
     constexpr int R = PI::R;
 #pragma unroll
     for (int i = 0; i < PI::NB; ++i) {
@@ -320,17 +320,17 @@ FD void compute_pass(cpx<T>* v, int tj, const cpx<T>* twl)
 
 // Copy the per-pass twiddle table of the length-N kernel from global memory
 // into LDS (all threads of the workgroup; visible after the next barrier).
-template <typename T, int N>
+template <typename T, int N, int ORD = 0>
 FD void stage_pass_twiddles(cpx<T>* twl, const cpx<T>* __restrict__ twp, int t, int nthreads)
 {
-    constexpr int S = pass_table_size(radix_plan(N));
+    constexpr int S = pass_table_size(radix_plan(N, ORD));
     for (int i = t; i < S; i += nthreads) twl[i] = twp[i];
 }
 
-template <typename T, int N>
+template <typename T, int N, int ORD = 0>
 constexpr size_t pass_table_bytes()
 {
-    return (size_t)pass_table_size(radix_plan(N)) * sizeof(cpx<T>);
+    return (size_t)pass_table_size(radix_plan(N, ORD)) * sizeof(cpx<T>);
 }
 
 // Bytes of a kernel's LDS data region rounded up so the twiddle table that
@@ -338,10 +338,10 @@ constexpr size_t pass_table_bytes()
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // Visit every output of pass P: f(register index, output element).
-template <int N, int TPL, int P, class F>
+template <int N, int TPL, int P, int ORD, class F>
 FD void for_outputs(int tj, F&& f)
 {
-    using PI = PassInfo<N, TPL, P>;
+    using PI = PassInfo<N, TPL, P, ORD>;
 #pragma unroll
     for (int i = 0; i < PI::NB; ++i) {
         const int j = tj + i * TPL;
@@ -355,10 +355,10 @@ FD void for_outputs(int tj, F&& f)
 }
 
 // Visit every input of pass P: f(register index, input element).
-template <int N, int TPL, int P, class F>
+template <int N, int TPL, int P, int ORD, class F>
 FD void for_inputs(int tj, F&& f)
 {
-    using PI = PassInfo<N, TPL, P>;
+    using PI = PassInfo<N, TPL, P, ORD>;
 #pragma unroll
     for (int i = 0; i < PI::NB; ++i) {
         const int j = tj + i * TPL;
@@ -371,37 +371,37 @@ FD void for_inputs(int tj, F&& f)
 
 // Outputs of pass P -> LDS -> inputs of pass P+1.  LEAD: a barrier is needed
 // first because other threads may still read this LDS.
-template <typename T, int N, int TPL, int P, bool SPLIT, bool LEAD>
+template <typename T, int N, int TPL, int P, bool SPLIT, bool LEAD, int ORD>
 FD void exchange(cpx<T>* v, int tj, const LdsView<cpx<T>>& L, const LdsView<T>& Ls)
 {
     if constexpr (!SPLIT) {
         if constexpr (LEAD) __syncthreads();
-        for_outputs<N, TPL, P>(tj, [&](int q, int e) { L[e] = v[q]; });
+        for_outputs<N, TPL, P, ORD>(tj, [&](int q, int e) { L[e] = v[q]; });
         __syncthreads();
-        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q] = L[e]; });
+        for_inputs<N, TPL, P + 1, ORD>(tj, [&](int q, int e) { v[q] = L[e]; });
     } else {
         if constexpr (LEAD) __syncthreads();
-        for_outputs<N, TPL, P>(tj, [&](int q, int e) { Ls[e] = v[q].re; });
+        for_outputs<N, TPL, P, ORD>(tj, [&](int q, int e) { Ls[e] = v[q].re; });
         __syncthreads();
-        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q].re = Ls[e]; });
+        for_inputs<N, TPL, P + 1, ORD>(tj, [&](int q, int e) { v[q].re = Ls[e]; });
         __syncthreads();
-        for_outputs<N, TPL, P>(tj, [&](int q, int e) { Ls[e] = v[q].im; });
+        for_outputs<N, TPL, P, ORD>(tj, [&](int q, int e) { Ls[e] = v[q].im; });
         __syncthreads();
-        for_inputs<N, TPL, P + 1>(tj, [&](int q, int e) { v[q].im = Ls[e]; });
+        for_inputs<N, TPL, P + 1, ORD>(tj, [&](int q, int e) { v[q].im = Ls[e]; });
     }
 }
 
-template <typename T, int N, int TPL, int P, bool SPLIT, bool SRC_LDS, bool DST_LDS, class Store>
+template <typename T, int N, int TPL, int P, bool SPLIT, bool SRC_LDS, bool DST_LDS, int ORD, class Store>
 FD void passes_from(cpx<T>* v, int tj, const cpx<T>* twl, const LdsView<cpx<T>>& L,
                     const LdsView<T>& Ls, Store& store)
 {
-    compute_pass<T, N, TPL, P>(v, tj, twl);
-    if constexpr (PassInfo<N, TPL, P>::LAST) {
+    compute_pass<T, N, TPL, P, ORD>(v, tj, twl);
+    if constexpr (PassInfo<N, TPL, P, ORD>::LAST) {
         if constexpr (DST_LDS && (P > 0 || SRC_LDS)) __syncthreads();
-        for_outputs<N, TPL, P>(tj, [&](int q, int e) { store(e, v[q]); });
+        for_outputs<N, TPL, P, ORD>(tj, [&](int q, int e) { store(e, v[q]); });
     } else {
-        exchange<T, N, TPL, P, SPLIT, (P > 0 || SRC_LDS)>(v, tj, L, Ls);
-        passes_from<T, N, TPL, P + 1, SPLIT, SRC_LDS, DST_LDS>(v, tj, twl, L, Ls, store);
+        exchange<T, N, TPL, P, SPLIT, (P > 0 || SRC_LDS), ORD>(v, tj, L, Ls);
+        passes_from<T, N, TPL, P + 1, SPLIT, SRC_LDS, DST_LDS, ORD>(v, tj, twl, L, Ls, store);
     }
 }
 
@@ -410,18 +410,19 @@ FD void passes_from(cpx<T>* v, int tj, const cpx<T>* twl, const LdsView<cpx<T>>&
 // LDS write may happen before every thread has loaded.  DST_LDS: the storer
 // writes LDS, so no store may happen before every thread has read its
 // inputs.  The loader is called for pass-0 inputs, the storer for the final
-// outputs (natural order).  For N == 1 it is a copy.
+// outputs (natural order).  For N == 1 it is a copy.  ORD selects the pass
+// order of the radices (radix_plan(N, ORD)); twl must hold that order's table.
 template <typename T, int N, int TPL = radix_plan(N).tpl, bool SPLIT = false, bool SRC_LDS = false,
-          bool DST_LDS = false, class Load, class Store>
+          bool DST_LDS = false, int ORD = 0, class Load, class Store>
 FD void fft_line(const LdsView<cpx<T>>& L, const LdsView<T>& Ls, int tj, const cpx<T>* twl, Load& load,
                  Store& store)
 {
     if constexpr (N == 1) {
         if (tj == 0) store(0, load(0));  // one slot per line, touched by one thread
     } else {
-        cpx<T> v[driver_ept<N, TPL>()];
-        load_first<T, N, TPL>(v, tj, load);
-        passes_from<T, N, TPL, 0, SPLIT, SRC_LDS, DST_LDS>(v, tj, twl, L, Ls, store);
+        cpx<T> v[driver_ept<N, TPL, ORD>()];
+        load_first<T, N, TPL, ORD>(v, tj, load);
+        passes_from<T, N, TPL, 0, SPLIT, SRC_LDS, DST_LDS, ORD>(v, tj, twl, L, Ls, store);
     }
 }
 

@@ -85,6 +85,29 @@ constexpr RadixPlan radix_plan(int n)
     return p;
 }
 
+// The same radices in the reverse pass order (ord 1), the alternative order
+// the autotuner may pick for the line kernels; ord 0 is radix_plan(n).
+constexpr RadixPlan radix_plan(int n, int ord)
+{
+    RadixPlan p = radix_plan(n);
+    if (ord == 1)
+        for (int i = 0, j = p.np - 1; i < j; ++i, --j) {
+            const int t = p.r[i];
+            p.r[i] = p.r[j];
+            p.r[j] = t;
+        }
+    return p;
+}
+
+// Whether the reverse order is a different plan (not a palindrome of radices).
+constexpr bool radix_order_distinct(int n)
+{
+    const RadixPlan p = radix_plan(n);
+    for (int i = 0; i < p.np; ++i)
+        if (p.r[i] != p.r[p.np - 1 - i]) return true;
+    return false;
+}
+
 // Product of the radices of passes [0, pass): the sub-transform length that
 // pass `pass` starts from.
 constexpr int radix_ns(const RadixPlan& p, int pass)

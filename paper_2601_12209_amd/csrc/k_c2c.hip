@@ -22,7 +22,7 @@
 
 namespace fft3d {
 
-template <typename T, int N, int TDIV, bool SPLIT, int NT>
+template <typename T, int N, int TDIV, bool SPLIT, int NT, int ORD>
 __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
 {
     constexpr int TPL = radix_plan(N).tpl / TDIV;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
     }
     const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
     cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + align16((size_t)a.lw * line * (SPLIT ? sizeof(T) : sizeof(cpx<T>))));
-    stage_pass_twiddles<T, N>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
+    stage_pass_twiddles<T, N, ORD>(twl, reinterpret_cast<const cpx<T>*>(a.twp), t, blockDim.x);
     const int64_t se = a.se, se_o = a.se_o;
     // element e of this thread's line sits (e - tj) * se past the thread base;
     // e - tj is a compile-time constant at every call site
@@ -95,17 +95,17 @@ __global__ __launch_bounds__(1024) void k_c2c(StageArgs a)
             else out[(e - tj) * se_o] = v * scale;
         }
     };
-    fft_line<T, N, TPL, SPLIT>(L, Ls, tj, twl, load, store);
+    fft_line<T, N, TPL, SPLIT, false, false, ORD>(L, Ls, tj, twl, load, store);
 }
 
-template <typename T, int N, int TDIV, bool SPLIT, int NT = 0>
+template <typename T, int N, int TDIV, bool SPLIT, int NT = 0, int ORD = 0>
 static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
 {
     constexpr int TPL = radix_plan(N).tpl / TDIV;
     const int threads = a.lw * TPL;
     const size_t elem = SPLIT ? sizeof(T) : sizeof(cpx<T>);
     const size_t line = a.strided ? (size_t)N : (size_t)(N + a.pad * (N / 8));
-    const size_t lds = align16((size_t)a.lw * line * elem) + pass_table_bytes<T, N>();
+    const size_t lds = align16((size_t)a.lw * line * elem) + pass_table_bytes<T, N, ORD>();
     dim3 grid;
     if (a.strided) grid = dim3((unsigned)((a.A + (a.align > 1 ? a.align - 1 : 0) + a.lw - 1) / a.lw), (unsigned)a.B, 1);
     else grid = dim3((unsigned)((a.A * a.B + a.lw - 1) / a.lw), 1, 1);
@@ -114,8 +114,8 @@ static hipError_t launch_c2c_v(const StageArgs& a, hipStream_t s)
     StageArgs arg = a;
     // the XCD-grouped tile order needs whole groups of 8 workgroups
     if (!a.strided || ((uint64_t)grid.x * grid.y) % 8 != 0) arg.xcd = 0;
-    return launch_stage_kernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT, NT>), grid, dim3(threads),
-                               arg, lds, s);
+    return launch_stage_kernel(reinterpret_cast<const void*>(&k_c2c<T, N, TDIV, SPLIT, NT, ORD>), grid,
+                               dim3(threads), arg, lds, s);
 }
 
 // Lengths that also get the TDIV = 2, 4 and SPLIT variants: the powers of
@@ -133,6 +133,12 @@ template <typename T, int N>
 static hipError_t launch_c2c_n(const StageArgs& a, hipStream_t s)
 {
     const int tdiv = a.tdiv < 1 ? 1 : a.tdiv;
+    if (a.order == 1) {  // the reverse radix order: one thread per butterfly, plain exchange and accesses
+        if constexpr (radix_order_distinct(N)) {
+            if (tdiv == 1 && !a.split && a.nt == 0) return launch_c2c_v<T, N, 1, false, 0, 1>(a, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (has_variants<N>()) {
         // non-temporal variants: one thread per butterfly only
         if (tdiv == 1 && a.nt == 1)
@@ -165,6 +171,11 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
         return hipErrorInvalidValue;
     }
 #undef FFT3D_C2C_CASE
+}
+
+bool c2c_order_available(int n, int tdiv, int split)
+{
+    return length_supported(n) && radix_order_distinct(n) && tdiv == 1 && !split;
 }
 
 bool c2c_variant_available(int n, int tdiv, int split)

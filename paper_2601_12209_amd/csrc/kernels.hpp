@@ -16,6 +16,9 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s);
 // Whether the C2C kernel of length n has the (tdiv, split) variant.
 bool c2c_variant_available(int n, int tdiv, int split);
+// Whether the C2C kernel of length n runs the reverse radix order
+// (StageArgs::order = 1) in this (tdiv, split) shape.
+bool c2c_order_available(int n, int tdiv, int split);
 // n is the real line length (even); the complex kernel runs at n/2.
 hipError_t launch_r2c_x(int n, int dtype, const StageArgs& a, hipStream_t s);
 hipError_t launch_c2r_x(int n, int dtype, const StageArgs& a, hipStream_t s);

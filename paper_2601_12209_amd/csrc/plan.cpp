@@ -367,10 +367,10 @@ void twiddles_f32(int64_t n, float* out)
 
 namespace fft3d {
 
-int64_t pass_twiddles_f64(int64_t n, double* out)
+int64_t pass_twiddles_f64(int64_t n, double* out, int ord)
 {
     if (!length_supported(n)) return -1;
-    const RadixPlan rp = radix_plan((int)n);
+    const RadixPlan rp = radix_plan((int)n, ord);
     const int64_t total = pass_table_size(rp);
     if (!out || total == 0) return total;
     std::vector<double> w((size_t)(2 * n));
@@ -389,12 +389,12 @@ int64_t pass_twiddles_f64(int64_t n, double* out)
     return total;
 }
 
-int64_t pass_twiddles_f32(int64_t n, float* out)
+int64_t pass_twiddles_f32(int64_t n, float* out, int ord)
 {
-    const int64_t total = pass_twiddles_f64(n, nullptr);
+    const int64_t total = pass_twiddles_f64(n, nullptr, ord);
     if (!out || total <= 0) return total;
     std::vector<double> d((size_t)(2 * total));
-    pass_twiddles_f64(n, d.data());
+    pass_twiddles_f64(n, d.data(), ord);
     for (int64_t i = 0; i < 2 * total; ++i) out[i] = (float)d[(size_t)i];
     return total;
 }

@@ -120,9 +120,10 @@ void twiddles_f32(int64_t n, float* out);  // round-to-nearest-even of the f64 t
 
 // Per-pass table of the length-n Stockham kernel (layout in fft_lengths.hpp),
 // built from the same FP64 roots (entries are copies of table values).
-// Returns the number of complex entries; writes them if out is non-null.
-int64_t pass_twiddles_f64(int64_t n, double* out);
-int64_t pass_twiddles_f32(int64_t n, float* out);
+// Returns the number of complex entries; writes them if out is non-null.  ord
+// 1: the table of the reverse radix order (radix_plan(n, 1)).
+int64_t pass_twiddles_f64(int64_t n, double* out, int ord = 0);
+int64_t pass_twiddles_f32(int64_t n, float* out, int ord = 0);
 
 // ---------------------------------------------------------------- batches
 

@@ -167,6 +167,7 @@ struct fft3d_plan_s {
     hipEvent_t fork = nullptr;
     void* tw[3] = {nullptr, nullptr, nullptr};   // per-axis forward root tables
     void* twp[3] = {nullptr, nullptr, nullptr};  // per-axis per-pass tables of the kernel length
+    void* twp_rev[3] = {nullptr, nullptr, nullptr};  // the same for the reverse radix order (C2C axes)
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = false;
@@ -174,6 +175,7 @@ struct fft3d_plan_s {
     bool pipe_ok[OP_COUNT] = {};
     std::vector<char> needs_event[OP_COUNT];
     KConf conf_override[3];  // per axis; lw == 0: default
+    int order_override[3] = {0, 0, 0};  // per axis: radix order of the C2C line kernels
     // Completion of the last call issued outside a stream capture, recorded on
     // that call's stream.  A call on another stream first waits on it, so two
     // streams never use the plan's workspace at once; the destructor and the
@@ -431,6 +433,21 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
         KConf o = ov;
         if (conf_fits(st, d.dtype, o, st.axis != 0)) c = o;
     }
+    // the reverse radix order where the axis asks for it: its kernel takes one
+    // thread per butterfly and the plain exchange, so the shape gives way
+    // (fewer lines where the threads no longer fit)
+    bool reverse = false;
+    if (st.kind == K_C2C && p->order_override[st.axis] == 1 && p->twp_rev[st.axis] &&
+        radix_order_distinct(kernel_length(st))) {
+        KConf o = c;
+        o.tdiv = 1;
+        o.split = 0;
+        while (o.lw > 1 && !conf_fits(st, d.dtype, o, st.axis != 0)) o.lw /= 2;
+        if (conf_fits(st, d.dtype, o, st.axis != 0) && c2c_order_available(kernel_length(st), 1, 0)) {
+            c = o;
+            reverse = true;
+        }
+    }
     a.lw = c.lw;
     a.tdiv = c.tdiv;
     a.split = c.split;
@@ -446,6 +463,11 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     // with it, so they keep the plain order
     if (a.strided && d.dtype == DT_F64) a.xcd = 1;
     a.nt = c2c_cache_policy(d, st, a, per_line);
+    if (reverse) {
+        a.order = 1;
+        a.twp = p->twp_rev[st.axis];
+        a.nt = 0;  // the reverse-order kernel has plain accesses only
+    }
     return a;
 }
 
@@ -839,6 +861,8 @@ void release(fft3d_plan_s* p)
         if (t) hipFree(t);
     for (void* t : p->twp)
         if (t) hipFree(t);
+    for (void* t : p->twp_rev)
+        if (t) hipFree(t);
     if (p->ws && p->ws_owned) hipFree(p->ws);
     delete p;
 }
@@ -905,6 +929,20 @@ static fft3d_status make_plan(fft3d_plan_t* plan, const PlanDesc& d)
         if (e != hipSuccess) {
             release(p);
             return hip_fail(e, "twiddle upload");
+        }
+        // the reverse radix order's table, for axes whose line kernels are C2C
+        if (!(r2c && ax == 0) && radix_order_distinct((int)nk)) {
+            const int64_t rentries = pass_twiddles_f64(nk, nullptr, 1);
+            const size_t rbytes = (size_t)rentries * elem_bytes(dtype);
+            std::vector<char> rhost(rbytes, 0);
+            if (dtype == DT_F64) pass_twiddles_f64(nk, (double*)rhost.data(), 1);
+            else pass_twiddles_f32(nk, (float*)rhost.data(), 1);
+            e = hipMalloc(&p->twp_rev[ax], rbytes);
+            if (e == hipSuccess) e = hipMemcpy(p->twp_rev[ax], rhost.data(), rbytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                release(p);
+                return hip_fail(e, "twiddle upload");
+            }
         }
     }
     if (r2c) {
@@ -1217,6 +1255,36 @@ int fft3d_get_issue(fft3d_plan_t p)
     }
     std::lock_guard<std::mutex> lock(p->mu);
     return p->issue;
+}
+
+fft3d_status fft3d_set_radix_order(fft3d_plan_t p, int axis, int order)
+{
+    if (!p) return fail(FFT3D_ERR_INVALID_ARG, "null plan");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (axis < 0 || axis > 2) return fail(FFT3D_ERR_INVALID_ARG, "axis must be 0..2");
+    if (order != 0 && order != 1) return fail(FFT3D_ERR_INVALID_ARG, "order must be 0 or 1");
+    if (order == 1) {
+        // some C2C line kernel of this axis must have a distinct reverse order
+        bool any = false;
+        for (int op = 0; op < OP_COUNT; ++op)
+            for (const Stage& st : op_stages(p->d, op))
+                any = any || (st.axis == axis && st.kind == K_C2C && radix_order_distinct(kernel_length(st)));
+        if (!any || !p->twp_rev[axis])
+            return fail(FFT3D_ERR_INVALID_ARG, "no line kernel of this axis has another radix order");
+    }
+    drop_groups(p);
+    p->order_override[axis] = order;
+    return FFT3D_OK;
+}
+
+int fft3d_get_radix_order(fft3d_plan_t p, int axis)
+{
+    if (!p || axis < 0 || axis > 2) {
+        fail(FFT3D_ERR_INVALID_ARG, "null plan or axis out of range");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    return p->order_override[axis];
 }
 
 fft3d_status fft3d_set_stage_config(fft3d_plan_t p, int axis, int lw, int tdiv, int split, int pad)

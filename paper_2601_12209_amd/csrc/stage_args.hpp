@@ -80,6 +80,9 @@ struct StageArgs {
     int weight;   // R2C: interior bins x2 / C2R: interior bins x1/2 (adjoint paths);
                   // K_R2R_Z: the transposed DCT2/DST2 (see R2RMode)
     int r2r;      // K_R2R_Z: R2RMode
+    int order;    // K_C2C: 1 runs the radices in the reverse pass order (twp is that
+                  // order's per-pass table; one thread per butterfly, no split, plain
+                  // accesses)
     double scale; // multiplies every output
     // spectral multiplier (K_POISSON_Z): full grid sizes and the global
     // (kx, ky) of line (0, 0)

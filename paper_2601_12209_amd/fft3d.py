@@ -204,6 +204,14 @@ class Plan:
         check(_lib.lib().fft3d_set_stage_config(self._h, int(axis), int(lw), int(tdiv), int(split),
                                                 int(pad)), "fft3d_set_stage_config")
 
+    def set_radix_order(self, axis: int, order: int):
+        """Radix order of the complex line kernels along one axis: 0 the default, 1 the reverse
+        pass order (changes rounding, not the result beyond it)."""
+        check(_lib.lib().fft3d_set_radix_order(self._h, int(axis), int(order)), "fft3d_set_radix_order")
+
+    def radix_order(self, axis: int) -> int:
+        return int(_lib.lib().fft3d_get_radix_order(self._h, int(axis)))
+
     def set_timing(self, enable: bool = True):
         """Record a HIP event after every stage of each call (stages then run one after another)."""
         check(_lib.lib().fft3d_set_timing(self._h, int(bool(enable))), "fft3d_set_timing")
@@ -262,6 +270,11 @@ class BatchPlan:
         """STAGING_IN_PLACE or STAGING_FUSED_XY for the transforms of one (nz, ny, nx) shape."""
         nz, ny, nx = shape
         check(_lib.lib().fft3d_batch_set_staging(self._h, nx, ny, nz, int(staging)), "fft3d_batch_set_staging")
+
+    def set_radix_order(self, shape, axis: int, order: int):
+        nz, ny, nx = shape
+        check(_lib.lib().fft3d_batch_set_radix_order(self._h, nx, ny, nz, int(axis), int(order)),
+              "fft3d_batch_set_radix_order")
 
     def set_streams(self, n: int):
         """Streams the batch's shapes run on concurrently (1: all on the caller's stream)."""

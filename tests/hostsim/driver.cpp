@@ -102,6 +102,21 @@ void c2c_cases(hipStream_t user)
                 EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_set_issue(p, 2) == FFT3D_ERR_INVALID_ARG);
+            // the reverse radix order on every axis that has one
+            for (int ax = 0; ax < 3; ++ax) {
+                const int64_t n = ax == 0 ? c.nx : ax == 1 ? c.ny : c.nz;
+                // x and y run as fused planes (no line kernel) in that staging
+                const bool lines = !(fft3d_get_staging(p) == FFT3D_STAGING_FUSED_XY && ax < 2);
+                const fft3d_status r = fft3d_set_radix_order(p, ax, 1);
+                EXPECT(r == (lines && fft3d::radix_order_distinct((int)n) ? FFT3D_OK : FFT3D_ERR_INVALID_ARG));
+            }
+            EXPECT(fft3d_forward(p, in.p, out.p, user) == FFT3D_OK);
+            EXPECT(fft3d_inverse(p, out.p, out.p, user) == FFT3D_OK);
+            EXPECT(fft3d_set_radix_order(p, 0, 2) == FFT3D_ERR_INVALID_ARG);
+            EXPECT(fft3d_set_radix_order(p, 3, 0) == FFT3D_ERR_INVALID_ARG);
+            for (int ax = 0; ax < 3; ++ax) EXPECT(fft3d_set_radix_order(p, ax, 0) == FFT3D_OK);
+            EXPECT(fft3d_get_radix_order(p, 1) == 0);
+            EXPECT(fft3d_get_radix_order(nullptr, 1) == -1);
             EXPECT(fft3d_get_issue(nullptr) == -1);
             // more buffer sets, then a setter
             {
@@ -234,6 +249,17 @@ void r2c_cases(hipStream_t user)
                 EXPECT(fft3d_poisson_backward(p, r2.p, r.p, user) == FFT3D_OK);
             }
             EXPECT(fft3d_forward(p, r.p, r.p, user) == FFT3D_ERR_ALIAS);
+            // radix order: none on the real x kernels; y and z where distinct
+            EXPECT(fft3d_set_radix_order(p, 0, 1) == FFT3D_ERR_INVALID_ARG);
+            for (int ax : {1, 2}) {
+                const int64_t n = ax == 1 ? c.ny : c.nz;
+                EXPECT(fft3d_set_radix_order(p, ax, 1) ==
+                       (fft3d::radix_order_distinct((int)n) ? FFT3D_OK : FFT3D_ERR_INVALID_ARG));
+            }
+            EXPECT(fft3d_forward(p, r.p, h.p, user) == FFT3D_OK);
+            EXPECT(fft3d_inverse(p, h.p, r2.p, user) == FFT3D_OK);
+            EXPECT(fft3d_poisson(p, r.p, r2.p, user) == FFT3D_OK);
+            for (int ax : {1, 2}) EXPECT(fft3d_set_radix_order(p, ax, 0) == FFT3D_OK);
             // both forward stagings, then back to in place
             for (int stg : {FFT3D_STAGING_IN_PLACE, FFT3D_STAGING_SWAP_YZ}) {
                 EXPECT(fft3d_set_staging(p, stg) == FFT3D_OK);

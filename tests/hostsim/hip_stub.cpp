@@ -460,7 +460,7 @@ bool has_variants(int n)
     return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 840;
 }
 
-size_t table_entries(int n) { return (size_t)pass_table_size(radix_plan(n)); }
+size_t table_entries(int n, int ord = 0) { return (size_t)pass_table_size(radix_plan(n, ord)); }
 
 size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
@@ -482,9 +482,9 @@ void check_range(const void* base, size_t es, int64_t off, int64_t A, int64_t sa
     in_alloc((const char*)base + lo * es, (size_t)(hi - lo + 1) * es, what);
 }
 
-void check_tables(const StageArgs& a, int n, size_t es, const char* what)
+void check_tables(const StageArgs& a, int n, size_t es, const char* what, int ord = 0)
 {
-    const size_t s = table_entries(n);
+    const size_t s = table_entries(n, ord);
     if (s) in_alloc(a.twp, s * es, what);
 }
 
@@ -509,6 +509,11 @@ hipError_t launched(const fft3d::StageArgs& a, hipStream_t s, int kind, int n, i
 
 }  // namespace
 
+bool c2c_order_available(int n, int tdiv, int split)
+{
+    return length_supported(n) && radix_order_distinct(n) && tdiv == 1 && !split;
+}
+
 bool c2c_variant_available(int n, int tdiv, int split)
 {
     if (tdiv == 1 && !split) return length_supported(n);
@@ -522,10 +527,12 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
     if (!length_supported(n)) return hipErrorInvalidValue;
     const int tdiv = a.tdiv < 1 ? 1 : a.tdiv;
     if (!c2c_variant_available(n, tdiv, a.split)) return hipErrorInvalidValue;
+    if (a.order != 0 && (a.order != 1 || !c2c_order_available(n, tdiv, a.split) || a.nt != 0))
+        return hipErrorInvalidValue;
     const size_t es = dtype == DT_F64 ? 16 : 8;
     const int threads = a.lw * (radix_plan(n).tpl / tdiv);
     const size_t line = a.strided ? (size_t)n : (size_t)(n + a.pad * (n / 8));
-    const size_t lds = align16((size_t)a.lw * line * (a.split ? es / 2 : es)) + table_entries(n) * es;
+    const size_t lds = align16((size_t)a.lw * line * (a.split ? es / 2 : es)) + table_entries(n, a.order) * es;
     const int64_t blocks = a.strided ? (a.A + (a.align > 1 ? a.align - 1 : 0) + a.lw - 1) / a.lw
                                      : (a.A * a.B + a.lw - 1) / a.lw;
     if (a.align > 1 && (!a.strided || a.lw % a.align != 0)) violation("c2c align without a strided tile of whole lines");
@@ -542,8 +549,8 @@ hipError_t launch_c2c(int n, int dtype, const StageArgs& a, hipStream_t s)
         check_range(a.in, es, a.off, a.A, a.sa, a.B, a.sb, n, 1, "c2c load");
         check_range(a.out, es, a.off_o, a.A, a.sa_o, a.B, a.sb_o, n, 1, "c2c store");
     }
-    check_tables(a, n, es, "c2c pass table");
-    return launched(a, s, K_C2C, n, 0, dtype);
+    check_tables(a, n, es, "c2c pass table", a.order);
+    return launched(a, s, K_C2C, n, a.order, dtype);
 }
 
 static hipError_t launch_real(bool r2c, int n, int dtype, const StageArgs& a, hipStream_t s)

@@ -444,6 +444,52 @@ def test_task_graph_replay_r2c(gpu_lib, dtype):
     plan.close()
 
 
+ORDER_CASES = [((48, 100, 120), (1, 1)), ((40, 256, 48), (2, 2)), ((35, 42, 56), (3, 2)), ((16, 1024, 8), (2, 2)),
+               ((6, 840, 4), (1, 1))]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c64", "c128"])
+@pytest.mark.parametrize("shape,grid", ORDER_CASES, ids=[f"{s}-{g}" for s, g in ORDER_CASES])
+def test_reverse_radix_order(gpu_lib, shape, grid, dtype):
+    """The reverse radix order on every axis that has one (in-place line
+    stages): forward, inverse and backward against the oracle; launch shapes
+    and issue modes still change no bits within that order."""
+    from paper_2601_12209_amd._lib import Fft3dError
+
+    print(f"case radix order shape={shape} grid={grid} dtype={dtype}", flush=True)
+    a = synth.complex_normal(shape, 52)
+    x = to_dev(a, dtype)
+    ref_in = promoted(a, dtype)
+    tol = bound(dtype, a.size)
+    plan = gpu_lib.Plan(shape, dtype, grid, streams=2, staging=gpu_lib.STAGING_IN_PLACE)
+    nz, ny, nx = shape
+    reversed_axes = []
+    for ax, n in enumerate((nx, ny, nz)):
+        radices, _ = gpu_lib.query_radix_plan(n)
+        if radices != radices[::-1]:
+            plan.set_radix_order(ax, 1)
+            reversed_axes.append(ax)
+        else:
+            with pytest.raises(Fft3dError):
+                plan.set_radix_order(ax, 1)
+    assert reversed_axes
+    X, xi, xb = plan.forward(x), plan.inverse(x), plan.backward(x)
+    torch.cuda.synchronize()
+    assert_parity(to_host(X), oracle.fftn(ref_in), tol)
+    assert_parity(to_host(xi), oracle.ifftn(ref_in), tol)
+    assert_parity(to_host(xb), oracle.bfftn(ref_in), tol)
+    plan.set_issue(gpu_lib.ISSUE_TILES)
+    for ax in reversed_axes:
+        try:
+            plan.set_stage_config(ax, 4 if ax else 2)
+        except Fft3dError:
+            pass
+    X2 = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(X2, X)
+    plan.close()
+
+
 FUSED_CASES = [((40, 64, 64), (1, 4)), ((12, 120, 100), (1, 2)), ((8, 160, 80), (1, 1)), ((16, 128, 128), (1, 1)),
                ((7, 24, 24), (1, 1)), ((5, 8, 8), (1, 1)), ((3, 48, 48), (1, 3)), ((20, 96, 96), (1, 1))]
 
