@@ -286,11 +286,23 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         // 2.42 ms at 512^3 on MI355X against 2.43 for 16-line tiles and 2.46
         // with the split exchange.  Otherwise (the R2C half spectrum's 257
         // columns) 16 lines, one thread per butterfly.
-        if (c2c && d.dtype == DT_F32 && nk == 512 && a >= 16) {
+        // (decided per plan, not per tile, so that every tile of a stage runs
+        // the same kernel and the stage stays one grouped launch)
+        if (c2c && d.dtype == DT_F32 && nk == 512 && d.nxc() >= 16) {
             KConf w;
-            const bool whole32 = a % 32 == 0 && c2c_variant_available(nk, 2, 0);
+            const bool whole32 = !d.r2c && d.nx % 32 == 0 && c2c_variant_available(nk, 2, 0);
             w.lw = whole32 ? 32 : 16;
             w.tdiv = whole32 ? 2 : 1;
+            w.split = 0;
+            if (conf_fits(st, d.dtype, w, true)) c = w;
+        }
+        // complex64 lines of 1024 over an R2C half spectrum: 16 lines with a
+        // full complex LDS tile as well (1024^3 z stage 2.52 ms against 2.74
+        // with the split exchange, MI355X)
+        if (c2c && d.dtype == DT_F32 && nk == 1024 && d.r2c && d.nxc() >= 16) {
+            KConf w;
+            w.lw = 16;
+            w.tdiv = 1;
             w.split = 0;
             if (conf_fits(st, d.dtype, w, true)) c = w;
         }
@@ -306,12 +318,14 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         // per line: 1.43 against 1.48; MI355X)
         if (!pow2_tpl)
             while (lw * tpl < (tpl >= 32 ? 128 : 256)) lw *= 2;
-        // the complex64 real kernels at half length 256 (512^3) run fastest with
-        // more lines per workgroup on MI355X: R2C split 16 lines (512
-        // threads), 237 -> 195 us; C2R merge 8 lines, 241 -> 233 us (the
-        // complex128 ones are best at the default 4 lines)
-        if (st.kind == K_R2C_X && d.dtype == DT_F32 && nk == 256) lw = 16;
-        if (st.kind == K_C2R_X && d.dtype == DT_F32 && nk == 256) lw = 8;
+        // the complex64 real kernels at half lengths 256 and 512 run fastest
+        // with more lines per workgroup on MI355X: R2C 512 threads (512^3:
+        // 16 lines, 237 -> 195 us; 1024^3: 8 lines), C2R 8 lines (512^3: 241
+        // -> 233 us); the complex128 ones are best at the default
+        if (d.dtype == DT_F32 && (nk == 256 || nk == 512)) {
+            if (st.kind == K_R2C_X) lw = 512 / tpl;
+            if (st.kind == K_C2R_X) lw = 8;
+        }
         c.lw = lw;
         c.split = c2c && c2c_variant_available(nk, 1, 1) ? 1 : 0;
         c.pad = 1;

@@ -439,6 +439,25 @@ def _by_stage(fft3d, shape, dtype, r2c=False, op=0, staging=0, grid=(1, 1)):
     return [(stages[t["stage"]], L) for t, L in zip(tasks, launches)]
 
 
+@pytest.mark.parametrize("shape,dtype,r2c,grid", [((256, 256, 256), "c64", False, (4, 4)),
+                                                   ((256, 256, 256), "c128", False, (4, 4)),
+                                                   ((1024, 1024, 1024), "f32", True, (8, 8)),
+                                                   ((512, 512, 512), "f32", True, (4, 4)),
+                                                   ((512, 512, 512), "c64", False, (3, 3)),
+                                                   ((840, 840, 840), "c64", False, (2, 2))])
+def test_tiles_of_a_stage_share_a_launch_shape(fft3d, shape, dtype, r2c, grid):
+    """Every tile of a stage gets the same launch configuration (the stage then
+    goes out as one grouped launch): the defaults are chosen per plan, not per
+    tile, for the tiled workloads."""
+    for op in (0, 1):
+        by = {}
+        for st, L in _by_stage(fft3d, shape, dtype, r2c=r2c, op=op, grid=grid):
+            key = (st["axis"], st["kind"])
+            by.setdefault(key, set()).add(tuple(sorted(L.items())))
+        for key, confs in by.items():
+            assert len(confs) == 1, (shape, dtype, op, key, confs)
+
+
 def test_cache_policy_large_c2c(fft3d):
     """512^3 swapped staging: complex128 stages stream with non-temporal loads and
     stores (whole cache lines of another buffer) and XCD-grouped strided tiles;
