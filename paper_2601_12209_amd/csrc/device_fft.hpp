@@ -221,6 +221,93 @@ template <typename T> FD void dft15(cpx<T>* x)
         for (int k2 = 0; k2 < 5; ++k2) x[(10 * k1 + 6 * k2) % 15] = b[k1][k2];
 }
 
+// ---------------------------------------------------------------- odd primes
+// cos and sin of 2 pi m / P for the generic prime radix, evaluated at compile
+// time in long double by their Taylor series (the argument is first reduced
+// to [0, pi/2] by symmetry) and rounded once to the kernel's precision.
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+
+constexpr long double taylor_sin(long double x)
+{
+    long double term = x, sum = x;
+    for (int k = 1; k < 30; ++k) {
+        term *= -x * x / ((2 * k) * (2 * k + 1));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr long double taylor_cos(long double x)
+{
+    long double term = 1, sum = 1;
+    for (int k = 1; k < 30; ++k) {
+        term *= -x * x / ((2 * k - 1) * (2 * k));
+        sum += term;
+    }
+    return sum;
+}
+
+// cos(2 pi m / P) and sin(2 pi m / P), 0 < m < P.
+constexpr long double cos_2pi(int m, int P)
+{
+    const long double x = 2 * kPiL * m / P;  // in [0, 2 pi)
+    if (x > kPiL) return cos_2pi(P - m, P);  // cos is even about pi
+    return x <= kPiL / 2 ? taylor_cos(x) : -taylor_cos(kPiL - x);
+}
+
+constexpr long double sin_2pi(int m, int P)
+{
+    const long double x = 2 * kPiL * m / P;
+    if (x > kPiL) return -sin_2pi(P - m, P);
+    return x <= kPiL / 2 ? taylor_sin(x) : taylor_sin(kPiL - x);
+}
+
+// The length-P DFT of an odd prime P from the mirrored pairs t_j = x_j +
+// x_(P-j), d_j = x_j - x_(P-j), j = 1..(P-1)/2:
+//   X_k = x_0 + sum_j t_j cos(2 pi jk/P) - i sum_j d_j sin(2 pi jk/P)
+// and X_(P-k) the same with +i, for k = 1..(P-1)/2 (jk reduced mod P).  The
+// generic form of the radix-7 butterfly, O(P^2) real multiply-adds.
+template <typename T, int P>
+struct PrimeRoots {
+    T c[P], s[P];
+    constexpr PrimeRoots() : c(), s()
+    {
+        for (int m = 0; m < P; ++m) {
+            c[m] = (T)cos_2pi(m, P);
+            s[m] = (T)sin_2pi(m, P);
+        }
+    }
+};
+
+template <int P, typename T> FD void dft_prime(cpx<T>* v)
+{
+    constexpr int H = (P - 1) / 2;
+    constexpr PrimeRoots<T, P> W{};  // folded at compile time
+    cpx<T> t[H + 1], d[H + 1];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        t[j] = v[j] + v[P - j];
+        d[j] = v[j] - v[P - j];
+    }
+    const cpx<T> x0 = v[0];
+    cpx<T> s0 = x0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) s0 = s0 + t[j];
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        cpx<T> a = x0, b = {(T)0, (T)0};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const T c = W.c[(j * k) % P], s = W.s[(j * k) % P];
+            a = a + t[j] * c;
+            b = b + d[j] * s;
+        }
+        v[k] = a + mul_negi(b);
+        v[P - k] = a + mul_i(b);
+    }
+    v[0] = s0;
+}
+
 template <int R, typename T> FD void dft_radix(cpx<T>* v)
 {
     if constexpr (R == 2) dft2(v);
@@ -229,6 +316,7 @@ template <int R, typename T> FD void dft_radix(cpx<T>* v)
     else if constexpr (R == 5) dft5(v);
     else if constexpr (R == 7) dft7(v);
     else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 11 || R == 13) dft_prime<R>(v);
     else if constexpr (R == 15) dft15(v);
     else if constexpr (R == 16) dft16(v);
     else static_assert(R == 2, "unsupported radix");

@@ -11,14 +11,16 @@
 
 // Lengths with a compiled kernel: products 2^a 3^b 5^c 7^d up to 4096 that
 // cover every workload shape (including the 480, 720 and 840 grids of the
-// paper's GPU runs) plus a spread of common sizes.
+// paper's GPU runs) plus a spread of common sizes, and 11 and 13 times powers
+// of two (the generic odd-prime radix).
 #define FFT3D_FOR_EACH_LENGTH(X)                                                      \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(14) X(15) X(16) X(20)       \
     X(21) X(24) X(25) X(28) X(30) X(32) X(35) X(40) X(42) X(48) X(50) X(56) X(60)     \
     X(64) X(70) X(75) X(80) X(84) X(96) X(100) X(105) X(112) X(120) X(125) X(128)     \
     X(140) X(150) X(160) X(168) X(192) X(200) X(210) X(240) X(250) X(256) X(280)      \
     X(300) X(320) X(384) X(400) X(420) X(480) X(500) X(512) X(600) X(640) X(720)      \
-    X(750) X(768) X(800) X(840) X(960) X(1000) X(1024) X(2048) X(4096)
+    X(750) X(768) X(800) X(840) X(960) X(1000) X(1024) X(2048) X(4096)                \
+    X(11) X(13) X(22) X(26) X(44) X(52) X(88) X(104) X(176) X(208)
 
 namespace fft3d {
 
@@ -39,11 +41,13 @@ constexpr RadixPlan radix_plan(int n)
         p.np = -1;
         return p;
     }
-    int m = n, a = 0, b = 0, c = 0, d = 0;
+    int m = n, a = 0, b = 0, c = 0, d = 0, e = 0, f = 0;
     while (m % 2 == 0) { m /= 2; ++a; }
     while (m % 3 == 0) { m /= 3; ++b; }
     while (m % 5 == 0) { m /= 5; ++c; }
     while (m % 7 == 0) { m /= 7; ++d; }
+    while (m % 11 == 0) { m /= 11; ++e; }  // the generic prime radix (dft_prime)
+    while (m % 13 == 0) { m /= 13; ++f; }
     if (m != 1) {
         p.np = -1;
         return p;
@@ -79,6 +83,8 @@ constexpr RadixPlan radix_plan(int n)
     for (int i = p15; i < b; ++i) p.r[p.np++] = 3;
     for (int i = p15; i < c; ++i) p.r[p.np++] = 5;
     for (int i = 0; i < d; ++i) p.r[p.np++] = 7;
+    for (int i = 0; i < e; ++i) p.r[p.np++] = 11;
+    for (int i = 0; i < f; ++i) p.r[p.np++] = 13;
     int rmax = 1;
     for (int i = 0; i < p.np; ++i) rmax = p.r[i] > rmax ? p.r[i] : rmax;
     p.tpl = n / rmax;

@@ -222,7 +222,7 @@ def test_batch_errors(gpu_lib):
     from paper_2601_12209_amd._lib import Fft3dError
 
     with pytest.raises(Fft3dError):
-        gpu_lib.BatchPlan([(8, 8, 11)])  # unsupported length
+        gpu_lib.BatchPlan([(8, 8, 17)])  # unsupported length
     bp = gpu_lib.BatchPlan([(8, 8, 8), (8, 8, 8)])
     buf = torch.zeros(1024, dtype=torch.complex64, device="cuda")
     a, b = buf[:512].view(8, 8, 8), buf[256:768].view(8, 8, 8)

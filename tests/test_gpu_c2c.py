@@ -45,6 +45,10 @@ CASES = [
     ((2, 5, 840), (1, 1)),
     ((6, 720, 4), (2, 2)),
     ((105, 70, 112), (1, 1)),
+    # the generic odd-prime radix: 11 and 13 times powers of two
+    ((13, 22, 11), (2, 2)),
+    ((26, 176, 52), (1, 2)),
+    ((208, 11, 104), (1, 1)),
 ]
 
 
@@ -178,7 +182,7 @@ def test_alias_and_argument_errors(gpu_lib):
     from paper_2601_12209_amd._lib import Fft3dError
 
     with pytest.raises(Fft3dError):
-        gpu_lib.Plan((8, 8, 11), torch.complex64)  # 11 has no kernel
+        gpu_lib.Plan((8, 8, 17), torch.complex64)  # 17 has no kernel
     with pytest.raises(Fft3dError):
         gpu_lib.Plan((8, 8, 8), torch.complex64, (9, 1))  # p1 > ny
     plan = gpu_lib.Plan((8, 8, 8), torch.complex64)

@@ -36,6 +36,7 @@ CASES = [
     ((96, 40, 30), (4, 2)),
     ((21, 14, 28), (1, 2)),   # radix 7
     ((512, 4, 6), (1, 1)),    # long bounded axis
+    ((13, 22, 26), (1, 1)),   # the generic odd-prime radix (11, 13)
 ]
 
 

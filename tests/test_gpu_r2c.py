@@ -36,6 +36,9 @@ CASES = [
     ((7, 35, 84), (1, 3)),
     ((4, 3, 840), (1, 1)),
     ((840, 2, 6), (1, 1)),
+    # the generic odd-prime radix: half lengths 11, 13, 104
+    ((13, 11, 22), (1, 1)),
+    ((11, 26, 208), (2, 1)),
 ]
 
 

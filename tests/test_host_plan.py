@@ -46,7 +46,7 @@ def test_header_symbols_exported(fft3d):
 SUPPORTED = [1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 15, 16, 20, 21, 24, 25, 28, 30, 32, 35, 40, 42, 48, 50,
              56, 60, 64, 70, 75, 80, 84, 96, 100, 105, 112, 120, 125, 128, 140, 150, 160, 168, 192, 200, 210,
              240, 250, 256, 280, 300, 320, 384, 400, 420, 480, 500, 512, 600, 640, 720, 750, 768, 800, 840,
-             960, 1000, 1024, 2048, 4096]
+             960, 1000, 1024, 2048, 4096, 11, 13, 22, 26, 44, 52, 88, 104, 176, 208]
 
 
 def test_supported_lengths_and_radix_plans(fft3d):
@@ -55,7 +55,7 @@ def test_supported_lengths_and_radix_plans(fft3d):
     for n in SUPPORTED:
         radices, tpl = fft3d.query_radix_plan(n)
         assert int(np.prod(radices)) == n
-        assert set(radices) <= {2, 3, 4, 5, 7, 8, 15, 16}
+        assert set(radices) <= {2, 3, 4, 5, 7, 8, 11, 13, 15, 16}
         if n % 15 == 0:  # a factor 3 and a factor 5 form one radix-15 pass unless a radix 16 sets the threads
             assert (15 in radices) != (16 in radices), (n, radices)
         assert tpl == (n // max(radices) if radices else 1)
@@ -519,7 +519,7 @@ def test_launch_query_rejects_bad_arguments(fft3d):
     with pytest.raises(ValueError):
         fft3d.query_launches((8, 8, 8), "c64", r2c=True, staging=2)
     with pytest.raises(ValueError):
-        fft3d.query_launches((8, 8, 11), "c64")
+        fft3d.query_launches((8, 8, 17), "c64")
 
 
 def test_x_ranges_of_tiles_start_on_cache_lines(fft3d):
