@@ -280,6 +280,11 @@ KConf default_conf(const PlanDesc& d, const Stage& st, const Box& b)
         c.lw = lw;
         c.tdiv = tdiv;
         c.split = c2c && c2c_variant_available(nk, tdiv, 1) ? 1 : 0;
+        // complex64 lines of 64-256 points: the full complex LDS tile (at most
+        // 32 KiB for 16 lines) runs faster than the split exchange (autotuner
+        // at 256^3 on MI355X: y and z 3-5 % faster; the batch's 64^3 and
+        // 100x120x128 z stages chose it too)
+        if (c2c && d.dtype == DT_F32 && nk <= 256 && pow2_tpl && (nk & (nk - 1)) == 0) c.split = 0;
         // complex64 lines of 512 with a full complex LDS tile (no split
         // exchange).  In whole 32-line tiles: 32 lines per workgroup
         // (256-byte row segments) with half the threads per line: fwd+inv
