@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -57,6 +58,7 @@ struct CachedIssue {
 }  // namespace
 
 struct fft3d_batch_s {
+    std::mutex mu;  // calls and setters on one batch are serialised
     std::vector<PlanDesc> ffts;
     int dtype = 0;
     int device = 0;
@@ -232,6 +234,7 @@ hipError_t ensure_streams(fft3d_batch_t b, int ns)
 fft3d_status run_batch(fft3d_batch_t b, int op, const void* const* in, void* const* out, void* stream)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    std::lock_guard<std::mutex> lock(b->mu);
     if (!in || !out) return set_error(FFT3D_ERR_INVALID_ARG, "null pointer array");
     const int count = (int)b->ffts.size();
     const size_t es = b->dtype == DT_F64 ? 16 : 8;
@@ -402,6 +405,7 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
                                           int tdiv, int split, int pad)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    std::lock_guard<std::mutex> lock(b->mu);
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     drop_cache(b);  // launch shapes are baked into the cached launches
@@ -411,6 +415,7 @@ fft3d_status fft3d_batch_set_stage_config(fft3d_batch_t b, int64_t nx, int64_t n
 fft3d_status fft3d_batch_set_radix_order(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int axis, int order)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    std::lock_guard<std::mutex> lock(b->mu);
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     drop_cache(b);  // the radix order is baked into the cached launches
@@ -420,6 +425,7 @@ fft3d_status fft3d_batch_set_radix_order(fft3d_batch_t b, int64_t nx, int64_t ny
 fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz, int staging)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    std::lock_guard<std::mutex> lock(b->mu);
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) return set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");
     if (staging != FFT3D_STAGING_IN_PLACE && staging != FFT3D_STAGING_FUSED_XY)
@@ -431,6 +437,7 @@ fft3d_status fft3d_batch_set_staging(fft3d_batch_t b, int64_t nx, int64_t ny, in
 fft3d_status fft3d_batch_set_streams(fft3d_batch_t b, int nstreams)
 {
     if (!b) return set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
+    std::lock_guard<std::mutex> lock(b->mu);
     if (nstreams < 1 || nstreams > 16) return set_error(FFT3D_ERR_INVALID_ARG, "nstreams must be 1..16");
     drop_cache(b);  // the chains are placed per stream count
     b->nstreams = nstreams;
@@ -443,6 +450,7 @@ int fft3d_batch_get_staging(fft3d_batch_t b, int64_t nx, int64_t ny, int64_t nz)
         set_error(FFT3D_ERR_INVALID_ARG, "null batch plan");
         return -1;
     }
+    std::lock_guard<std::mutex> lock(b->mu);
     auto it = b->plans.find(Shape(nx, ny, nz));
     if (it == b->plans.end()) {
         set_error(FFT3D_ERR_INVALID_ARG, "no transform of that shape in the batch");

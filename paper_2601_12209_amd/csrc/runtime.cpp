@@ -106,6 +106,10 @@ bool can_group(const KernelLaunch* v, size_t n)
 {
     if (n < 2) return false;
     const StageArgs a0 = without_tile_fields(v[0].args);
+    uint64_t gmax = 1;
+    for (size_t i = 0; i < n; ++i) gmax = std::max<uint64_t>(gmax, (uint64_t)v[i].grid.x * v[i].grid.y);
+    // the grouped grid (gmax * n workgroups along x) must fit the dispatch's 32-bit work-item count
+    if (gmax * n > 0x7fffffffu || gmax * n * v[0].block.x > 0xffffffffu) return false;
     for (size_t i = 0; i < n; ++i) {
         if (v[i].func != v[0].func || v[i].lds != v[0].lds || v[i].block.x != v[0].block.x ||
             v[i].block.y != v[0].block.y || v[i].block.z != v[0].block.z || v[i].grid.z != 1 ||
