@@ -484,10 +484,15 @@ StageArgs make_args(const fft3d_plan_s* p, const Stage& st, const Box& b, void* 
     // complex128 strided tiles in XCD-grouped order: 2.5-5 % faster per y/z
     // stage at 512^3 on MI355X (C2C and R2C); complex64 stages ran 3-5 % slower
     // with it (C2C, and the R2C z stages at 512^3), so they keep the plain
-    // order, except the strided stages of half spectra of 2 GiB and more
-    // (1024^3 R2C: z stages 3-5 % faster, y stages unchanged)
-    const bool big_half = d.r2c && (size_t)d.nxc() * d.ny * d.nz * elem_bytes(d.dtype) >= kR2CSwapMaxBytes;
-    if (a.strided && (d.dtype == DT_F64 || big_half)) a.xcd = 1;
+    // order, except in R2C plans of half spectra from 512 MiB: the y stages
+    // (512^3: 2-6 % faster) and, from 2 GiB, the z stages (1024^3: 3-5 %
+    // faster); and tiles narrower than a cache line, whose neighbours share
+    // every line they read and write (8-line complex64 tiles of the lengths
+    // with 45 or 56 threads per line: 720^3 y/z stages 1.66 -> 1.51 ms)
+    const size_t half = d.r2c ? (size_t)d.nxc() * d.ny * d.nz * elem_bytes(d.dtype) : 0;
+    const bool r2c_xcd = half >= kR2CSwapMaxBytes || (half >= kSwapStagingMinBytes && st.axis == 1);
+    const bool narrow = a.lw * (int64_t)elem_bytes(d.dtype) < 128;
+    if (a.strided && (d.dtype == DT_F64 || r2c_xcd || narrow)) a.xcd = 1;
     a.nt = c2c_cache_policy(d, st, a, per_line);
     if (reverse) {
         a.order = 1;
