@@ -487,6 +487,24 @@ def test_cache_policy_in_place_and_cache_resident(fft3d):
             assert all(L["nt"] == 0 for _, L in _by_stage(fft3d, (256, 256, 256), dtype, staging=staging))
 
 
+def test_xcd_grouped_order_policy(fft3d):
+    """XCD-grouped strided tiles: complex128 always; complex64 C2C only for tiles
+    narrower than a cache line (8-line tiles of 720 and 840); R2C y stages from
+    a 512 MiB half spectrum, and every R2C strided stage from 2 GiB."""
+    def xcd(shape, dtype, r2c=False, op=0):
+        return [(st["axis"], L["lw"], L["xcd"]) for st, L in _by_stage(fft3d, shape, dtype, r2c=r2c, op=op)
+                if L["strided"]]
+    for op in (0, 1):
+        assert all(x == 1 for _, _, x in xcd((512, 512, 512), "c128", op=op))
+        assert all(x == 0 for _, _, x in xcd((512, 512, 512), "c64", op=op))
+        for n in (720, 840):
+            got = xcd((n, n, n), "c64", op=op)
+            assert got and all(lw == 8 and x == 1 for _, lw, x in got), (n, got)
+        assert all(x == (axis == 1) for axis, _, x in xcd((512, 512, 512), "f32", r2c=True, op=op))
+        assert all(x == 1 for _, _, x in xcd((1024, 1024, 1024), "f32", r2c=True, op=op))
+        assert all(x == 0 for _, _, x in xcd((256, 256, 256), "f32", r2c=True, op=op))
+
+
 def test_r2c_launches(fft3d):
     """512^3 R2C: padded LDS lines in the real x kernels; output rows of 257 values
     get shifted (cache-line aligned) tiles; non-temporal loads only where whole
