@@ -45,6 +45,9 @@ CASES = [
     ((2, 5, 840), (1, 1)),
     ((6, 720, 4), (2, 2)),
     ((105, 70, 112), (1, 1)),
+    # 8-line strided tiles of 840 and 720 in the XCD-grouped order
+    ((120, 840, 16), (1, 1)),
+    ((720, 8, 16), (1, 1)),
     # the generic odd-prime radix: 11 and 13 times powers of two
     ((13, 22, 11), (2, 2)),
     ((26, 176, 52), (1, 2)),
