@@ -137,7 +137,14 @@ __global__ __launch_bounds__(1024) void k_c2r_x(StageArgs a)
     };
     const T scale = (T)a.scale;
     auto store = [&](int e, cpx<T> v) {
-        if (ok) out[e] = conj(v) * scale;
+        if (ok) {
+            if constexpr (sizeof(T) == 8) {  // FP64: a.nt asks for non-temporal stores
+                if (a.nt) store_nt(&out[e], conj(v) * scale);
+                else out[e] = conj(v) * scale;
+            } else {
+                out[e] = conj(v) * scale;
+            }
+        }
     };
     fft_line<T, H, TPL, false, true, false>(L, Ls, tj, twl, load, store);
 }
