@@ -64,19 +64,23 @@ DEFAULT_STAGING = "swap_yz"
 
 
 def _timed_steps(step, steps, warmup, torch):
+    """Mean ms per step over the timed region, its wall time, and the median
+    of the per-step times (an event recorded on the stream after each step)."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
+    events[0].record()
+    for i in range(steps):
         step()
-    end.record()
+        events[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(end) / steps, wall
+    per_step = sorted(events[i].elapsed_time(events[i + 1]) for i in range(steps))
+    mid = steps // 2
+    median = per_step[mid] if steps % 2 else 0.5 * (per_step[mid - 1] + per_step[mid])
+    return events[0].elapsed_time(events[-1]) / steps, wall, median
 
 
 def _stage_profile(plan, x, X, Y, reps, torch):
@@ -107,13 +111,13 @@ def _measure(dtype, shape, grid, streams, steps, warmup, a_host, torch, fft3d, s
 
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        ms, wall = _timed_steps(step, steps, warmup, torch)
+        ms, wall, ms_median = _timed_steps(step, steps, warmup, torch)
     fwd_st, inv_st = _stage_profile(plan, x, X, Y, max(3, min(steps, 10)), torch)
     plan.forward(x, out=X)
     plan.inverse(X, out=Y)
     torch.cuda.synchronize()
     plan.close()
-    return dict(ms=ms, wall=wall, fwd_stages=fwd_st, inv_stages=inv_st, X=X, Y=Y)
+    return dict(ms=ms, ms_median=ms_median, wall=wall, fwd_stages=fwd_st, inv_stages=inv_st, X=X, Y=Y)
 
 
 def _time(fn, reps, torch):
@@ -550,6 +554,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r32["ms"], 4),
+        "ms_per_step_median": round(r32["ms_median"], 4),
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
@@ -566,6 +571,7 @@ def main():
     if r64 is not None:
         gflops64 = 2 * flop_per_transform / (r64["ms"] * 1e-3) / 1e9
         result["fp64"] = {"value": round(gflops64, 1), "unit": "GFLOP/s", "ms_per_step": round(r64["ms"], 4),
+                          "ms_per_step_median": round(r64["ms_median"], 4),
                           "hbm_frac_whole_step": round(6 * 2.0 * 16 * N / (r64["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "stages_c128": stage_report(r64, 16),
                           "fp32_over_fp64_speedup": round(r64["ms"] / r32["ms"], 3)}
