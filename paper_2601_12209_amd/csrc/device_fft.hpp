@@ -538,8 +538,15 @@ FD bool tile_coord(Args& a, TileCoord& c)
     }
     // 32-bit index arithmetic: a grid's workgroup counts fit in 32 bits (and
     // a 64-bit division here costs the kernel a scratch stack frame)
-    const uint32_t w = blockIdx.x, gmax = (uint32_t)a.gmax;
-    const uint32_t t = w / gmax, local = w - t * gmax;
+    const uint32_t w = blockIdx.x, gmax = (uint32_t)a.gmax, nt = (uint32_t)a.ntiles;
+    uint32_t t, local;
+    if (nt > 0) {  // tiles interleaved: consecutive workgroups in different tiles
+        local = w / nt;
+        t = w - local * nt;
+    } else {
+        t = w / gmax;
+        local = w - t * gmax;
+    }
     const auto& e = a.tiles[t];
     const uint32_t gx = (uint32_t)e.gx;
     if (local >= gx * (uint32_t)e.gy) return false;

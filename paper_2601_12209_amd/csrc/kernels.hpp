@@ -55,9 +55,11 @@ hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const St
 // qualify; make_group fills the table entries (in/out left null when
 // own_buffers is false: the tiles of one transform share the launch's
 // buffers) and the common launch (grid = tiles x gmax workgroups, args with
-// gmax set; the caller sets args.tiles to the device copy of the entries).
+// gmax set, and ntiles set when interleave asks for the tiles' workgroups to
+// alternate; the caller sets args.tiles to the device copy of the entries).
 bool can_group(const KernelLaunch* v, size_t n);
-void make_group(const KernelLaunch* v, size_t n, bool own_buffers, TileEntry* entries, KernelLaunch* common);
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, bool interleave, TileEntry* entries,
+                KernelLaunch* common);
 
 // Size of the library's static device scratch (one per GPU, scratch.hip),
 // the workspace of the calls that allocate nothing: 256 MiB holds the R2C

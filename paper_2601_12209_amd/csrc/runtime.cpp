@@ -121,7 +121,8 @@ bool can_group(const KernelLaunch* v, size_t n)
     return true;
 }
 
-void make_group(const KernelLaunch* v, size_t n, bool own_buffers, TileEntry* entries, KernelLaunch* common)
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, bool interleave, TileEntry* entries,
+                KernelLaunch* common)
 {
     int64_t gmax = 1;
     for (size_t i = 0; i < n; ++i) {
@@ -141,6 +142,7 @@ void make_group(const KernelLaunch* v, size_t n, bool own_buffers, TileEntry* en
     }
     *common = v[0];
     common->args.gmax = gmax;
+    common->args.ntiles = interleave ? (int64_t)n : 0;
     common->grid = dim3((unsigned)(gmax * (int64_t)n), 1, 1);
 }
 
@@ -711,7 +713,13 @@ fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
         const std::vector<KernelLaunch>& v = rec[st];
         if (!can_group(v.data(), v.size())) continue;
         G.stages[st].grouped = true;
-        make_group(v.data(), v.size(), false, host.data() + pos, &G.stages[st].launch);
+        // the tiles of a C2C plan's stage interleaved workgroup by workgroup, so the
+        // workgroups in flight cover every tile's slice of the rows, as on one
+        // tile (MI355X: 256^3 complex128 on 4x4 tiles 0.586 -> 0.559 ms, 512^3
+        // complex64 on 4x4 2.67 -> 2.54 ms, 256^3 complex64 unchanged); R2C
+        // plans keep the tiles one after another (1024^3 on 8x8 tiles ran 6 %
+        // slower interleaved)
+        make_group(v.data(), v.size(), false, !p->d.r2c, host.data() + pos, &G.stages[st].launch);
         G.stages[st].launch.args.tiles = reinterpret_cast<const TileEntry*>(pos);  // offset until uploaded
         pos += v.size();
     }

@@ -641,6 +641,36 @@ void check_grouped(const void* f, dim3 grid, const StageArgs& a)
     }
     const int64_t count = grid.x / a.gmax;
     if (!in_alloc(a.tiles, (size_t)count * sizeof(TileEntry), "tile table")) return;
+    if (a.ntiles != 0 && a.ntiles != count)
+        violation("interleaved grouped launch with ntiles %lld for %lld tiles", (long long)a.ntiles, (long long)count);
+    {
+        // the device's workgroup -> (tile, local workgroup) map, tile-major or
+        // interleaved, hits every workgroup of every tile exactly once
+        std::vector<int64_t> hits((size_t)grid.x, 0);
+        for (uint32_t w = 0; w < grid.x; ++w) {
+            uint32_t t, local;
+            if (a.ntiles > 0) {
+                local = w / (uint32_t)a.ntiles;
+                t = w - local * (uint32_t)a.ntiles;
+            } else {
+                t = w / (uint32_t)a.gmax;
+                local = w - t * (uint32_t)a.gmax;
+            }
+            if ((int64_t)t >= count || (int64_t)local >= a.gmax) {
+                violation("workgroup %u maps outside the grouped launch", w);
+                break;
+            }
+            if (local < a.tiles[t].gx * a.tiles[t].gy) ++hits[(size_t)t * a.gmax + local];
+        }
+        for (int64_t t = 0; t < count; ++t)
+            for (int64_t l = 0; l < a.tiles[t].gx * a.tiles[t].gy && l < a.gmax; ++l)
+                if (hits[(size_t)(t * a.gmax + l)] != 1) {
+                    violation("tile %lld workgroup %lld mapped %lld times", (long long)t, (long long)l,
+                              (long long)hits[(size_t)(t * a.gmax + l)]);
+                    t = count;
+                    break;
+                }
+    }
     g_checking = true;
     for (int64_t i = 0; i < count; ++i) {
         const TileEntry& e = a.tiles[i];
@@ -648,6 +678,7 @@ void check_grouped(const void* f, dim3 grid, const StageArgs& a)
         StageArgs b = a;
         b.tiles = nullptr;
         b.gmax = 0;
+        b.ntiles = 0;
         if (e.in) b.in = e.in;
         if (e.out) b.out = e.out;
         b.off = e.off;
