@@ -178,7 +178,7 @@ fft3d_status build_issue(fft3d_batch_t b, int op, const void* const* in, void* c
                 continue;
             }
             KernelLaunch kl;
-            make_group(groups[k][g].data(), groups[k][g].size(), true, false, host.data() + pos, &kl);
+            make_group(groups[k][g].data(), groups[k][g].size(), true, 0, host.data() + pos, &kl);
             pos += groups[k][g].size();
             launches[k].push_back(kl);
         }

@@ -540,9 +540,10 @@ FD bool tile_coord(Args& a, TileCoord& c)
     // a 64-bit division here costs the kernel a scratch stack frame)
     const uint32_t w = blockIdx.x, gmax = (uint32_t)a.gmax, nt = (uint32_t)a.ntiles;
     uint32_t t, local;
-    if (nt > 0) {  // tiles interleaved: consecutive workgroups in different tiles
-        local = w / nt;
-        t = w - local * nt;
+    if (nt > 0) {  // runs of nt tiles, each run's workgroups interleaved
+        const uint32_t span = nt * gmax, run = w / span, r = w - run * span;
+        local = r / nt;
+        t = run * nt + (r - local * nt);
     } else {
         t = w / gmax;
         local = w - t * gmax;

@@ -55,10 +55,11 @@ hipError_t launch_stage_kernel(const void* func, dim3 grid, dim3 block, const St
 // qualify; make_group fills the table entries (in/out left null when
 // own_buffers is false: the tiles of one transform share the launch's
 // buffers) and the common launch (grid = tiles x gmax workgroups, args with
-// gmax set, and ntiles set when interleave asks for the tiles' workgroups to
-// alternate; the caller sets args.tiles to the device copy of the entries).
+// gmax set, and ntiles > 0 interleaving the workgroups of each run of ntiles
+// consecutive tiles; the caller sets args.tiles to the device copy of the
+// entries).
 bool can_group(const KernelLaunch* v, size_t n);
-void make_group(const KernelLaunch* v, size_t n, bool own_buffers, bool interleave, TileEntry* entries,
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, int64_t ntiles, TileEntry* entries,
                 KernelLaunch* common);
 
 // Size of the library's static device scratch (one per GPU, scratch.hip),

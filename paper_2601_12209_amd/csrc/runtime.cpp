@@ -121,7 +121,7 @@ bool can_group(const KernelLaunch* v, size_t n)
     return true;
 }
 
-void make_group(const KernelLaunch* v, size_t n, bool own_buffers, bool interleave, TileEntry* entries,
+void make_group(const KernelLaunch* v, size_t n, bool own_buffers, int64_t ntiles, TileEntry* entries,
                 KernelLaunch* common)
 {
     int64_t gmax = 1;
@@ -142,7 +142,7 @@ void make_group(const KernelLaunch* v, size_t n, bool own_buffers, bool interlea
     }
     *common = v[0];
     common->args.gmax = gmax;
-    common->args.ntiles = interleave ? (int64_t)n : 0;
+    common->args.ntiles = ntiles > 0 && n % (size_t)ntiles == 0 ? ntiles : 0;
     common->grid = dim3((unsigned)(gmax * (int64_t)n), 1, 1);
 }
 
@@ -665,9 +665,10 @@ fft3d_status issue_forked(fft3d_plan_s* p, int op, const Pipeline& pl, void* con
 // Record the launch of every tile of stage `stage` (in task order) instead
 // of issuing it; tiles with nothing to launch are left out.
 hipError_t record_tiles(fft3d_plan_s* p, const Pipeline& pl, int stage, void* const bufs[3],
-                        std::vector<KernelLaunch>* launches)
+                        std::vector<KernelLaunch>* launches, std::vector<Box>* boxes = nullptr)
 {
     launches->clear();
+    if (boxes) boxes->clear();
     for (const Task& t : pl.tasks) {
         if (t.stage != stage) continue;
         const Stage& st = pl.stages[t.stage];
@@ -677,9 +678,42 @@ hipError_t record_tiles(fft3d_plan_s* p, const Pipeline& pl, int stage, void* co
         const hipError_t e = launch_task(p, st, make_args(p, st, t.box, bufs), nullptr);
         set_launch_recorder(nullptr, nullptr);
         if (e != hipSuccess) return e;
-        if (recorded) launches->push_back(kl);
+        if (recorded) {
+            launches->push_back(kl);
+            if (boxes) boxes->push_back(t.box);
+        }
     }
     return hipSuccess;
+}
+
+// Puts the tiles of a stage that share their rows (the same range of the
+// second index of their line grids) next to each other, in x order within a
+// row of tiles, and returns the tiles per row of tiles; 0 (order kept) when
+// the rows of tiles do not all hold the same number.
+int64_t order_tile_rows(std::vector<KernelLaunch>& v, std::vector<Box>& b, int axis)
+{
+    if (v.size() != b.size() || v.empty()) return 0;
+    const int s1 = axis == 0 ? 1 : 0, s2 = axis == 2 ? 1 : 2;
+    std::vector<size_t> idx(v.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+        return b[x].lo[s2] != b[y].lo[s2] ? b[x].lo[s2] < b[y].lo[s2] : b[x].lo[s1] < b[y].lo[s1];
+    });
+    std::vector<KernelLaunch> v2;
+    std::vector<Box> b2;
+    for (size_t i : idx) {
+        v2.push_back(v[i]);
+        b2.push_back(b[i]);
+    }
+    int64_t g = 0;
+    while (g < (int64_t)b2.size() && b2[g].lo[s2] == b2[0].lo[s2]) ++g;
+    if ((int64_t)b2.size() % g != 0) return 0;
+    for (size_t k = 0; k < b2.size(); ++k)
+        if (b2[k].lo[s2] != b2[k - k % g].lo[s2] || (k % g == 0 && k > 0 && b2[k].lo[s2] == b2[k - g].lo[s2]))
+            return 0;
+    v.swap(v2);
+    b.swap(b2);
+    return g;
 }
 
 // Free the grouped launches' tables after the last call has finished.
@@ -700,9 +734,10 @@ fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
     G = fft3d_plan_s::OpGroups();
     void* const none[3] = {nullptr, nullptr, nullptr};
     std::vector<std::vector<KernelLaunch>> rec(pl.stages.size());
+    std::vector<std::vector<Box>> boxes(pl.stages.size());
     size_t total = 0;
     for (size_t st = 0; st < pl.stages.size(); ++st) {
-        hipError_t e = record_tiles(p, pl, (int)st, none, &rec[st]);
+        hipError_t e = record_tiles(p, pl, (int)st, none, &rec[st], &boxes[st]);
         if (e != hipSuccess) return hip_fail(e, "recording tile launches");
         if (can_group(rec[st].data(), rec[st].size())) total += rec[st].size();
     }
@@ -710,16 +745,23 @@ fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
     G.stages.resize(pl.stages.size());
     size_t pos = 0;
     for (size_t st = 0; st < pl.stages.size(); ++st) {
-        const std::vector<KernelLaunch>& v = rec[st];
+        std::vector<KernelLaunch>& v = rec[st];
         if (!can_group(v.data(), v.size())) continue;
         G.stages[st].grouped = true;
-        // the tiles of a C2C plan's stage interleaved workgroup by workgroup, so the
-        // workgroups in flight cover every tile's slice of the rows, as on one
-        // tile (MI355X: 256^3 complex128 on 4x4 tiles 0.586 -> 0.559 ms, 512^3
-        // complex64 on 4x4 2.67 -> 2.54 ms, 256^3 complex64 unchanged); R2C
-        // plans keep the tiles one after another (1024^3 on 8x8 tiles ran 6 %
-        // slower interleaved)
-        make_group(v.data(), v.size(), false, !p->d.r2c, host.data() + pos, &G.stages[st].launch);
+        // C2C plans: the tiles of each row of tiles (the tiles sharing their
+        // rows) interleaved workgroup by workgroup, so the workgroups in flight
+        // cover every tile's slice of the same rows, as on one tile (MI355X,
+        // fwd+inv: 256^3 complex128 on 4x4 tiles 0.586 -> 0.552 ms, 512^3
+        // complex64 on 4x4 2.67 -> 2.44 ms, 256^3 complex64 unchanged; every
+        // tile of the stage interleaved gave 0.559 and 2.54 ms).  R2C plans
+        // keep the tiles one after another: 1024^3 on 8x8 tiles ran 6 % slower
+        // with either interleave.
+        int64_t ntiles = 0;
+        if (!p->d.r2c) {
+            const int64_t g = order_tile_rows(v, boxes[st], pl.stages[st].axis);
+            ntiles = g > 0 ? g : (int64_t)v.size();
+        }
+        make_group(v.data(), v.size(), false, ntiles, host.data() + pos, &G.stages[st].launch);
         G.stages[st].launch.args.tiles = reinterpret_cast<const TileEntry*>(pos);  // offset until uploaded
         pos += v.size();
     }

@@ -89,8 +89,9 @@ struct StageArgs {
     int64_t pnx, pny, pnz;
     int64_t kx0, ky0;
     // grouped launch: tiles[w / gmax] is the tile of workgroup w (nullptr: a
-    // launch of this one tile on its own grid); with ntiles > 0 the tiles are
-    // interleaved instead: workgroup w belongs to tiles[w % ntiles]
+    // launch of this one tile on its own grid); with ntiles > 0 the tiles go in
+    // runs of ntiles whose workgroups are interleaved: workgroup w belongs to
+    // tile (w / (ntiles gmax)) ntiles + w mod ntiles
     const TileEntry* tiles;
     int64_t gmax;
     int64_t ntiles;

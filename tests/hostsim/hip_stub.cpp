@@ -641,8 +641,8 @@ void check_grouped(const void* f, dim3 grid, const StageArgs& a)
     }
     const int64_t count = grid.x / a.gmax;
     if (!in_alloc(a.tiles, (size_t)count * sizeof(TileEntry), "tile table")) return;
-    if (a.ntiles != 0 && a.ntiles != count)
-        violation("interleaved grouped launch with ntiles %lld for %lld tiles", (long long)a.ntiles, (long long)count);
+    if (a.ntiles < 0 || (a.ntiles > 0 && count % a.ntiles != 0))
+        violation("interleaved grouped launch with runs of %lld for %lld tiles", (long long)a.ntiles, (long long)count);
     {
         // the device's workgroup -> (tile, local workgroup) map, tile-major or
         // interleaved, hits every workgroup of every tile exactly once
@@ -650,8 +650,10 @@ void check_grouped(const void* f, dim3 grid, const StageArgs& a)
         for (uint32_t w = 0; w < grid.x; ++w) {
             uint32_t t, local;
             if (a.ntiles > 0) {
-                local = w / (uint32_t)a.ntiles;
-                t = w - local * (uint32_t)a.ntiles;
+                const uint32_t nt = (uint32_t)a.ntiles, span = nt * (uint32_t)a.gmax, run = w / span,
+                               r = w - run * span;
+                local = r / nt;
+                t = run * nt + (r - local * nt);
             } else {
                 t = w / (uint32_t)a.gmax;
                 local = w - t * (uint32_t)a.gmax;
