@@ -716,6 +716,57 @@ int64_t order_tile_rows(std::vector<KernelLaunch>& v, std::vector<Box>& b, int a
     return g;
 }
 
+// A grouped strided stage whose output rows do not start on cache lines (the
+// tiles shift their lines so that every stored segment is a whole line) runs
+// each row of tiles as one tile spanning the row: between two tiles of a row
+// the shifted tiles would store partial lines from both sides of the border.
+// Merges the recorded tiles of stage `stage` that way; false (unchanged)
+// where the stage has no such tiles or its rows of tiles are not contiguous.
+bool merge_row_tiles(fft3d_plan_s* p, const Pipeline& pl, int stage, std::vector<KernelLaunch>& v,
+                     std::vector<Box>& b)
+{
+    if (v.size() < 2 || v.size() != b.size()) return false;
+    for (const KernelLaunch& k : v)
+        if (!k.args.strided || k.args.align <= 1) return false;
+    const Stage& st = pl.stages[stage];
+    const int s1 = st.axis == 0 ? 1 : 0, s2 = st.axis == 2 ? 1 : 2;
+    if (s1 != 0) return false;
+    std::vector<Box> rows;
+    for (const Box& x : b) {
+        bool found = false;
+        for (Box& r : rows)
+            if (r.lo[s2] == x.lo[s2] && r.hi[s2] == x.hi[s2] && r.lo[st.axis] == x.lo[st.axis] &&
+                r.hi[st.axis] == x.hi[st.axis]) {
+                r.lo[s1] = std::min(r.lo[s1], x.lo[s1]);
+                r.hi[s1] = std::max(r.hi[s1], x.hi[s1]);
+                found = true;
+            }
+        if (!found) rows.push_back(x);
+    }
+    // every row of tiles must cover one contiguous x range (its tiles' total)
+    for (const Box& r : rows) {
+        int64_t covered = 0;
+        for (const Box& x : b)
+            if (x.lo[s2] == r.lo[s2] && x.hi[s2] == r.hi[s2]) covered += x.hi[s1] - x.lo[s1];
+        if (covered != r.hi[s1] - r.lo[s1]) return false;
+    }
+    if (rows.size() == b.size()) return false;
+    void* const none[3] = {nullptr, nullptr, nullptr};
+    std::vector<KernelLaunch> v2;
+    for (const Box& r : rows) {
+        KernelLaunch kl;
+        bool recorded = false;
+        set_launch_recorder(&kl, &recorded);
+        const hipError_t e = launch_task(p, st, make_args(p, st, r, none), nullptr);
+        set_launch_recorder(nullptr, nullptr);
+        if (e != hipSuccess || !recorded) return false;
+        v2.push_back(kl);
+    }
+    v.swap(v2);
+    b.swap(rows);
+    return true;
+}
+
 // Free the grouped launches' tables after the last call has finished.
 void drop_groups(fft3d_plan_s* p)
 {
@@ -739,6 +790,7 @@ fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
     for (size_t st = 0; st < pl.stages.size(); ++st) {
         hipError_t e = record_tiles(p, pl, (int)st, none, &rec[st], &boxes[st]);
         if (e != hipSuccess) return hip_fail(e, "recording tile launches");
+        if (can_group(rec[st].data(), rec[st].size())) merge_row_tiles(p, pl, (int)st, rec[st], boxes[st]);
         if (can_group(rec[st].data(), rec[st].size())) total += rec[st].size();
     }
     std::vector<TileEntry> host(total);
