@@ -800,16 +800,18 @@ fft3d_status build_groups(fft3d_plan_s* p, int op, const Pipeline& pl)
         std::vector<KernelLaunch>& v = rec[st];
         if (!can_group(v.data(), v.size())) continue;
         G.stages[st].grouped = true;
-        // C2C plans: the tiles of each row of tiles (the tiles sharing their
-        // rows) interleaved workgroup by workgroup, so the workgroups in flight
-        // cover every tile's slice of the same rows, as on one tile (MI355X,
-        // fwd+inv: 256^3 complex128 on 4x4 tiles 0.586 -> 0.552 ms, 512^3
-        // complex64 on 4x4 2.67 -> 2.44 ms, 256^3 complex64 unchanged; every
-        // tile of the stage interleaved gave 0.559 and 2.54 ms).  R2C plans
-        // keep the tiles one after another: 1024^3 on 8x8 tiles ran 6 % slower
-        // with either interleave.
+        // C2C plans, and the contiguous x stages of R2C plans: the tiles of each
+        // row of tiles (the tiles sharing their rows) interleaved workgroup by
+        // workgroup, so the workgroups in flight cover every tile's slice of the
+        // same rows, as on one tile (MI355X, fwd+inv: 256^3 complex128 on 4x4
+        // tiles 0.586 -> 0.552 ms, 512^3 complex64 on 4x4 2.67 -> 2.44 ms,
+        // 256^3 complex64 unchanged, every tile of the stage interleaved gave
+        // 0.559 and 2.54 ms; 512^3 R2C on 4x4 1.41 -> 1.37 ms, 1024^3 on 8x8
+        // 12.6 -> 12.45 ms).  The strided stages of R2C plans keep the tiles
+        // one after another: 1024^3 on 8x8 tiles ran 6 % slower with either
+        // interleave.
         int64_t ntiles = 0;
-        if (!p->d.r2c) {
+        if (!p->d.r2c || !v[0].args.strided) {
             const int64_t g = order_tile_rows(v, boxes[st], pl.stages[st].axis);
             ntiles = g > 0 ? g : (int64_t)v.size();
         }
